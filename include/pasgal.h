@@ -1,0 +1,227 @@
+/*
+ * pasgal.h -- C ABI of libpasgal.so: frontier-based graph traversal with
+ * vertical granularity control (VGC) on one AMD Instinct MI355X (gfx950).
+ *
+ * Operations (PASGAL, SPAA'24 brief announcement):
+ *   - BFS: hop distance of every vertex from one source (Parallel BFS,
+ *     Other Algorithms section; frontier framework of Algorithm 1). VGC lets
+ *     each frontier vertex run a local search that may visit a vertex more
+ *     than once; a vertex is kept for later rounds whenever its hop distance
+ *     was lowered, so the result is still the exact hop distance.
+ *   - Reachability: for a set of sources, every vertex reachable from each
+ *     (reachability search, Parallel SCC section). Visit order is free, so
+ *     the local search of VGC (Vertical Granularity Control paragraph) may go
+ *     deep. Backward reachability is forward reachability on G^T.
+ *
+ * Graph: int32 CSR, G = (V, E), n = |V|, m arcs (Preliminaries). offsets[n+1]
+ * with offsets[0] = 0 and offsets[n] = m, targets[m] in [0, n). Self-loops and
+ * duplicate arcs are allowed and do not change any result. Rows need not be
+ * sorted. All graph and output arrays are DEVICE pointers owned by the caller
+ * (typically torch tensors); the library never frees them and keeps no
+ * pointer to them after a call returns (server-resident graphs are copied).
+ *
+ * Errors: every int-returning call returns PASGAL_OK (0) or a negative code.
+ * No C++ exception crosses this interface. On PASGAL_EINVAL nothing is
+ * written. After any other error the outputs are unspecified but every
+ * pointer stayed in bounds, and the library remains usable.
+ *
+ * Threads: calls on different streams may run concurrently from different
+ * host threads; each stream has its own workspace. A persistent traversal
+ * launch assumes it has the GPU's compute units to itself (its grid barrier
+ * needs every workgroup resident); two such launches must not overlap.
+ */
+#ifndef PASGAL_H
+#define PASGAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PASGAL_VERSION 1
+
+#define PASGAL_OK 0
+#define PASGAL_EINVAL (-1)    /* bad argument: null pointer, n <= 0, m < 0, src or a source out of range, k <= 0 */
+#define PASGAL_ENOMEM (-2)    /* device or host allocation failed */
+#define PASGAL_EHIP (-3)      /* a HIP runtime call failed; see pasgal_last_hip_error() */
+#define PASGAL_ECSR (-4)      /* malformed CSR (only detected with PASGAL_FLAG_VALIDATE) */
+#define PASGAL_ECAPACITY (-5) /* a fixed-size structure was too small (never for traversals) */
+#define PASGAL_EAGAIN (-6)    /* server: no room for the request right now (non-blocking submit) */
+#define PASGAL_ETIMEOUT (-7)  /* a device-side bounded wait expired (e.g. grid barrier); results invalid */
+#define PASGAL_ENOTFOUND (-8) /* server: unknown request or graph id */
+
+/* Graph in device memory. */
+typedef struct pasgal_csr {
+  int32_t n;
+  int32_t m;
+  const int32_t *offsets; /* device, n+1 */
+  const int32_t *targets; /* device, m */
+} pasgal_csr;
+
+/* Traversal engine. */
+#define PASGAL_MODE_VGC 0   /* persistent kernel, rounds of VGC local searches (default) */
+#define PASGAL_MODE_PLAIN 1 /* level-synchronous frontier rounds, one launch per round (Algorithm 1, VGC off) */
+
+#define PASGAL_FLAG_VALIDATE 1u /* check the CSR on the device first (O(n+m)) */
+#define PASGAL_FLAG_ASYNC 2u    /* do not synchronize the stream before returning (VGC mode only) */
+
+typedef struct pasgal_opts {
+  int32_t mode;              /* PASGAL_MODE_VGC or PASGAL_MODE_PLAIN */
+  int32_t tau;               /* VGC: vertices a local search expands per frontier vertex before it
+                                publishes what is left (the paper's tau); <= 0 selects 256. tau = 1
+                                makes every round one BFS level inside the persistent kernel. */
+  int32_t wg_size;           /* threads per workgroup: 64..1024, multiple of 64; <= 0 selects 1024 */
+  int32_t blocks_per_cu;     /* persistent workgroups per compute unit; <= 0 selects 1 */
+  int64_t frontier_capacity; /* entries per frontier buffer; <= 0 selects max(2n, 65536). Smaller values
+                                are legal: overflowing entries go to a per-vertex dirty bitmap and are
+                                rescanned next round, never dropped. */
+  uint32_t flags;            /* PASGAL_FLAG_* */
+  int32_t timeout_ms;        /* bound on any device-side wait; <= 0 selects 20000 */
+  void *stream;              /* hipStream_t to run on; NULL = the null stream */
+} pasgal_opts;
+
+/* Counters of one call (schedule dependent, never part of the result). */
+typedef struct pasgal_stats {
+  int64_t rounds;         /* frontier rounds (VGC) or BFS levels (plain) */
+  int64_t expansions;     /* frontier/local entries whose out-arcs were scanned */
+  int64_t arcs_scanned;   /* arcs relaxed */
+  int64_t relax_success;  /* relaxations that changed the state (lowered a distance / added bits) */
+  int64_t published;      /* entries written to a global frontier */
+  int64_t overflow;       /* entries that went to the dirty bitmap instead */
+  int64_t stale;          /* popped entries skipped because a better value was already known */
+  int64_t max_frontier;   /* largest global frontier */
+  double device_ms;       /* traversal time on the stream (events around the launches) */
+} pasgal_stats;
+
+void pasgal_opts_default(pasgal_opts *opts);
+const char *pasgal_strerror(int code);
+int pasgal_last_hip_error(void); /* hipError_t of the last EHIP in this thread */
+int pasgal_version(void);
+
+/* BFS from src. dist_out[v] = hop distance from src along out-arcs, or -1 if
+ * v is unreachable. dist_out: device, n int32, written entirely. Synchronous
+ * on the null stream. */
+int pasgal_bfs(const pasgal_csr *g, int32_t src, int32_t *dist_out);
+/* Same with options and optional counters (stats may be NULL). Runs on
+ * opts->stream; returns after the stream is synchronized unless
+ * PASGAL_FLAG_ASYNC is set (VGC mode only; stats->device_ms is then 0). */
+int pasgal_bfs_ex(const pasgal_csr *g, int32_t src, int32_t *dist_out, const pasgal_opts *opts,
+                  pasgal_stats *stats);
+
+/* Multi-source reachability. sources: HOST array of k vertex ids (repeats
+ * allowed), k >= 1. label_out: device, n * W uint64 with W = ceil(k/64);
+ * bit (i % 64) of label_out[v*W + i/64] is set iff sources[i] reaches v
+ * (v = sources[i] included). Written entirely. */
+int pasgal_reach(const pasgal_csr *g, const int32_t *sources, int32_t k, uint64_t *label_out);
+int pasgal_reach_ex(const pasgal_csr *g, const int32_t *sources, int32_t k, uint64_t *label_out,
+                    const pasgal_opts *opts, pasgal_stats *stats);
+
+/* G^T (needed for backward reachability): t_offsets device n+1, t_targets
+ * device m. Row v of G^T lists every u with an arc u->v, once per arc; the
+ * order inside a row is unspecified. Synchronous on opts->stream (opts may be
+ * NULL). */
+int pasgal_transpose(const pasgal_csr *g, int32_t *t_offsets, int32_t *t_targets, const pasgal_opts *opts);
+
+/* Device-side CSR check (monotone offsets, offsets[0]=0, offsets[n]=m,
+ * targets in range). Returns PASGAL_OK or PASGAL_ECSR. */
+int pasgal_validate(const pasgal_csr *g, const pasgal_opts *opts);
+
+/* ------------------------------------------------------------ batched form --
+ * Many BFS queries over many graphs in ONE persistent launch, captured once
+ * in a hipGraph and replayed. The graphs are laid out as one packed CSR over
+ * the disjoint union of their vertex sets (graph g owns global vertices
+ * [vbase[g], vbase[g+1]); targets hold global ids). Query j runs on graph
+ * q_graph[j] from local vertex q_source[j] and writes its n_g distances to
+ * dist_out[q_out[j] .. q_out[j] + n_g). Output regions may not overlap. */
+typedef struct pasgal_batch pasgal_batch;
+
+typedef struct pasgal_batch_desc {
+  pasgal_csr packed;       /* device CSR of the packed graphs */
+  int32_t ngraphs;
+  const int32_t *vbase;    /* HOST, ngraphs+1, vbase[0] = 0, vbase[ngraphs] = packed.n */
+  int32_t nqueries;
+  const int32_t *q_graph;  /* HOST, nqueries */
+  const int32_t *q_source; /* HOST, nqueries, local ids */
+  const int64_t *q_out;    /* HOST, nqueries, element offsets into dist_out */
+  int32_t *dist_out;       /* device */
+  int64_t dist_len;        /* elements in dist_out (bounds check) */
+} pasgal_batch_desc;
+
+#define PASGAL_BATCH_AUTOTUNE 1u /* choose tau, wg_size, blocks_per_cu, capacity by timed probes */
+
+/* Builds the batch (uploads query tables, sizes the workspace, optionally
+ * autotunes, captures the hipGraph). opts supplies the starting parameters and
+ * the stream; flags may include PASGAL_BATCH_AUTOTUNE. */
+int pasgal_batch_create(const pasgal_batch_desc *desc, const pasgal_opts *opts, uint32_t batch_flags,
+                        pasgal_batch **out);
+/* Replays the captured launch: every query's distances are rewritten. Returns
+ * after the stream is synchronized. stats may be NULL. */
+int pasgal_batch_run(pasgal_batch *b, pasgal_stats *stats);
+/* The parameters the batch runs with (after autotuning). */
+int pasgal_batch_config(const pasgal_batch *b, pasgal_opts *chosen);
+void pasgal_batch_destroy(pasgal_batch *b);
+
+/* ------------------------------------------------------------- served form --
+ * A request loop over graphs kept resident in device memory. Requests (BFS
+ * from one source, or reachability from up to 64 sources) are admitted while
+ * the per-request state fits the memory budget and a slot is free, and join
+ * the running traversal at the next round boundary (continuous batching): the
+ * device advances every admitted request in shared persistent launches of a
+ * bounded number of rounds, retiring finished ones and admitting new ones
+ * between launches. Results are copied into the caller's device buffer. */
+typedef struct pasgal_server pasgal_server;
+
+typedef struct pasgal_server_opts {
+  int64_t memory_budget;   /* bytes of request state (result slots + bitmaps); <= 0: 1/4 of free HBM */
+  int32_t max_slots;       /* concurrent requests; <= 0 selects 256 */
+  int32_t slice_rounds;    /* rounds per launch before re-admitting; <= 0 selects 16 */
+  int32_t tau;             /* <= 0 selects 256 */
+  int32_t wg_size;         /* <= 0 selects 1024 */
+  int32_t blocks_per_cu;   /* <= 0 selects 1 */
+  int64_t frontier_capacity; /* per kind; <= 0 selects 64M entries */
+  int32_t timeout_ms;
+} pasgal_server_opts;
+
+#define PASGAL_REQ_BFS 0
+#define PASGAL_REQ_REACH 1
+
+typedef struct pasgal_request {
+  int32_t graph;          /* id from pasgal_server_add_graph */
+  int32_t kind;           /* PASGAL_REQ_BFS or PASGAL_REQ_REACH */
+  int32_t nsources;       /* BFS: 1; REACH: 1..64 */
+  int32_t sources[64];    /* local vertex ids */
+  void *out;              /* device: int32[n] (BFS) or uint64[n] (REACH); may be NULL (result dropped) */
+  uint64_t tag;           /* caller's cookie, echoed in the completion */
+} pasgal_request;
+
+typedef struct pasgal_completion {
+  int64_t id;             /* from pasgal_server_submit */
+  uint64_t tag;
+  int32_t status;         /* PASGAL_OK or an error code */
+  int32_t graph;
+  double t_submit_ms;     /* host monotonic clock, ms */
+  double t_admit_ms;
+  double t_done_ms;
+  int64_t rounds;         /* rounds the request was resident for */
+} pasgal_completion;
+
+int pasgal_server_create(const pasgal_server_opts *opts, pasgal_server **out);
+/* Copies the graph into server-owned device memory; returns its id. */
+int pasgal_server_add_graph(pasgal_server *s, const pasgal_csr *g, int32_t *graph_id);
+/* Queues a request; id receives its number. Never blocks: PASGAL_EAGAIN when
+ * the submission queue is full. */
+int pasgal_server_submit(pasgal_server *s, const pasgal_request *req, int64_t *id);
+/* Takes up to max finished requests; *count receives how many. */
+int pasgal_server_poll(pasgal_server *s, pasgal_completion *out, int32_t max, int32_t *count);
+/* Blocks until every submitted request has completed (or timeout_ms passes). */
+int pasgal_server_drain(pasgal_server *s, int32_t timeout_ms);
+/* Current queue depth, admitted requests and bytes of state in use. */
+int pasgal_server_load(pasgal_server *s, int32_t *queued, int32_t *active, int64_t *bytes_in_use);
+void pasgal_server_destroy(pasgal_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PASGAL_H */

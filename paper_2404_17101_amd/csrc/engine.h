@@ -1,0 +1,86 @@
+// engine.h -- host-side helpers shared by engine.hip, batch.hip and server.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+
+#include "kern.h"
+#include "pasgal.h"
+
+namespace pg {
+
+struct DevInfo {
+  int device = 0;
+  int cus = 0;
+  size_t lds_per_cu = 0;
+  size_t lds_per_block = 0;
+  int wall_khz = 100000;
+  int coop = 0;
+};
+
+// grow-only device buffer
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+// grow-only pinned host buffer
+struct HBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Library-owned scratch of one stream: frontier buffers, dirty bitmap,
+// control block, query tables, plain-mode frontiers, pinned staging.
+struct Workspace {
+  std::mutex mu;
+  hipStream_t stream = nullptr;
+  DBuf ctl, fv[2], fq[2], fval[2], dirty, qi, qword, seeds, pf[2], stamp, tmp_state, tscratch, plain_src;
+  uint32_t cap = 0;
+  HBuf h_ctl, h_stage;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  ~Workspace();
+};
+
+struct Opts {
+  int mode = PASGAL_MODE_VGC;
+  uint32_t tau = 256;
+  int wg = 1024;
+  int bpc = 1;
+  int64_t cap = 0;
+  uint32_t flags = 0;
+  int timeout_ms = 20000;
+  hipStream_t stream = nullptr;
+};
+
+struct LaunchGeom {
+  int grid = 0, block = 0;
+  size_t lds = 0;
+  uint32_t ring = 0, stage = 0;
+};
+
+extern thread_local int g_last_hip;
+int hip_fail(hipError_t e);
+const DevInfo &dev_info();
+int grow(DBuf &b, size_t bytes);
+int grow_host(HBuf &b, size_t bytes);
+void free_buf(DBuf &b);
+void free_hbuf(HBuf &b);
+Workspace *workspace_for(hipStream_t s);
+Opts resolve_opts(const pasgal_opts *o);
+bool opts_valid(const pasgal_opts *o);
+bool csr_valid(const pasgal_csr *g);
+int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg);
+uint64_t default_cap(int64_t requested, uint64_t nvert);
+void fill_stats_from_ctl(const Ctl &c, pasgal_stats *st, bool add);
+int validate_csr_device(Workspace &w, const pasgal_csr *g, hipStream_t s);
+
+hipError_t launch_strided_u64(unsigned long long *dst, int stride, int word, const unsigned long long *src,
+                              uint64_t n, hipStream_t s);
+hipError_t launch_add_const(int32_t *dst, const int32_t *src, int64_t n, int32_t c, hipStream_t s);
+hipError_t launch_fill_segments_u32(uint32_t *base, const int64_t *seg_off, const int64_t *seg_len, int32_t nseg,
+                                    uint32_t val, hipStream_t s);
+hipError_t launch_fill_segments_u64(unsigned long long *base, const int64_t *seg_off, const int64_t *seg_len,
+                                    int32_t nseg, unsigned long long val, hipStream_t s);
+
+}  // namespace pg

@@ -1,0 +1,136 @@
+// kern.h -- types shared by the host engine and the gfx950 kernels.
+//
+// Device data layout (all in HBM):
+//   CSR        offsets int32[n+1], targets int32[m] (caller's, read-only)
+//   state      BFS: uint32 dist[v] (0xFFFFFFFF = unreached = -1 as int32)
+//              REACH: uint64 mask[v] (bit i = source i of the request)
+//              A launch serves several queries: query q's value of global
+//              vertex v lives at state[qi[q].sbase + v].
+//   dirty      uint32 bitmap words per query, qi[q].dbase + local/32; a bit is
+//              set for a vertex whose frontier entry did not fit.
+//   frontier   two buffers (current / next) of entries {v, q, val}, SoA:
+//              v uint32, q uint32, val uint64 (dist or mask), capacity cap.
+//   ctl        control block: barrier counter, abort flag, frontier tails,
+//              claim counters and overflow flags rotating over 3 rounds,
+//              exit record and 64-bit statistics.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pg {
+
+enum Kind : int { KIND_BFS = 0, KIND_REACH = 1 };
+
+struct QInfo {
+  int64_t sbase;  // state index of global vertex v is sbase + v
+  int64_t dbase;  // dirty word of local vertex l is dbase + l/32
+  int32_t vbase;  // first global vertex of the query's graph
+  int32_t nv;     // vertices of the query's graph
+};
+
+enum StatIdx {
+  ST_EXPAND = 0,
+  ST_ARCS,
+  ST_SUCCESS,
+  ST_PUBLISH,
+  ST_OVERFLOW,
+  ST_STALE,
+  ST_COUNT
+};
+
+struct Ctl {
+  uint32_t bar;       // grid-barrier arrivals within one launch
+  uint32_t abort;     // set when a bounded wait expired
+  uint32_t cnt[3];    // frontier tails: round r reads cnt[r%3], appends to cnt[(r+1)%3]
+  uint32_t claim[3];  // entries claimed from the current frontier
+  uint32_t dclaim[3]; // dirty words claimed
+  uint32_t ovf[3];    // ovf[(r+1)%3] != 0: round r+1 must rescan the dirty bitmaps
+  uint32_t rounds;    // rounds run by the launch (exit record)
+  uint32_t final_cnt; // entries left in the last next-frontier
+  uint32_t final_ovf; // dirty bits pending at exit
+  uint32_t final_buf; // frontier buffer holding the leftover entries
+  uint32_t max_frontier;
+  uint32_t bad_csr;   // validation result
+  uint32_t pad[10];
+  unsigned long long stats[8];
+};
+
+struct Frontier {
+  uint32_t *v[2];
+  uint32_t *q[2];
+  unsigned long long *val[2];
+  uint32_t cap;
+};
+
+struct VgcArgs {
+  const int32_t *off;
+  const int32_t *tgt;
+  void *state;
+  uint32_t *dirty;
+  const QInfo *qi;
+  const int64_t *qword;   // nq+1 prefix of dirty words per query (dirty scan)
+  int64_t dirty_words;    // qword[nq]
+  int32_t nq;
+  Frontier fr;
+  uint32_t start_buf;
+  uint32_t tau;
+  uint32_t max_rounds;
+  uint32_t ring_cap;      // LDS ring entries per wave (power of two)
+  uint32_t stage_cap;     // LDS staging entries per wave
+  long long timeout_ticks;
+  Ctl *ctl;
+};
+
+// Initial frontier entries for a launch (host-built, uploaded).
+struct SeedEnt {
+  uint32_t v;  // global vertex
+  uint32_t q;
+  unsigned long long val;
+};
+
+// LDS of a persistent launch: per wavefront a ring (local queue) of ring_cap
+// entries and a staging buffer of stage_cap entries ({v, val[, q]} each, SoA)
+// plus 64 words of scan scratch, 16-byte aligned.
+__host__ __device__ inline size_t vgc_lds_bytes(int kind, bool multi, int waves, uint32_t ring_cap,
+                                                uint32_t stage_cap) {
+  const size_t vsz = (kind == KIND_BFS) ? 4 : 8;
+  size_t per = (size_t)(ring_cap + stage_cap) * (vsz + 4 + (multi ? 4 : 0)) + 64 * 4;
+  per = (per + 15) & ~(size_t)15;
+  return per * (size_t)waves;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t val, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long val, hipStream_t s);
+// Zero the control block, set cnt[0] = start_cnt + nseed and ovf[0]; write the
+// seed entries into frontier buffer start_buf after start_cnt and apply them
+// to the state (BFS: store val; REACH: OR val).
+hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_t nseed, uint32_t start_cnt,
+                       uint32_t start_ovf, hipStream_t s);
+hipError_t launch_vgc(int kind, bool multi, const VgcArgs &a, int grid, int block, size_t lds, bool cooperative,
+                      hipStream_t s);
+const void *vgc_kernel_ptr(int kind, bool multi);
+
+// Plain level-synchronous rounds (one launch per BFS level).
+hipError_t launch_plain_bfs_level(const int32_t *off, const int32_t *tgt, uint32_t *dist, const uint32_t *cur,
+                                  uint32_t ncur, uint32_t *nxt, uint32_t *cnt, uint32_t level, Ctl *ctl,
+                                  hipStream_t s);
+hipError_t launch_plain_reach_level(const int32_t *off, const int32_t *tgt, unsigned long long *mask,
+                                    uint32_t *stamp, const uint32_t *cur, uint32_t ncur, uint32_t *nxt,
+                                    uint32_t *cnt, uint32_t level, Ctl *ctl, hipStream_t s);
+hipError_t launch_plain_seed(int kind, void *state, uint32_t *frontier, uint32_t *cnt_slots, uint32_t *stamp,
+                             const uint32_t *srcs, const unsigned long long *vals, uint32_t nsrc, hipStream_t s);
+
+// Transpose (counting sort by target).
+hipError_t launch_transpose(const int32_t *off, const int32_t *tgt, int32_t n, int32_t m, int32_t *t_off,
+                            int32_t *t_tgt, int32_t *scratch /* n+1 + block sums */, hipStream_t s);
+size_t transpose_scratch_elems(int32_t n);
+
+hipError_t launch_validate(const int32_t *off, const int32_t *tgt, int32_t n, int32_t m, Ctl *ctl, hipStream_t s);
+
+// Per-query frontier census (served form): counts[q] = entries of query q in
+// the frontier; any[q] |= dirty bits of q non-zero.
+hipError_t launch_census(const uint32_t *fq, uint32_t cnt, uint32_t cap, uint32_t *counts, const QInfo *qi,
+                         const int64_t *qword, const uint32_t *dirty, int32_t nq, uint32_t *dirty_any,
+                         hipStream_t s);
+
+}  // namespace pg

@@ -1,0 +1,1019 @@
+// kernels.hip -- gfx950 (CDNA4) kernels for frontier traversal with vertical
+// granularity control (VGC).
+//
+// Paper mapping (PASGAL, SPAA'24):
+//  * Algorithm 1 (frontier framework): rounds over a frontier F_i; every
+//    vertex of F_i visits its neighbours and puts a subset into F_{i+1}.
+//    plain_*_level kernels run one round per launch (VGC off).
+//  * Vertical granularity control (Parallel SCC section): each frontier
+//    vertex runs a local search that keeps going for about tau vertices over
+//    several hops before the leftovers go to the next frontier.
+//    vgc_kernel runs all rounds inside one persistent launch; one wavefront
+//    runs one local search over the frontier vertices it claimed, with its
+//    queue in LDS.
+//  * BFS with VGC (Other Algorithms section): a vertex is (re)queued whenever
+//    the search lowers its hop distance, so a vertex may be expanded more than
+//    once; atomicMin keeps every stored value the length of a real walk and
+//    the fixpoint is the exact hop distance.
+//  * Reachability (Parallel SCC section): order is free, so the local search
+//    is a LIFO stack (deep first); masks grow by atomicOr, one bit per source.
+//  * The hash-bag frontier is replaced by per-wavefront LDS append buffers:
+//    ballot + mbcnt give each lane its slot, one global atomicAdd reserves
+//    room for a whole buffer, and the copy out is coalesced.
+//
+// Memory model: every datum that one workgroup writes and another reads in
+// the same launch (state, frontier entries, counters, dirty bits) is accessed
+// with agent-scope relaxed atomics, which gfx950 executes coherently across
+// its XCDs without L2 writeback/invalidate. The grid barrier waits for each
+// wave's memory operations to complete (s_waitcnt 0) before arriving. CSR
+// arrays are read-only during a launch and use ordinary cached loads.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+
+#include "engine.h"
+#include "kern.h"
+
+namespace pg {
+
+#define AG __HIP_MEMORY_SCOPE_AGENT
+constexpr uint32_t INF32 = 0xFFFFFFFFu;
+
+template <class T>
+__device__ __forceinline__ T ld_ag(T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, AG);
+}
+template <class T>
+__device__ __forceinline__ void st_ag(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, AG);
+}
+template <class T>
+__device__ __forceinline__ T add_ag(T *p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, AG);
+}
+template <class T>
+__device__ __forceinline__ T or_ag(T *p, T v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, AG);
+}
+template <class T>
+__device__ __forceinline__ T min_ag(T *p, T v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, AG);
+}
+template <class T>
+__device__ __forceinline__ T max_ag(T *p, T v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, AG);
+}
+template <class T>
+__device__ __forceinline__ T xchg_ag(T *p, T v) {
+  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, AG);
+}
+__device__ __forceinline__ uint32_t cas_ag(uint32_t *p, uint32_t expect, uint32_t desired) {
+  __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED, AG);
+  return expect;  // old value
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint32_t mbcnt64(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, uint32_t ln) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d);
+    if (ln >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor(x, d));
+  return x;
+}
+__device__ __forceinline__ unsigned long long shfl64(unsigned long long x, int src) {
+  uint32_t lo = __shfl((uint32_t)x, src), hi = __shfl((uint32_t)(x >> 32), src);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
+// Grid barrier for a persistent launch whose workgroups are all resident.
+// Fence-free: callers keep cross-workgroup data in agent-scope atomics.
+// Returns true when the launch must stop (a wait expired somewhere).
+__device__ bool grid_barrier(Ctl *ctl, uint32_t &epoch, long long deadline) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  __shared__ uint32_t s_abort;
+  if (threadIdx.x == 0) {
+    epoch += 1;
+    const uint32_t target = epoch * gridDim.x;
+    add_ag(&ctl->bar, 1u);
+    uint32_t ab = 0;
+    while (ld_ag(&ctl->bar) < target) {
+      if (ld_ag(&ctl->abort)) { ab = 1; break; }
+      if (wall_clock64() > deadline) {
+        st_ag(&ctl->abort, 1u);
+        ab = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    if (ld_ag(&ctl->abort)) ab = 1;
+    s_abort = ab;
+  }
+  __syncthreads();
+  return s_abort != 0;
+}
+
+// ------------------------------------------------------------ VGC engine --
+
+template <int KIND>
+struct ValT;
+template <>
+struct ValT<KIND_BFS> { using T = uint32_t; };
+template <>
+struct ValT<KIND_REACH> { using T = unsigned long long; };
+
+template <int KIND, bool MULTI>
+struct Wave {
+  using Val = typename ValT<KIND>::T;
+  static constexpr bool FIFO = (KIND == KIND_BFS);  // BFS: local BFS order; reach: LIFO (deep first)
+
+  const VgcArgs &a;
+  Val *state;
+  // per-wave LDS
+  Val *rval, *sval;
+  uint32_t *rv, *sv, *rq, *sq, *scan;
+  uint32_t Q, S, ln;
+  // wave-uniform
+  uint32_t head, tail, scount;
+  uint32_t nslot, nbuf;
+  unsigned long long st[ST_COUNT];
+
+  __device__ Wave(const VgcArgs &args, uint8_t *lds_wave) : a(args) {
+    state = (Val *)a.state;
+    Q = a.ring_cap;
+    S = a.stage_cap;
+    ln = lane_id();
+    uint8_t *p = lds_wave;
+    rval = (Val *)p; p += sizeof(Val) * Q;
+    sval = (Val *)p; p += sizeof(Val) * S;
+    rv = (uint32_t *)p; p += 4 * Q;
+    sv = (uint32_t *)p; p += 4 * S;
+    if (MULTI) {
+      rq = (uint32_t *)p; p += 4 * Q;
+      sq = (uint32_t *)p; p += 4 * S;
+    } else {
+      rq = sq = nullptr;
+    }
+    scan = (uint32_t *)p;
+    head = tail = scount = 0;
+    nslot = nbuf = 0;
+#pragma unroll
+    for (int i = 0; i < ST_COUNT; i++) st[i] = 0;
+  }
+
+  __device__ __forceinline__ int64_t sbase_of(uint32_t q) const { return MULTI ? a.qi[q].sbase : 0; }
+
+  __device__ void mark_dirty(uint32_t v, uint32_t q) {
+    int64_t dbase = 0;
+    uint32_t local = v;
+    if (MULTI) {
+      const QInfo qi = a.qi[q];
+      dbase = qi.dbase;
+      local = v - (uint32_t)qi.vbase;
+    }
+    or_ag(&a.dirty[dbase + (local >> 5)], 1u << (local & 31));
+  }
+
+  // Write the staging buffer to the next global frontier: one reservation
+  // per buffer, coalesced agent-scope stores; entries past the capacity go
+  // to the dirty bitmap (never dropped).
+  __device__ void flush_stage() {
+    if (scount == 0) return;
+    wave_sync();
+    uint32_t base = 0;
+    if (ln == 0) base = add_ag(&a.ctl->cnt[nslot], scount);
+    base = __shfl(base, 0);
+    bool ovf = false;
+    for (uint32_t i = ln; i < scount; i += 64) {
+      const uint32_t v = sv[i];
+      const Val val = sval[i];
+      const uint32_t q = MULTI ? sq[i] : 0u;
+      const uint32_t idx = base + i;
+      if (idx >= base && idx < a.fr.cap) {
+        st_ag(&a.fr.v[nbuf][idx], v);
+        if (MULTI) st_ag(&a.fr.q[nbuf][idx], q);
+        st_ag(&a.fr.val[nbuf][idx], (unsigned long long)val);
+      } else {
+        mark_dirty(v, q);
+        ovf = true;
+      }
+    }
+    const unsigned long long ob = __ballot(ovf);
+    if (ob) {
+      if (ln == 0) st_ag(&a.ctl->ovf[nslot], 1u);
+    }
+    st[ST_OVERFLOW] += __popcll(ob);
+    st[ST_PUBLISH] += scount;
+    scount = 0;
+    wave_sync();
+  }
+
+  // Wave-collective push: lanes with p hand (w, q, nv) to the local queue
+  // when allowed and there is room, else to the staging buffer.
+  __device__ __forceinline__ void push(bool p, uint32_t w, uint32_t q, Val nv, bool ring_ok) {
+    const unsigned long long bal = __ballot(p);
+    if (bal == 0) return;
+    const uint32_t c = __popcll(bal);
+    const uint32_t pos = mbcnt64(bal);
+    if (ring_ok && (tail - head) + c <= Q) {
+      if (p) {
+        const uint32_t i = (tail + pos) & (Q - 1);
+        rv[i] = w;
+        rval[i] = nv;
+        if (MULTI) rq[i] = q;
+      }
+      tail += c;
+    } else {
+      if (scount + c > S) flush_stage();
+      if (p) {
+        const uint32_t i = scount + pos;
+        sv[i] = w;
+        sval[i] = nv;
+        if (MULTI) sq[i] = q;
+      }
+      scount += c;
+    }
+  }
+
+  // Relax arc (., w) with value val of its tail; returns whether the state of
+  // w changed and the value to carry.
+  __device__ __forceinline__ bool relax(int64_t sb, uint32_t w, Val val, Val &nv) {
+    if (KIND == KIND_BFS) {
+      const uint32_t nd = (uint32_t)val + 1u;
+      const uint32_t old = min_ag((uint32_t *)&state[sb + w], nd);
+      nv = (Val)nd;
+      return nd < old;
+    } else {
+      const unsigned long long old = or_ag((unsigned long long *)&state[sb + w], (unsigned long long)val);
+      nv = (Val)(old | (unsigned long long)val);
+      return nv != (Val)old;
+    }
+  }
+
+  // Expand the active lanes' entries: scan out-arcs, relax, push successes.
+  // Returns the number of entries expanded (not stale).
+  __device__ uint32_t expand(bool act, uint32_t v, uint32_t q, Val val, bool ring_ok) {
+    const int64_t sb = (act && MULTI) ? sbase_of(q) : 0;
+    int32_t b = 0, e = 0;
+    if (act) {
+      b = a.off[v];
+      e = a.off[v + 1];
+    }
+    if (KIND == KIND_BFS && act) {
+      // a smaller distance is already known: another entry carries it
+      const uint32_t cur = ld_ag((uint32_t *)&state[sb + v]);
+      if (cur < (uint32_t)val) act = false;
+    }
+    const unsigned long long actb = __ballot(act);
+    const uint32_t nexp = __popcll(actb);
+    st[ST_EXPAND] += nexp;
+    const uint32_t deg = act ? (uint32_t)(e - b) : 0u;
+    const uint32_t maxd = wave_max(deg);
+    if (maxd == 0) return nexp;
+    if (maxd <= 8) {
+      int32_t w[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) w[u] = ((uint32_t)u < deg) ? a.tgt[b + u] : 0;
+      bool ok[8];
+      Val nv[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        ok[u] = false;
+        nv[u] = 0;
+        if ((uint32_t)u < deg) ok[u] = relax(sb, (uint32_t)w[u], val, nv[u]);
+      }
+      uint32_t nsucc = 0, arcs = 0;
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        if ((uint32_t)u < maxd) {
+          arcs += __popcll(__ballot((uint32_t)u < deg));
+          nsucc += __popcll(__ballot(ok[u]));
+          push(ok[u], (uint32_t)w[u], q, nv[u], ring_ok);
+        }
+      }
+      st[ST_SUCCESS] += nsucc;
+      st[ST_ARCS] += arcs;
+      return nexp;
+    }
+    // Flattened: the wave's arcs are dealt out 64 at a time; each lane finds
+    // its arc's owner lane by binary search over the inclusive degree scan.
+    const uint32_t incl = wave_incl_scan(deg, ln);
+    const uint32_t total = __shfl(incl, 63);
+    const uint32_t excl = incl - deg;
+    scan[ln] = incl;
+    wave_sync();
+    st[ST_ARCS] += total;
+    uint32_t nsucc = 0;
+    for (uint32_t j = 0; j < total; j += 64) {
+      const uint32_t ai = j + ln;
+      const bool okl = ai < total;
+      uint32_t pos = 0;
+#pragma unroll
+      for (uint32_t step = 32; step >= 1; step >>= 1)
+        if (scan[pos + step - 1] <= ai) pos += step;
+      const int owner = (int)min(pos, 63u);
+      const int32_t bo = __shfl(b, owner);
+      const uint32_t eo = __shfl(excl, owner);
+      const uint32_t qo = MULTI ? (uint32_t)__shfl(q, owner) : 0u;
+      const int64_t sbo = MULTI ? (int64_t)shfl64((unsigned long long)sb, owner) : 0;
+      Val vo;
+      if (KIND == KIND_BFS)
+        vo = (Val)__shfl((uint32_t)val, owner);
+      else
+        vo = (Val)shfl64((unsigned long long)val, owner);
+      uint32_t w = 0;
+      bool ok = false;
+      Val nv = 0;
+      if (okl) {
+        w = (uint32_t)a.tgt[bo + (int32_t)(ai - eo)];
+        ok = relax(sbo, w, vo, nv);
+      }
+      nsucc += __popcll(__ballot(ok));
+      push(ok, w, qo, nv, ring_ok);
+    }
+    wave_sync();
+    st[ST_SUCCESS] += nsucc;
+    return nexp;
+  }
+
+  // Pop up to 64 entries from the local queue and expand them.
+  __device__ uint32_t step(bool ring_ok) {
+    const uint32_t avail = tail - head;
+    const uint32_t k = min(avail, 64u);
+    const uint32_t idx = FIFO ? (head + ln) : (tail - k + ln);
+    const bool act = ln < k;
+    uint32_t v = 0, q = 0;
+    Val val = 0;
+    if (act) {
+      const uint32_t s = idx & (Q - 1);
+      v = rv[s];
+      val = rval[s];
+      if (MULTI) q = rq[s];
+    }
+    wave_sync();
+    if (FIFO)
+      head += k;
+    else
+      tail -= k;
+    const uint32_t ne = expand(act, v, q, val, ring_ok);
+    st[ST_STALE] += (uint32_t)__popcll(__ballot(act)) - ne;
+    return ne;
+  }
+
+  // Move whatever is left in the local queue to the staging buffer.
+  __device__ void spill_ring() {
+    while (tail != head) {
+      const uint32_t k = min(tail - head, 64u);
+      const bool act = ln < k;
+      uint32_t v = 0, q = 0;
+      Val val = 0;
+      if (act) {
+        const uint32_t s = (head + ln) & (Q - 1);
+        v = rv[s];
+        val = rval[s];
+        if (MULTI) q = rq[s];
+      }
+      wave_sync();
+      head += k;
+      push(act, v, q, val, false);
+    }
+    head = tail = 0;
+  }
+
+  // One local search: the ring holds the roots; expand until the budget of
+  // expanded vertices is spent or nothing is left, then publish the rest.
+  __device__ void local_search(uint32_t budget) {
+    uint32_t expanded = 0;
+    while (tail != head) {
+      if (expanded >= budget) {
+        spill_ring();
+        break;
+      }
+      expanded += step(true);
+    }
+    head = tail = 0;
+  }
+
+  __device__ void load_roots(bool has, uint32_t v, uint32_t q, Val val) {
+    const unsigned long long bal = __ballot(has);
+    const uint32_t pos = mbcnt64(bal);
+    if (has) {
+      rv[pos] = v;
+      rval[pos] = val;
+      if (MULTI) rq[pos] = q;
+    }
+    wave_sync();
+    head = 0;
+    tail = __popcll(bal);
+  }
+
+  __device__ void process_frontier(uint32_t cbuf, uint32_t cslot, uint32_t nproc, uint32_t chunk) {
+    while (true) {
+      uint32_t base = 0;
+      if (ln == 0) base = add_ag(&a.ctl->claim[cslot], chunk);
+      base = __shfl(base, 0);
+      if (base >= nproc) break;
+      const uint32_t cnt = min(chunk, nproc - base);
+      const bool has = ln < cnt;
+      uint32_t v = 0, q = 0;
+      Val val = 0;
+      if (has) {
+        v = ld_ag(&a.fr.v[cbuf][base + ln]);
+        if (MULTI) q = ld_ag(&a.fr.q[cbuf][base + ln]);
+        val = (Val)ld_ag(&a.fr.val[cbuf][base + ln]);
+      }
+      load_roots(has, v, q, val);
+      local_search(a.tau * cnt);
+    }
+  }
+
+  // Re-expand vertices whose frontier entries overflowed last round.
+  __device__ void process_dirty(uint32_t cslot) {
+    while (true) {
+      uint32_t base = 0;
+      if (ln == 0) base = add_ag(&a.ctl->dclaim[cslot], 64u);
+      base = __shfl(base, 0);
+      if ((int64_t)base >= a.dirty_words) break;
+      // virtual word index -> (query, word of that query's bitmap)
+      const int64_t widx = (int64_t)base + ln;
+      uint32_t q = 0;
+      int64_t lw = widx;
+      if (MULTI && widx < a.dirty_words) {
+        int32_t lo = 0, hi = a.nq - 1;  // last q with qword[q] <= widx
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) >> 1;
+          if (a.qword[mid] <= widx) lo = mid;
+          else hi = mid - 1;
+        }
+        q = (uint32_t)lo;
+        lw = widx - a.qword[q];
+      }
+      uint32_t word = 0;
+      if (widx < a.dirty_words) {
+        uint32_t *wp = &a.dirty[(MULTI ? a.qi[q].dbase : 0) + lw];
+        word = ld_ag(wp);
+        if (word) word = xchg_ag(wp, 0u);
+      }
+      while (__ballot(word != 0)) {
+        const bool has = word != 0;
+        uint32_t v = 0;
+        Val val = 0;
+        if (has) {
+          const uint32_t bit = __builtin_ctz(word);
+          word &= word - 1;
+          int32_t vbase = 0;
+          int64_t sb = 0;
+          if (MULTI) {
+            vbase = a.qi[q].vbase;
+            sb = a.qi[q].sbase;
+          }
+          v = (uint32_t)vbase + (uint32_t)(lw * 32 + bit);
+          val = ld_ag(&state[sb + v]);
+        }
+        const uint32_t c = __popcll(__ballot(has));
+        load_roots(has, v, q, val);
+        local_search(a.tau * c);
+      }
+    }
+  }
+
+  __device__ void flush_stats() {
+    if (ln == 0) {
+#pragma unroll
+      for (int i = 0; i < ST_COUNT; i++)
+        if (st[i]) add_ag(&a.ctl->stats[i], st[i]);
+    }
+  }
+};
+
+template <int KIND, bool MULTI>
+__global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t wid = threadIdx.x >> 6;
+  const size_t per_wave = vgc_lds_bytes(KIND, MULTI, 1, a.ring_cap, a.stage_cap);
+  Wave<KIND, MULTI> wv(a, smem + per_wave * wid);
+  const uint32_t total_waves = gridDim.x * nw;
+  const long long deadline = wall_clock64() + a.timeout_ticks;
+  uint32_t epoch = 0;
+  uint32_t cbuf = a.start_buf;
+  uint32_t ncur = ld_ag(&a.ctl->cnt[0]);
+  uint32_t ovf = ld_ag(&a.ctl->ovf[0]);
+  uint32_t maxf = 0;
+  uint32_t r = 0;
+  for (; r < a.max_rounds; ++r) {
+    if (ncur == 0 && ovf == 0) break;
+    maxf = max(maxf, ncur);
+    const uint32_t cslot = r % 3, nslot = (r + 1) % 3, fslot = (r + 2) % 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st_ag(&a.ctl->cnt[fslot], 0u);
+      st_ag(&a.ctl->claim[fslot], 0u);
+      st_ag(&a.ctl->dclaim[fslot], 0u);
+      st_ag(&a.ctl->ovf[fslot], 0u);
+    }
+    wv.nslot = nslot;
+    wv.nbuf = cbuf ^ 1u;
+    if (ovf) wv.process_dirty(cslot);
+    const uint32_t nproc = min(ncur, a.fr.cap);
+    uint32_t chunk = (nproc + total_waves - 1) / total_waves;
+    chunk = min(max(chunk, 1u), 64u);
+    wv.process_frontier(cbuf, cslot, nproc, chunk);
+    wv.flush_stage();
+    if (grid_barrier(a.ctl, epoch, deadline)) break;
+    ncur = ld_ag(&a.ctl->cnt[nslot]);
+    ovf = ld_ag(&a.ctl->ovf[nslot]);
+    cbuf ^= 1u;
+  }
+  wv.flush_stats();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st_ag(&a.ctl->rounds, r);
+    st_ag(&a.ctl->final_cnt, ncur);
+    st_ag(&a.ctl->final_ovf, ovf);
+    st_ag(&a.ctl->final_buf, cbuf);
+    max_ag(&a.ctl->max_frontier, maxf);
+  }
+}
+
+template <int KIND>
+__global__ void seed_kernel(VgcArgs a, const SeedEnt *seeds, uint32_t nseed, uint32_t start_cnt, uint32_t start_ovf) {
+  using Val = typename ValT<KIND>::T;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t base = min(start_cnt, a.fr.cap);
+  if (i == 0) {
+    st_ag(&a.ctl->cnt[0], base + nseed);
+    if (start_ovf) or_ag(&a.ctl->ovf[0], 1u);
+  }
+  if (i < nseed) {
+    const SeedEnt s = seeds[i];
+    const QInfo qi = a.qi[s.q];
+    Val *state = (Val *)a.state;
+    if (KIND == KIND_BFS)
+      min_ag((uint32_t *)&state[qi.sbase + s.v], (uint32_t)s.val);
+    else
+      or_ag((unsigned long long *)&state[qi.sbase + s.v], (unsigned long long)s.val);
+    const uint32_t pos = base + i;
+    if (pos < a.fr.cap) {
+      st_ag(&a.fr.v[a.start_buf][pos], s.v);
+      if (a.fr.q[a.start_buf]) st_ag(&a.fr.q[a.start_buf][pos], s.q);
+      st_ag(&a.fr.val[a.start_buf][pos], s.val);
+    } else {
+      const uint32_t local = s.v - (uint32_t)qi.vbase;
+      or_ag(&a.dirty[qi.dbase + (local >> 5)], 1u << (local & 31));
+      or_ag(&a.ctl->ovf[0], 1u);
+    }
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t val) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t n4 = n / 4;
+  uint4 *p4 = (uint4 *)p;
+  const bool aligned = (((uintptr_t)p) & 15) == 0;
+  if (aligned) {
+    const uint4 v = make_uint4(val, val, val, val);
+    for (uint64_t j = i; j < n4; j += stride) p4[j] = v;
+    for (uint64_t j = n4 * 4 + i; j < n; j += stride) p[j] = val;
+  } else {
+    for (uint64_t j = i; j < n; j += stride) p[j] = val;
+  }
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, uint64_t n, unsigned long long val) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) p[j] = val;
+}
+
+static int fill_grid(uint64_t n) {
+  uint64_t blocks = (n / 4 + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 8192) blocks = 8192;
+  return (int)blocks;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t val, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, val);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long val, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(fill_grid(4 * n)), dim3(256), 0, s, p, n, val);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_t nseed, uint32_t start_cnt,
+                       uint32_t start_ovf, hipStream_t s) {
+  const int grid = (int)((nseed + 255) / 256) > 0 ? (int)((nseed + 255) / 256) : 1;
+  if (kind == KIND_BFS)
+    hipLaunchKernelGGL(seed_kernel<KIND_BFS>, dim3(grid), dim3(256), 0, s, a, seeds, nseed, start_cnt, start_ovf);
+  else
+    hipLaunchKernelGGL(seed_kernel<KIND_REACH>, dim3(grid), dim3(256), 0, s, a, seeds, nseed, start_cnt, start_ovf);
+  return hipGetLastError();
+}
+
+const void *vgc_kernel_ptr(int kind, bool multi) {
+  if (kind == KIND_BFS) return multi ? (const void *)vgc_kernel<KIND_BFS, true> : (const void *)vgc_kernel<KIND_BFS, false>;
+  return multi ? (const void *)vgc_kernel<KIND_REACH, true> : (const void *)vgc_kernel<KIND_REACH, false>;
+}
+
+hipError_t launch_vgc(int kind, bool multi, const VgcArgs &a, int grid, int block, size_t lds, bool cooperative,
+                      hipStream_t s) {
+  const void *fn = vgc_kernel_ptr(kind, multi);
+  VgcArgs copy = a;
+  void *args[] = {&copy};
+  if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, s);
+  return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, s);
+}
+
+// ------------------------------------------------------ plain (VGC off) --
+// One BFS level per launch: wavefronts take 64 frontier vertices each and
+// deal their arcs out over the lanes; atomicCAS from "unreached" to level+1
+// admits each vertex exactly once (the standard parallel BFS condition of
+// the frontier framework).
+
+template <int KIND>
+__global__ void __launch_bounds__(256) plain_level_kernel(const int32_t *off, const int32_t *tgt, void *statev,
+                                                          uint32_t *stamp, const uint32_t *cur, uint32_t ncur,
+                                                          uint32_t *nxt, uint32_t *cnt, uint32_t level, Ctl *ctl) {
+  __shared__ uint32_t scan_s[4][64];
+  const uint32_t ln = lane_id();
+  const uint32_t wid = threadIdx.x >> 6;
+  const uint32_t gw = blockIdx.x * (blockDim.x >> 6) + wid;
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[(level + 2) % 3] = 0;
+  uint32_t *nxt_cnt = &cnt[(level + 1) % 3];
+  unsigned long long arcs = 0, succ = 0;
+  for (uint32_t base = gw * 64; base < ncur; base += nw * 64) {
+    const bool act = base + ln < ncur;
+    uint32_t v = 0;
+    int32_t b = 0, e = 0;
+    unsigned long long m = 0;
+    if (act) {
+      v = cur[base + ln];
+      b = off[v];
+      e = off[v + 1];
+      if (KIND == KIND_REACH) m = ld_ag(&((unsigned long long *)statev)[v]);
+    }
+    const uint32_t deg = act ? (uint32_t)(e - b) : 0u;
+    const uint32_t incl = wave_incl_scan(deg, ln);
+    const uint32_t total = __shfl(incl, 63);
+    const uint32_t excl = incl - deg;
+    scan_s[wid][ln] = incl;
+    wave_sync();
+    arcs += total;
+    for (uint32_t j = 0; j < total; j += 64) {
+      const uint32_t ai = j + ln;
+      uint32_t pos = 0;
+#pragma unroll
+      for (uint32_t step = 32; step >= 1; step >>= 1)
+        if (scan_s[wid][pos + step - 1] <= ai) pos += step;
+      const int owner = (int)min(pos, 63u);
+      const int32_t bo = __shfl(b, owner);
+      const uint32_t eo = __shfl(excl, owner);
+      const unsigned long long mo = (KIND == KIND_REACH) ? shfl64(m, owner) : 0ull;
+      bool ok = false;
+      uint32_t w = 0;
+      if (ai < total) {
+        w = (uint32_t)tgt[bo + (int32_t)(ai - eo)];
+        if (KIND == KIND_BFS) {
+          ok = cas_ag(&((uint32_t *)statev)[w], INF32, level + 1) == INF32;
+        } else {
+          const unsigned long long old = or_ag(&((unsigned long long *)statev)[w], mo);
+          if ((old | mo) != old) ok = xchg_ag(&stamp[w], level + 1) != level + 1;
+        }
+      }
+      const unsigned long long bal = __ballot(ok);
+      if (bal) {
+        uint32_t at = 0;
+        if (ln == 0) at = add_ag(nxt_cnt, (uint32_t)__popcll(bal));
+        at = __shfl(at, 0);
+        if (ok) nxt[at + mbcnt64(bal)] = w;
+        succ += __popcll(bal);
+      }
+    }
+    wave_sync();
+  }
+  if (ln == 0) {
+    if (arcs) add_ag(&ctl->stats[ST_ARCS], arcs);
+    if (succ) add_ag(&ctl->stats[ST_SUCCESS], succ);
+  }
+}
+
+hipError_t launch_plain_bfs_level(const int32_t *off, const int32_t *tgt, uint32_t *dist, const uint32_t *cur,
+                                  uint32_t ncur, uint32_t *nxt, uint32_t *cnt, uint32_t level, Ctl *ctl,
+                                  hipStream_t s) {
+  uint32_t waves = (ncur + 63) / 64;
+  uint32_t blocks = (waves + 3) / 4;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(plain_level_kernel<KIND_BFS>, dim3(blocks), dim3(256), 0, s, off, tgt, (void *)dist,
+                     (uint32_t *)nullptr, cur, ncur, nxt, cnt, level, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_reach_level(const int32_t *off, const int32_t *tgt, unsigned long long *mask,
+                                    uint32_t *stamp, const uint32_t *cur, uint32_t ncur, uint32_t *nxt,
+                                    uint32_t *cnt, uint32_t level, Ctl *ctl, hipStream_t s) {
+  uint32_t waves = (ncur + 63) / 64;
+  uint32_t blocks = (waves + 3) / 4;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(plain_level_kernel<KIND_REACH>, dim3(blocks), dim3(256), 0, s, off, tgt, (void *)mask, stamp,
+                     cur, ncur, nxt, cnt, level, ctl);
+  return hipGetLastError();
+}
+
+// Level-0 frontier: BFS sets dist[src] = 0; reach ORs bit i into
+// mask[srcs[i]]. A vertex enters the frontier once (stamp 0 for reach).
+__global__ void plain_seed_kernel(int kind, void *state, uint32_t *frontier, uint32_t *cnt, uint32_t *stamp,
+                                  const uint32_t *srcs, const unsigned long long *vals, uint32_t nsrc) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsrc) return;
+  const uint32_t v = srcs[i];
+  bool push;
+  if (kind == KIND_BFS) {
+    push = cas_ag(&((uint32_t *)state)[v], INF32, 0u) == INF32;
+  } else {
+    or_ag(&((unsigned long long *)state)[v], vals[i]);
+    push = xchg_ag(&stamp[v], 0u) != 0u;
+  }
+  if (push) frontier[add_ag(&cnt[0], 1u)] = v;
+}
+
+hipError_t launch_plain_seed(int kind, void *state, uint32_t *frontier, uint32_t *cnt_slots, uint32_t *stamp,
+                             const uint32_t *srcs, const unsigned long long *vals, uint32_t nsrc, hipStream_t s) {
+  hipLaunchKernelGGL(plain_seed_kernel, dim3((nsrc + 255) / 256), dim3(256), 0, s, kind, state, frontier, cnt_slots,
+                     stamp, srcs, vals, nsrc);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- transpose --
+// G^T by counting sort on the target: histogram, exclusive scan, scatter.
+
+__global__ void hist_kernel(const int32_t *tgt, int32_t m, int32_t *cnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride)
+    add_ag(&cnt[tgt[e]], 1);
+}
+
+constexpr int SCAN_TILE = 1024;  // elements per block (256 threads x 4)
+
+__device__ int32_t block_excl_scan_256(int32_t x, int32_t &total) {
+  __shared__ int32_t wsum[4];
+  const uint32_t ln = lane_id(), wid = threadIdx.x >> 6;
+  int32_t incl = (int32_t)wave_incl_scan((uint32_t)x, ln);
+  if (ln == 63) wsum[wid] = incl;
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+  for (uint32_t w = 0; w < 4; w++) {
+    if (w < wid) off += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  total = tot;
+  return off + incl - x;
+}
+
+// tile sums of in[0..len)
+__global__ void scan_tiles_kernel(const int32_t *in, int64_t len, int32_t *sums) {
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 4;
+  int32_t s = 0;
+  for (int k = 0; k < 4; k++)
+    if (base + k < len) s += in[base + k];
+  int32_t tot;
+  block_excl_scan_256(s, tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// exclusive scan of sums[0..nt) in place, one block
+__global__ void scan_sums_kernel(int32_t *sums, int64_t nt) {
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nt; base += 256) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t x = (i < nt) ? sums[i] : 0;
+    int32_t tot;
+    const int32_t ex = block_excl_scan_256(x, tot);
+    const int32_t c = carry;
+    if (i < nt) sums[i] = c + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c + tot;
+    __syncthreads();
+  }
+}
+
+// out[i] = exclusive prefix of in over [0..len); out has len+1 entries
+__global__ void scan_apply_kernel(const int32_t *in, int64_t len, const int32_t *sums, int32_t *out) {
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 4;
+  int32_t v[4];
+  int32_t s = 0;
+  for (int k = 0; k < 4; k++) {
+    v[k] = (base + k < len) ? in[base + k] : 0;
+    s += v[k];
+  }
+  int32_t tot;
+  int32_t ex = block_excl_scan_256(s, tot) + sums[blockIdx.x];
+  for (int k = 0; k < 4; k++) {
+    if (base + k <= len) out[base + k] = ex;
+    ex += v[k];
+  }
+}
+
+__global__ void __launch_bounds__(256) scatter_kernel(const int32_t *off, const int32_t *tgt, int32_t n,
+                                                      int32_t *cursor, int32_t *t_tgt) {
+  __shared__ uint32_t scan_s[4][64];
+  const uint32_t ln = lane_id();
+  const uint32_t wid = threadIdx.x >> 6;
+  const uint32_t gw = blockIdx.x * 4 + wid;
+  const uint32_t nw = gridDim.x * 4;
+  for (uint32_t base = gw * 64; base < (uint32_t)n; base += nw * 64) {
+    const bool act = base + ln < (uint32_t)n;
+    const uint32_t u = base + ln;
+    int32_t b = 0, e = 0;
+    if (act) {
+      b = off[u];
+      e = off[u + 1];
+    }
+    const uint32_t deg = act ? (uint32_t)(e - b) : 0u;
+    const uint32_t incl = wave_incl_scan(deg, ln);
+    const uint32_t total = __shfl(incl, 63);
+    const uint32_t excl = incl - deg;
+    scan_s[wid][ln] = incl;
+    wave_sync();
+    for (uint32_t j = 0; j < total; j += 64) {
+      const uint32_t ai = j + ln;
+      uint32_t pos = 0;
+#pragma unroll
+      for (uint32_t step = 32; step >= 1; step >>= 1)
+        if (scan_s[wid][pos + step - 1] <= ai) pos += step;
+      const int owner = (int)min(pos, 63u);
+      const int32_t bo = __shfl(b, owner);
+      const uint32_t eo = __shfl(excl, owner);
+      if (ai < total) {
+        const int32_t w = tgt[bo + (int32_t)(ai - eo)];
+        const int32_t at = add_ag(&cursor[w], 1);
+        t_tgt[at] = (int32_t)(base + (uint32_t)owner);
+      }
+    }
+    wave_sync();
+  }
+}
+
+size_t transpose_scratch_elems(int32_t n) {
+  const int64_t tiles = ((int64_t)n + 1 + SCAN_TILE - 1) / SCAN_TILE;
+  return (size_t)n + 1 + (size_t)tiles + 16;
+}
+
+hipError_t launch_transpose(const int32_t *off, const int32_t *tgt, int32_t n, int32_t m, int32_t *t_off,
+                            int32_t *t_tgt, int32_t *scratch, hipStream_t s) {
+  int32_t *cnt = scratch;                 // n+1 (histogram, then cursor)
+  const int64_t len = (int64_t)n + 1;
+  const int64_t tiles = (len + SCAN_TILE - 1) / SCAN_TILE;
+  int32_t *sums = scratch + n + 1;        // tiles
+  hipError_t e = launch_fill_u32((uint32_t *)cnt, (uint64_t)len, 0u, s);
+  if (e != hipSuccess) return e;
+  if (m > 0) {
+    int g = (int)((m + 255) / 256);
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(hist_kernel, dim3(g), dim3(256), 0, s, tgt, m, cnt);
+  }
+  // counts live at cnt[0..n); scan them into t_off[0..n]
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(256), 0, s, cnt, (int64_t)n, sums);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, sums, tiles);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(256), 0, s, cnt, (int64_t)n, sums, t_off);
+  e = hipMemcpyAsync(cnt, t_off, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  if (m > 0) {
+    int g = (int)(((int64_t)n + 255) / 256);
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(256), 0, s, off, tgt, n, cnt, t_tgt);
+  }
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- validate --
+
+__global__ void validate_kernel(const int32_t *off, const int32_t *tgt, int32_t n, int32_t m, Ctl *ctl) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  if (tid == 0) bad = (off[0] != 0) || (off[n] != m);
+  for (int64_t v = tid; v < n; v += stride) bad |= off[v] > off[v + 1];
+  if (!bad) {
+    for (int64_t e = tid; e < m; e += stride) {
+      const int32_t w = tgt[e];
+      bad |= (w < 0) || (w >= n);
+    }
+  }
+  if (bad) or_ag(&ctl->bad_csr, 1u);
+}
+
+hipError_t launch_validate(const int32_t *off, const int32_t *tgt, int32_t n, int32_t m, Ctl *ctl, hipStream_t s) {
+  int64_t work = (int64_t)n > (int64_t)m ? (int64_t)n : (int64_t)m;
+  int g = (int)((work + 255) / 256);
+  if (g < 1) g = 1;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(validate_kernel, dim3(g), dim3(256), 0, s, off, tgt, n, m, ctl);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- census --
+
+__global__ void census_kernel(const uint32_t *fq, uint32_t cnt, uint32_t *counts, const QInfo *qi,
+                              const int64_t *qword, const uint32_t *dirty, int32_t nq, uint32_t *dirty_any,
+                              int scan_dirty) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = tid; i < cnt; i += stride) add_ag(&counts[fq[i]], 1u);
+  if (scan_dirty) {
+    const int64_t words = qword[nq];
+    for (int64_t w = tid; w < words; w += stride) {
+      int32_t lo = 0, hi = nq - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (qword[mid] <= w) lo = mid;
+        else hi = mid - 1;
+      }
+      if (dirty[qi[lo].dbase + (w - qword[lo])]) st_ag(&dirty_any[lo], 1u);
+    }
+  }
+}
+
+hipError_t launch_census(const uint32_t *fq, uint32_t cnt, uint32_t cap, uint32_t *counts, const QInfo *qi,
+                         const int64_t *qword, const uint32_t *dirty, int32_t nq, uint32_t *dirty_any,
+                         hipStream_t s) {
+  const uint32_t c = cnt < cap ? cnt : cap;
+  int g = (int)((c + 255) / 256);
+  if (g < 64) g = 64;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(census_kernel, dim3(g), dim3(256), 0, s, fq, c, counts, qi, qword, dirty, nq, dirty_any,
+                     dirty_any != nullptr ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ small utils --
+
+__global__ void strided_u64_kernel(unsigned long long *dst, int stride, int word, const unsigned long long *src,
+                                   uint64_t n) {
+  const uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += st)
+    dst[v * (uint64_t)stride + (uint64_t)word] = src[v];
+}
+
+hipError_t launch_strided_u64(unsigned long long *dst, int stride, int word, const unsigned long long *src,
+                              uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(strided_u64_kernel, dim3(fill_grid(4 * n)), dim3(256), 0, s, dst, stride, word, src, n);
+  return hipGetLastError();
+}
+
+// One block per segment (grid-stride over segments); segments are
+// [seg_off[i], seg_off[i] + seg_len[i]) of base.
+template <class T>
+__global__ void fill_segments_kernel(T *base, const int64_t *seg_off, const int64_t *seg_len, int32_t nseg, T val) {
+  for (int32_t sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
+    T *p = base + seg_off[sgi];
+    const int64_t len = seg_len[sgi];
+    for (int64_t j = threadIdx.x; j < len; j += blockDim.x) p[j] = val;
+  }
+}
+
+hipError_t launch_fill_segments_u32(uint32_t *base, const int64_t *seg_off, const int64_t *seg_len, int32_t nseg,
+                                    uint32_t val, hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_segments_kernel<uint32_t>, dim3(nseg < 65536 ? nseg : 65536), dim3(1024), 0, s, base,
+                     seg_off, seg_len, nseg, val);
+  return hipGetLastError();
+}
+hipError_t launch_fill_segments_u64(unsigned long long *base, const int64_t *seg_off, const int64_t *seg_len,
+                                    int32_t nseg, unsigned long long val, hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_segments_kernel<unsigned long long>, dim3(nseg < 65536 ? nseg : 65536), dim3(1024), 0, s,
+                     base, seg_off, seg_len, nseg, val);
+  return hipGetLastError();
+}
+
+__global__ void add_const_kernel(int32_t *dst, const int32_t *src, int64_t n, int32_t c) {
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += st) dst[i] = src[i] + c;
+}
+
+hipError_t launch_add_const(int32_t *dst, const int32_t *src, int64_t n, int32_t c, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(add_const_kernel, dim3(fill_grid(4 * (uint64_t)n)), dim3(256), 0, s, dst, src, n, c);
+  return hipGetLastError();
+}
+
+}  // namespace pg

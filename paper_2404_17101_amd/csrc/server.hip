@@ -1,0 +1,620 @@
+// server.hip -- served form: a request loop over graphs resident in device
+// memory, with continuous batching.
+//
+//  * Graphs are copied into one server-owned packed CSR (global vertex ids),
+//    so a single persistent launch can advance requests on any of them.
+//  * Each request's state (dist or mask array, plus its dirty bitmap) is
+//    carved from an arena of memory_budget bytes; a request is admitted when
+//    a slot is free and its state fits (first-fit allocator on the host).
+//  * The scheduler thread runs slices: one persistent VGC launch per kind
+//    (BFS, reach) of at most slice_rounds rounds over every admitted request
+//    of that kind. The frontier survives between slices, newly admitted
+//    requests are seeded into it at the slice boundary, and a census of the
+//    frontier (plus the dirty bitmaps when an overflow is pending) tells
+//    which requests have no work left; those are copied to the caller's
+//    buffer, completed and their memory is returned. Requests therefore join
+//    and leave while others are still being traversed on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "engine.h"
+#include "kern.h"
+#include "pasgal.h"
+
+using namespace pg;
+
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, size) with coalescing, 256-byte granules.
+struct Arena {
+  std::map<int64_t, int64_t> free_;  // offset -> length
+  int64_t size = 0;
+  std::atomic<int64_t> used{0};
+  void reset(int64_t sz) {
+    free_.clear();
+    size = sz;
+    used = 0;
+    if (sz > 0) free_[0] = sz;
+  }
+  int64_t alloc(int64_t len) {
+    len = (len + 255) & ~(int64_t)255;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= len) {
+        const int64_t off = it->first, rest = it->second - len;
+        free_.erase(it);
+        if (rest > 0) free_[off + len] = rest;
+        used += len;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off, int64_t len) {
+    len = (len + 255) & ~(int64_t)255;
+    used -= len;
+    auto it = free_.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Req {
+  int64_t id = 0;
+  pasgal_request r{};
+  double t_submit = 0, t_admit = 0;
+  int64_t rounds = 0;
+  int slot = -1;
+  int64_t off = -1, bytes = 0, dirty_off = 0;
+  int32_t vbase = 0, nv = 0;
+};
+
+// One multi-query VGC engine per request kind.
+struct Lane {
+  int kind = KIND_BFS;
+  uint64_t cap = 0;
+  DBuf fv[2], fq[2], fval[2], ctl, qi, qword, seeds, counts, dany;
+  HBuf h_ctl, h_counts, h_dany, h_stage;
+  uint32_t cur_buf = 0, cur_cnt = 0, cur_ovf = 0;
+  std::vector<Req *> slots;  // slot -> request (nullptr = free)
+  std::vector<Req *> fresh;  // admitted, not yet seeded
+  std::atomic<int> active{0};
+  LaunchGeom lg;
+  ~Lane() {
+    for (DBuf *b : {&fv[0], &fv[1], &fq[0], &fq[1], &fval[0], &fval[1], &ctl, &qi, &qword, &seeds, &counts, &dany})
+      free_buf(*b);
+    for (HBuf *b : {&h_ctl, &h_counts, &h_dany, &h_stage}) free_hbuf(*b);
+  }
+};
+
+}  // namespace
+
+struct pasgal_server {
+  pasgal_server_opts opts{};
+  Opts vopts;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // resident packed CSR
+  DBuf off, tgt;
+  int32_t n_total = 0, m_total = 0;
+  std::mutex graph_mu;            // guards vbase/ebase
+  std::vector<int32_t> vbase{0};
+  std::vector<int32_t> ebase{0};
+  // request state arena
+  DBuf arena;
+  Arena alloc;
+  Lane lanes[2];
+  // queues
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::deque<Req *> submitted;   // not yet admitted
+  std::deque<pasgal_completion> done;
+  int64_t next_id = 1;
+  int64_t inflight = 0;          // submitted and not completed
+  bool stop = false;
+  std::thread thr;
+  std::mutex gpu_mu;             // serializes device work (graph adds vs loop)
+
+  ~pasgal_server() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    if (thr.joinable()) thr.join();
+    for (Req *r : submitted) delete r;
+    for (Lane &l : lanes)
+      for (Req *r : l.slots) delete r;
+    free_buf(off);
+    free_buf(tgt);
+    free_buf(arena);
+    if (stream) hipStreamDestroy(stream);
+  }
+
+  void complete(Req *r, int status) {
+    pasgal_completion c{};
+    c.id = r->id;
+    c.tag = r->r.tag;
+    c.status = status;
+    c.graph = r->r.graph;
+    c.t_submit_ms = r->t_submit;
+    c.t_admit_ms = r->t_admit;
+    c.t_done_ms = now_ms();
+    c.rounds = r->rounds;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      done.push_back(c);
+      inflight--;
+    }
+    cv_done.notify_all();
+    delete r;
+  }
+
+  int64_t state_bytes(const Req *r) const {
+    const int64_t es = r->r.kind == PASGAL_REQ_BFS ? 4 : 8;
+    const int64_t words = ((int64_t)r->nv + 31) / 32;
+    return ((es * r->nv + 255) & ~(int64_t)255) + 4 * words;
+  }
+
+  // Admit queued requests while slots and memory allow (FIFO, head-of-line).
+  void admit() {
+    std::deque<Req *> q;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      q.swap(submitted);
+    }
+    std::deque<Req *> back;
+    bool blocked = false;
+    for (Req *r : q) {
+      if (blocked) {
+        back.push_back(r);
+        continue;
+      }
+      Lane &L = lanes[r->r.kind == PASGAL_REQ_BFS ? 0 : 1];
+      int slot = -1;
+      for (size_t i = 0; i < L.slots.size(); i++)
+        if (!L.slots[i]) {
+          slot = (int)i;
+          break;
+        }
+      const int64_t bytes = state_bytes(r);
+      int64_t o = slot >= 0 ? alloc.alloc(bytes) : -1;
+      if (slot < 0 || o < 0) {
+        blocked = true;  // keep arrival order: later requests wait too
+        back.push_back(r);
+        continue;
+      }
+      r->off = o;
+      r->bytes = bytes;
+      const int64_t es = r->r.kind == PASGAL_REQ_BFS ? 4 : 8;
+      r->dirty_off = o + ((es * r->nv + 255) & ~(int64_t)255);
+      r->slot = slot;
+      r->t_admit = now_ms();
+      L.slots[slot] = r;
+      L.fresh.push_back(r);
+      L.active++;
+    }
+    if (!back.empty()) {
+      std::lock_guard<std::mutex> lk(mu);
+      for (auto it = back.rbegin(); it != back.rend(); ++it) submitted.push_front(*it);
+    }
+  }
+
+  void fail_lane(Lane &L, int status) {
+    for (size_t i = 0; i < L.slots.size(); i++)
+      if (L.slots[i]) {
+        Req *r = L.slots[i];
+        alloc.release(r->off, r->bytes);
+        L.slots[i] = nullptr;
+        complete(r, status);
+      }
+    L.fresh.clear();
+    L.active = 0;
+    L.cur_cnt = 0;
+    L.cur_ovf = 0;
+  }
+
+  // One slice of one kind. Returns a PASGAL_* code (device errors).
+  int slice(Lane &L) {
+    hipStream_t s = stream;
+    const int kind = L.kind;
+    const int nslots = (int)L.slots.size();
+    const size_t es = kind == KIND_BFS ? 4 : 8;
+    // query tables over all slots (inactive slots own no words)
+    std::vector<QInfo> qi(nslots);
+    std::vector<int64_t> qword(nslots + 1, 0);
+    int64_t words = 0;
+    for (int i = 0; i < nslots; i++) {
+      const Req *r = L.slots[i];
+      qword[i] = words;
+      if (r) {
+        qi[i].sbase = r->off / (int64_t)es - r->vbase;
+        qi[i].dbase = r->dirty_off / 4;
+        qi[i].vbase = r->vbase;
+        qi[i].nv = r->nv;
+        words += (r->nv + 31) / 32;
+      } else {
+        qi[i] = QInfo{0, 0, 0, 0};
+      }
+    }
+    qword[nslots] = words;
+    std::vector<SeedEnt> seeds;
+    std::vector<int64_t> segoff, seglen, doff, dlen;
+    for (Req *r : L.fresh) {
+      for (int k = 0; k < r->r.nsources; k++) {
+        SeedEnt e;
+        e.v = (uint32_t)(r->vbase + r->r.sources[k]);
+        e.q = (uint32_t)r->slot;
+        e.val = kind == KIND_BFS ? 0ull : (1ull << k);
+        seeds.push_back(e);
+      }
+      segoff.push_back(r->off / (int64_t)es);
+      seglen.push_back(r->nv);
+      doff.push_back(r->dirty_off / 4);
+      dlen.push_back((r->nv + 31) / 32);
+    }
+    const size_t nseed = seeds.size(), nfresh = L.fresh.size();
+    // pinned staging: qi | qword | seeds | segoff | seglen | doff | dlen
+    const size_t b_qi = sizeof(QInfo) * nslots, b_qw = sizeof(int64_t) * (nslots + 1),
+                 b_se = sizeof(SeedEnt) * std::max<size_t>(nseed, 1), b_sg = sizeof(int64_t) * std::max<size_t>(nfresh, 1);
+    int rc;
+    if ((rc = grow_host(L.h_stage, b_qi + b_qw + b_se + 4 * b_sg))) return rc;
+    if ((rc = grow(L.seeds, b_se + 4 * b_sg))) return rc;
+    uint8_t *hs = (uint8_t *)L.h_stage.p;
+    memcpy(hs, qi.data(), b_qi);
+    memcpy(hs + b_qi, qword.data(), b_qw);
+    uint8_t *hx = hs + b_qi + b_qw;
+    if (nseed) memcpy(hx, seeds.data(), sizeof(SeedEnt) * nseed);
+    int64_t *hseg = (int64_t *)(hx + b_se);
+    for (size_t i = 0; i < nfresh; i++) {
+      hseg[i] = segoff[i];
+      hseg[b_sg / 8 + i] = seglen[i];
+      hseg[2 * b_sg / 8 + i] = doff[i];
+      hseg[3 * b_sg / 8 + i] = dlen[i];
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(L.qi.p, hs, b_qi, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemcpyAsync(L.qword.p, hs + b_qi, b_qw, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemcpyAsync(L.seeds.p, hx, b_se + 4 * b_sg, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return hip_fail(e);
+    const int64_t *dsegoff = (const int64_t *)((uint8_t *)L.seeds.p + b_se);
+    const int64_t *dseglen = dsegoff + b_sg / 8, *ddoff = dsegoff + 2 * b_sg / 8, *ddlen = dsegoff + 3 * b_sg / 8;
+    if (nfresh) {
+      if (kind == KIND_BFS)
+        e = launch_fill_segments_u32((uint32_t *)arena.p, dsegoff, dseglen, (int32_t)nfresh, 0xFFFFFFFFu, s);
+      else
+        e = launch_fill_segments_u64((unsigned long long *)arena.p, dsegoff, dseglen, (int32_t)nfresh, 0ull, s);
+      if (e != hipSuccess) return hip_fail(e);
+      if ((e = launch_fill_segments_u32((uint32_t *)arena.p, ddoff, ddlen, (int32_t)nfresh, 0u, s)) != hipSuccess)
+        return hip_fail(e);
+    }
+    VgcArgs a{};
+    a.off = (const int32_t *)off.p;
+    a.tgt = (const int32_t *)tgt.p;
+    a.state = arena.p;
+    a.dirty = (uint32_t *)arena.p;
+    a.qi = (const QInfo *)L.qi.p;
+    a.qword = (const int64_t *)L.qword.p;
+    a.dirty_words = words;
+    a.nq = nslots;
+    for (int i = 0; i < 2; i++) {
+      a.fr.v[i] = (uint32_t *)L.fv[i].p;
+      a.fr.q[i] = (uint32_t *)L.fq[i].p;
+      a.fr.val[i] = (unsigned long long *)L.fval[i].p;
+    }
+    a.fr.cap = (uint32_t)L.cap;
+    a.start_buf = L.cur_buf;
+    a.tau = vopts.tau;
+    a.max_rounds = (uint32_t)opts.slice_rounds;
+    a.ring_cap = L.lg.ring;
+    a.stage_cap = L.lg.stage;
+    a.timeout_ticks = (long long)vopts.timeout_ms * (long long)dev_info().wall_khz;
+    a.ctl = (Ctl *)L.ctl.p;
+    if ((e = launch_fill_u32((uint32_t *)L.ctl.p, sizeof(Ctl) / 4, 0u, s)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_seed(kind, a, (const SeedEnt *)L.seeds.p, (uint32_t)nseed, L.cur_cnt, L.cur_ovf, s)) !=
+        hipSuccess)
+      return hip_fail(e);
+    if ((e = launch_vgc(kind, true, a, L.lg.grid, L.lg.block, L.lg.lds, dev_info().coop != 0, s)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = hipMemcpyAsync(L.h_ctl.p, L.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
+    L.fresh.clear();
+    const Ctl c = *(const Ctl *)L.h_ctl.p;
+    if (c.abort) return PASGAL_ETIMEOUT;
+    L.cur_buf = c.final_buf;
+    L.cur_cnt = c.final_cnt;
+    L.cur_ovf = c.final_ovf;
+    for (Req *r : L.slots)
+      if (r) r->rounds += c.rounds;
+    // census: which requests still have frontier entries or dirty bits
+    if ((e = launch_fill_u32((uint32_t *)L.counts.p, (uint64_t)nslots, 0u, s)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_fill_u32((uint32_t *)L.dany.p, (uint64_t)nslots, 0u, s)) != hipSuccess) return hip_fail(e);
+    if (L.cur_cnt > 0 || L.cur_ovf) {
+      if ((e = launch_census((const uint32_t *)L.fq[L.cur_buf].p, L.cur_cnt, (uint32_t)L.cap, (uint32_t *)L.counts.p,
+                             (const QInfo *)L.qi.p, (const int64_t *)L.qword.p, (const uint32_t *)arena.p, nslots,
+                             L.cur_ovf ? (uint32_t *)L.dany.p : nullptr, s)) != hipSuccess)
+        return hip_fail(e);
+    }
+    if ((e = hipMemcpyAsync(L.h_counts.p, L.counts.p, 4 * (size_t)nslots, hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = hipMemcpyAsync(L.h_dany.p, L.dany.p, 4 * (size_t)nslots, hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
+    const uint32_t *cnts = (const uint32_t *)L.h_counts.p, *dany = (const uint32_t *)L.h_dany.p;
+    std::vector<Req *> fin;
+    for (int i = 0; i < nslots; i++) {
+      Req *r = L.slots[i];
+      if (!r) continue;
+      if (cnts[i] == 0 && dany[i] == 0) fin.push_back(r);
+    }
+    if (fin.empty()) return PASGAL_OK;
+    for (Req *r : fin) {
+      if (r->r.out) {
+        if ((e = hipMemcpyAsync(r->r.out, (uint8_t *)arena.p + r->off, es * (size_t)r->nv, hipMemcpyDeviceToDevice,
+                                s)) != hipSuccess)
+          return hip_fail(e);
+      }
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
+    for (Req *r : fin) {
+      L.slots[r->slot] = nullptr;
+      L.active--;
+      alloc.release(r->off, r->bytes);
+      complete(r, PASGAL_OK);
+    }
+    return PASGAL_OK;
+  }
+
+  void loop() {
+    hipSetDevice(device);
+    while (true) {
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait_for(lk, std::chrono::milliseconds(50), [&] {
+          return stop || !submitted.empty() || lanes[0].active > 0 || lanes[1].active > 0;
+        });
+        if (stop) return;
+      }
+      std::lock_guard<std::mutex> g(gpu_mu);
+      admit();
+      for (Lane &L : lanes) {
+        if (L.active == 0) continue;
+        int rc = slice(L);
+        if (rc != PASGAL_OK) {
+          hipGetLastError();
+          fail_lane(L, rc);
+        }
+      }
+    }
+  }
+};
+
+extern "C" {
+
+int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
+  if (!out) return PASGAL_EINVAL;
+  *out = nullptr;
+  pasgal_server *s = new (std::nothrow) pasgal_server();
+  if (!s) return PASGAL_ENOMEM;
+  if (o) s->opts = *o;
+  pasgal_server_opts &so = s->opts;
+  if (so.max_slots <= 0) so.max_slots = 256;
+  if (so.slice_rounds <= 0) so.slice_rounds = 16;
+  if (so.timeout_ms <= 0) so.timeout_ms = 20000;
+  if (so.memory_budget <= 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      delete s;
+      return PASGAL_EHIP;
+    }
+    so.memory_budget = (int64_t)(fr / 4);
+  }
+  if (so.max_slots > 4096) {
+    delete s;
+    return PASGAL_EINVAL;
+  }
+  hipGetDevice(&s->device);
+  pasgal_opts po;
+  pasgal_opts_default(&po);
+  if (so.tau > 0) po.tau = so.tau;
+  if (so.wg_size > 0) po.wg_size = so.wg_size;
+  if (so.blocks_per_cu > 0) po.blocks_per_cu = so.blocks_per_cu;
+  po.timeout_ms = so.timeout_ms;
+  if (!opts_valid(&po)) {
+    delete s;
+    return PASGAL_EINVAL;
+  }
+  hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e);
+  }
+  po.stream = s->stream;
+  s->vopts = resolve_opts(&po);
+  int rc = grow(s->arena, (size_t)so.memory_budget);
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  s->alloc.reset(so.memory_budget);
+  const uint64_t cap = so.frontier_capacity > 0 ? (uint64_t)so.frontier_capacity : (64ull << 20);
+  for (int k = 0; k < 2; k++) {
+    Lane &L = s->lanes[k];
+    L.kind = k == 0 ? KIND_BFS : KIND_REACH;
+    L.cap = std::min<uint64_t>(cap, 0x7FFFFFFFull);
+    L.slots.assign(so.max_slots, nullptr);
+    for (int i = 0; i < 2 && !rc; i++) {
+      rc = grow(L.fv[i], 4 * L.cap);
+      if (!rc) rc = grow(L.fq[i], 4 * L.cap);
+      if (!rc) rc = grow(L.fval[i], 8 * L.cap);
+    }
+    if (!rc) rc = grow(L.ctl, sizeof(Ctl));
+    if (!rc) rc = grow(L.qi, sizeof(QInfo) * so.max_slots);
+    if (!rc) rc = grow(L.qword, sizeof(int64_t) * (so.max_slots + 1));
+    if (!rc) rc = grow(L.counts, 4 * (size_t)so.max_slots);
+    if (!rc) rc = grow(L.dany, 4 * (size_t)so.max_slots);
+    if (!rc) rc = grow_host(L.h_ctl, sizeof(Ctl));
+    if (!rc) rc = grow_host(L.h_counts, 4 * (size_t)so.max_slots);
+    if (!rc) rc = grow_host(L.h_dany, 4 * (size_t)so.max_slots);
+    if (!rc) rc = vgc_geometry(L.kind, true, s->vopts, L.lg);
+    if (rc) {
+      delete s;
+      return rc;
+    }
+  }
+  try {
+    s->thr = std::thread([s] { s->loop(); });
+  } catch (...) {
+    delete s;
+    return PASGAL_ENOMEM;
+  }
+  *out = s;
+  return PASGAL_OK;
+}
+
+int pasgal_server_add_graph(pasgal_server *s, const pasgal_csr *g, int32_t *graph_id) {
+  if (!s || !csr_valid(g) || !graph_id) return PASGAL_EINVAL;
+  std::lock_guard<std::mutex> gl(s->gpu_mu);
+  const int64_t n2 = (int64_t)s->n_total + g->n, m2 = (int64_t)s->m_total + g->m;
+  if (n2 >= 0x7FFFFFFFLL || m2 >= 0x7FFFFFFFLL) return PASGAL_ECAPACITY;
+  {  // no request may be queued or resident while the packed CSR moves
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->inflight || s->lanes[0].active || s->lanes[1].active) return PASGAL_EAGAIN;
+  }
+  DBuf noff, ntgt;
+  int rc = grow(noff, 4 * (size_t)(n2 + 1));
+  if (!rc) rc = grow(ntgt, 4 * (size_t)std::max<int64_t>(m2, 1));
+  if (rc) {
+    free_buf(noff);
+    free_buf(ntgt);
+    return rc;
+  }
+  hipStream_t st = s->stream;
+  hipError_t e = hipSuccess;
+  if (s->n_total > 0) {
+    e = hipMemcpyAsync(noff.p, s->off.p, 4 * (size_t)s->n_total, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && s->m_total > 0)
+      e = hipMemcpyAsync(ntgt.p, s->tgt.p, 4 * (size_t)s->m_total, hipMemcpyDeviceToDevice, st);
+  }
+  if (e == hipSuccess)
+    e = launch_add_const((int32_t *)noff.p + s->n_total, g->offsets, (int64_t)g->n + 1, s->m_total, st);
+  if (e == hipSuccess && g->m > 0)
+    e = launch_add_const((int32_t *)ntgt.p + s->m_total, g->targets, g->m, s->n_total, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    free_buf(noff);
+    free_buf(ntgt);
+    return hip_fail(e);
+  }
+  free_buf(s->off);
+  free_buf(s->tgt);
+  s->off = noff;
+  s->tgt = ntgt;
+  s->n_total = (int32_t)n2;
+  s->m_total = (int32_t)m2;
+  std::lock_guard<std::mutex> gm(s->graph_mu);
+  s->vbase.push_back((int32_t)n2);
+  s->ebase.push_back((int32_t)m2);
+  *graph_id = (int32_t)s->vbase.size() - 2;
+  return PASGAL_OK;
+}
+
+int pasgal_server_submit(pasgal_server *s, const pasgal_request *req, int64_t *id) {
+  if (!s || !req || !id) return PASGAL_EINVAL;
+  if (req->kind != PASGAL_REQ_BFS && req->kind != PASGAL_REQ_REACH) return PASGAL_EINVAL;
+  int32_t nv = 0, vb = 0;
+  {
+    std::lock_guard<std::mutex> gm(s->graph_mu);
+    const int32_t ng = (int32_t)s->vbase.size() - 1;
+    if (req->graph < 0 || req->graph >= ng) return PASGAL_ENOTFOUND;
+    vb = s->vbase[req->graph];
+    nv = s->vbase[req->graph + 1] - vb;
+  }
+  if (req->nsources < 1 || req->nsources > 64 || (req->kind == PASGAL_REQ_BFS && req->nsources != 1))
+    return PASGAL_EINVAL;
+  for (int i = 0; i < req->nsources; i++)
+    if (req->sources[i] < 0 || req->sources[i] >= nv) return PASGAL_EINVAL;
+  Req *r = new (std::nothrow) Req();
+  if (!r) return PASGAL_ENOMEM;
+  r->r = *req;
+  r->vbase = vb;
+  r->nv = nv;
+  r->t_submit = now_ms();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->state_bytes(r) > s->opts.memory_budget) {
+      delete r;
+      return PASGAL_ECAPACITY;
+    }
+    if (s->submitted.size() >= 1u << 20) {
+      delete r;
+      return PASGAL_EAGAIN;
+    }
+    r->id = s->next_id++;
+    s->submitted.push_back(r);
+    s->inflight++;
+    *id = r->id;
+  }
+  s->cv.notify_all();
+  return PASGAL_OK;
+}
+
+int pasgal_server_poll(pasgal_server *s, pasgal_completion *out, int32_t max, int32_t *count) {
+  if (!s || !count || (max > 0 && !out)) return PASGAL_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  int32_t c = 0;
+  while (c < max && !s->done.empty()) {
+    out[c++] = s->done.front();
+    s->done.pop_front();
+  }
+  *count = c;
+  return PASGAL_OK;
+}
+
+int pasgal_server_drain(pasgal_server *s, int32_t timeout_ms) {
+  if (!s) return PASGAL_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  const bool ok = s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms > 0 ? timeout_ms : 60000),
+                                      [&] { return s->inflight == 0; });
+  return ok ? PASGAL_OK : PASGAL_ETIMEOUT;
+}
+
+int pasgal_server_load(pasgal_server *s, int32_t *queued, int32_t *active, int64_t *bytes_in_use) {
+  if (!s) return PASGAL_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (queued) *queued = (int32_t)s->submitted.size();
+  if (active) *active = s->lanes[0].active + s->lanes[1].active;
+  if (bytes_in_use) *bytes_in_use = s->alloc.used;
+  return PASGAL_OK;
+}
+
+void pasgal_server_destroy(pasgal_server *s) { delete s; }
+
+}  // extern "C"

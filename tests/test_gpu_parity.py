@@ -1,0 +1,360 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every traversal result has exactly one correct value (hop distance / the
+reachable set), so the bar is bit-exact equality on every case, for every
+schedule parameter (tau, workgroup size, workgroups per CU, frontier
+capacity down to a size that forces the overflow path).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    sys.stdout.write(f"[case] {msg}\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pg():
+    import paper_2404_17101_amd as pg_
+    pg_.load()
+    assert torch.cuda.is_available()
+    return pg_
+
+
+def dev(pg, g):
+    return pg.DeviceGraph.from_graph(g)
+
+
+def np_dist(t):
+    return t.cpu().numpy().astype(np.int32)
+
+
+def np_mask(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+# ------------------------------------------------------------------ BFS ---
+
+def test_c1_grid_plain_and_vgc_manhattan(pg):
+    """256x256 grid from vertex 0: dist = r + c (511 levels)."""
+    g = gg.grid(256, 256)
+    d = dev(pg, g)
+    r, c = np.divmod(np.arange(g.n), 256)
+    exp = (r + c).astype(np.int32)
+    _say("c1 plain")
+    got, st = pg.bfs(d, 0, mode="plain", stats=True)
+    assert np.array_equal(np_dist(got), exp)
+    assert st["rounds"] == 511
+    for tau in [1, 16, 64, 256, 1024, 4096]:
+        _say(f"c1 vgc tau={tau}")
+        got, st = pg.bfs(d, 0, tau=tau, stats=True)
+        assert np.array_equal(np_dist(got), exp), tau
+        if tau == 1:
+            assert st["rounds"] == 511
+        else:
+            assert st["rounds"] < 511
+
+
+@pytest.mark.parametrize("wg,bpc", [(64, 1), (256, 2), (512, 1), (1024, 1), (1024, 2)])
+def test_bfs_launch_shapes(pg, wg, bpc):
+    g = gg.knn(20000, 5, 2)
+    d = dev(pg, g)
+    for s in gg.sources(g, 3, 1002):
+        _say(f"knn20k wg={wg} bpc={bpc} src={s}")
+        exp = oracle.bfs(g, int(s))
+        got = pg.bfs(d, int(s), tau=256, wg_size=wg, blocks_per_cu=bpc)
+        assert np.array_equal(np_dist(got), exp)
+
+
+@pytest.mark.parametrize("cap", [64, 200, 1000])
+def test_bfs_tiny_frontier_forces_overflow_path(pg, cap):
+    g = gg.road(128, 3)
+    d = dev(pg, g)
+    overflowed = 0
+    for s in gg.sources(g, 2, 7):
+        _say(f"road128 cap={cap} src={s}")
+        exp = oracle.bfs(g, int(s))
+        for tau in [1, 64, 1024]:
+            got, st = pg.bfs(d, int(s), tau=tau, frontier_capacity=cap, stats=True)
+            assert np.array_equal(np_dist(got), exp), (cap, tau)
+            overflowed += st["overflow"]
+    # the level-synchronous schedule (tau=1) of a 128x128 grid outgrows 64 and 200 entries
+    assert overflowed > 0 or cap >= 1000
+
+
+def test_bfs_families_and_degenerate(pg):
+    cases = [gg.simple("dchain", 3000), gg.simple("uchain", 1000), gg.simple("dcycle", 777),
+             gg.simple("complete", 90), gg.simple("star", 5000), gg.simple("empty", 100), gg.simple("empty", 1),
+             gg.grid(1, 1), gg.grid(1, 4097), gg.grid(3, 1000, torus=True), gg.random_graph(3000, 9000, 5)]
+    for g in cases:
+        d = dev(pg, g)
+        srcs = sorted(set([0, g.n - 1, g.n // 2]))
+        for s in srcs:
+            exp = oracle.bfs(g, s)
+            for mode, tau in [("plain", 0), ("vgc", 1), ("vgc", 64), ("vgc", 4096)]:
+                _say(f"{g.name} src={s} {mode} tau={tau}")
+                got = pg.bfs(d, s, mode=mode, tau=tau or 256)
+                assert np.array_equal(np_dist(got), exp), (g.name, s, mode, tau)
+
+
+def test_bfs_rmat_skewed_degrees(pg):
+    g = gg.rmat(14, 16, 5)
+    d = dev(pg, g)
+    for s in gg.sources(g, 3, 9, min_degree=1):
+        exp = oracle.bfs(g, int(s))
+        for tau in [1, 256]:
+            _say(f"rmat14 src={s} tau={tau}")
+            assert np.array_equal(np_dist(pg.bfs(d, int(s), tau=tau)), exp)
+        assert np.array_equal(np_dist(pg.bfs(d, int(s), mode="plain")), exp)
+
+
+def test_bfs_metamorphic_relabel_and_duplicates(pg):
+    g = gg.knn(5000, 5, 4, layout="draw")
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(g.n).astype(np.int32)  # new id of old vertex
+    inv = np.argsort(perm)
+    u = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    nu, nw = perm[u], perm[g.targets]
+    # duplicate every 4th arc and add self-loops
+    nu = np.concatenate([nu, nu[::4], np.arange(g.n)])
+    nw = np.concatenate([nw, nw[::4], np.arange(g.n)])
+    order = np.lexsort((nw, nu))
+    off = np.zeros(g.n + 1, dtype=np.int64)
+    np.add.at(off, nu + 1, 1)
+    g2 = gg.Graph(np.cumsum(off).astype(np.int32), nw[order].astype(np.int32))
+    d1, d2 = dev(pg, g), dev(pg, g2)
+    for s in [0, 17, 4999]:
+        a = np_dist(pg.bfs(d1, s))
+        b = np_dist(pg.bfs(d2, int(perm[s])))
+        assert np.array_equal(a, b[perm]), s
+        assert np.array_equal(a, oracle.bfs(g, s))
+    _ = inv
+
+
+def test_bfs_repeatable_across_schedules(pg):
+    """Schedules change, the result does not (grid-size perturbation)."""
+    g = gg.knn(30000, 5, 8)
+    d = dev(pg, g)
+    exp = oracle.bfs(g, 123)
+    for wg in [64, 128, 192, 256, 320, 448, 640, 1024]:
+        for tau in [3, 17, 100]:
+            got = pg.bfs(d, 123, tau=tau, wg_size=wg)
+            assert np.array_equal(np_dist(got), exp), (wg, tau)
+
+
+# ---------------------------------------------------------------- reach ---
+
+@pytest.mark.parametrize("k", [1, 5, 64, 70, 130])
+def test_reach_matches_oracle(pg, k):
+    g = gg.road(96, 11)
+    d = dev(pg, g)
+    srcs = gg.sources(g, k, 1003 + k)
+    exp = oracle.reach(g, srcs)
+    for mode, tau, cap in [("plain", 256, 0), ("vgc", 1, 0), ("vgc", 256, 0), ("vgc", 4096, 0), ("vgc", 64, 100)]:
+        _say(f"reach road96 k={k} {mode} tau={tau} cap={cap}")
+        got = pg.reach(d, srcs, mode=mode, tau=tau, frontier_capacity=cap)
+        assert np.array_equal(np_mask(got), exp), (k, mode, tau, cap)
+
+
+def test_reach_duplicate_sources_and_families(pg):
+    for g in [gg.simple("dchain", 2000), gg.simple("dcycle", 300), gg.simple("empty", 50), gg.knn(3000, 5, 1)]:
+        d = dev(pg, g)
+        srcs = np.array([0, g.n - 1, 0, g.n // 3, g.n - 1], dtype=np.int32)
+        exp = oracle.reach(g, srcs)
+        for mode in ["plain", "vgc"]:
+            _say(f"reach {g.name} {mode}")
+            assert np.array_equal(np_mask(pg.reach(d, srcs, mode=mode)), exp)
+
+
+def test_transpose_and_backward_reach_scc_partition(pg):
+    g = gg.road(128, 3)
+    d = dev(pg, g)
+    _say("transpose road128")
+    t = pg.transpose(d)
+    t_off, t_tgt = oracle.transpose(g)
+    got_off = t.offsets.cpu().numpy()
+    got_tgt = t.targets.cpu().numpy()
+    assert np.array_equal(got_off, t_off)
+    for v in range(0, g.n, 97):
+        assert np.array_equal(np.sort(got_tgt[got_off[v]:got_off[v + 1]]), t_tgt[t_off[v]:t_off[v + 1]])
+    assert np.array_equal(np.sort(got_tgt), np.sort(t_tgt))
+    gt = gg.Graph(t_off, t_tgt)
+    pivots = gg.sources(g, 64, 1003)
+    fw = np_mask(pg.reach(d, pivots))
+    bw = np_mask(pg.reach(t, pivots))
+    assert np.array_equal(fw, oracle.reach(g, pivots))
+    assert np.array_equal(bw, oracle.reach(gt, pivots))
+    comp = oracle.scc(g)
+    for i, p in enumerate(pivots):
+        both = ((fw[:, 0] & bw[:, 0]) >> np.uint64(i)) & np.uint64(1)
+        assert np.array_equal(both.astype(bool), comp == comp[p]), i
+
+
+def test_transpose_degenerate(pg):
+    for g in [gg.simple("empty", 10), gg.simple("star", 3000), gg.rmat(12, 8, 1)]:
+        d = dev(pg, g)
+        t = pg.transpose(d)
+        t_off, t_tgt = oracle.transpose(g)
+        assert np.array_equal(t.offsets.cpu().numpy(), t_off)
+        got = t.targets.cpu().numpy()
+        for v in range(g.n):
+            assert np.array_equal(np.sort(got[t_off[v]:t_off[v + 1]]), t_tgt[t_off[v]:t_off[v + 1]])
+
+
+# --------------------------------------------------------------- errors ---
+
+def test_error_paths_leave_outputs_untouched(pg):
+    import ctypes
+    from paper_2404_17101_amd import _lib as L
+    lib = pg.load()
+    g = gg.grid(8, 8)
+    d = dev(pg, g)
+    out = torch.full((g.n,), 12345, dtype=torch.int32, device="cuda")
+    csr = d.csr()
+    assert lib.pasgal_bfs(ctypes.byref(csr), -1, out.data_ptr()) == -1
+    assert lib.pasgal_bfs(ctypes.byref(csr), g.n, out.data_ptr()) == -1
+    assert lib.pasgal_bfs(ctypes.byref(csr), 0, None) == -1
+    assert lib.pasgal_bfs(None, 0, out.data_ptr()) == -1
+    bad = L.Csr(0, 0, csr.offsets, csr.targets)
+    assert lib.pasgal_bfs(ctypes.byref(bad), 0, out.data_ptr()) == -1
+    src = (ctypes.c_int32 * 2)(0, 64)
+    lab = torch.full((g.n,), 7, dtype=torch.int64, device="cuda")
+    assert lib.pasgal_reach(ctypes.byref(csr), src, 2, lab.data_ptr()) == -1
+    assert lib.pasgal_reach(ctypes.byref(csr), src, 0, lab.data_ptr()) == -1
+    torch.cuda.synchronize()
+    assert int((out != 12345).sum()) == 0
+    assert int((lab != 7).sum()) == 0
+    # malformed CSR is caught with the validate flag
+    off = g.offsets.copy()
+    tgt = g.targets.copy()
+    tgt[5] = g.n + 3
+    bad_g = pg.DeviceGraph.from_numpy(off, tgt)
+    assert not pg.validate(bad_g)
+    assert pg.validate(d)
+    with pytest.raises(pg.PasgalError) as ei:
+        pg.bfs(bad_g, 0, validate=True)
+    assert ei.value.code == -4
+    off2 = g.offsets.copy()
+    off2[3] = off2[4] + 1
+    assert not pg.validate(pg.DeviceGraph.from_numpy(off2, g.targets))
+
+
+# ---------------------------------------------------------------- batch ---
+
+def _batch_inputs(pg, graphs, per_graph, seed):
+    packed = gg.pack(graphs)
+    pd = pg.DeviceGraph.from_numpy(packed.offsets, packed.targets)
+    qg, qs, qo = [], [], []
+    off = 0
+    for gi, g in enumerate(graphs):
+        srcs = gg.sources(g, min(per_graph, g.n), seed + gi)
+        for s in srcs:
+            qg.append(gi)
+            qs.append(int(s))
+            qo.append(off)
+            off += g.n
+    dist = torch.empty(off, dtype=torch.int32, device="cuda")
+    return packed, pd, np.array(qg), np.array(qs), np.array(qo, dtype=np.int64), dist
+
+
+def test_batch_matches_single_and_oracle(pg):
+    graphs = [gg.grid(40, 70), gg.knn(3000, 5, 3), gg.road(50, 2), gg.simple("dchain", 500), gg.grid(1, 1),
+              gg.knn(800, 5, 9), gg.rmat(10, 8, 3)]
+    packed, pd, qg, qs, qo, dist = _batch_inputs(pg, graphs, 3, 100)
+    for cap in [0, 300]:
+        _say(f"batch cap={cap}")
+        b = pg.Batch(pd, packed.vbase, qg, qs, qo, dist, tau=64, frontier_capacity=cap)
+        for rep in range(3):
+            dist.fill_(-7)
+            b.run()
+            got = dist.cpu().numpy()
+            for j in range(len(qg)):
+                g = graphs[qg[j]]
+                exp = oracle.bfs(g, int(qs[j]))
+                assert np.array_equal(got[qo[j]:qo[j] + g.n], exp), (cap, rep, j)
+            # eager work between graph replays
+            single = np_dist(pg.bfs(dev(pg, graphs[0]), int(qs[0])))
+            assert np.array_equal(single, got[qo[0]:qo[0] + graphs[0].n])
+        b.close()
+
+
+def test_batch_autotune(pg):
+    graphs = [gg.grid(30, 30), gg.knn(2000, 5, 5)]
+    packed, pd, qg, qs, qo, dist = _batch_inputs(pg, graphs, 4, 7)
+    b = pg.Batch(pd, packed.vbase, qg, qs, qo, dist, autotune=True)
+    cfg = b.config()
+    assert cfg["tau"] in (16, 64, 256, 1024, 4096)
+    b.run()
+    got = dist.cpu().numpy()
+    for j in range(len(qg)):
+        g = graphs[qg[j]]
+        assert np.array_equal(got[qo[j]:qo[j] + g.n], oracle.bfs(g, int(qs[j])))
+    b.close()
+
+
+# --------------------------------------------------------------- server ---
+
+def test_server_results_equal_alone_and_in_mix(pg):
+    g1, g2 = gg.grid(60, 60), gg.rmat(11, 8, 2)
+    srv = pg.Server(max_slots=8, slice_rounds=4, tau=64)
+    d1, d2 = dev(pg, g1), dev(pg, g2)
+    ids = [srv.add_graph(d1), srv.add_graph(d2)]
+    reqs = []
+    for i in range(24):
+        gid = ids[i % 2]
+        g = g1 if gid == ids[0] else g2
+        kind = "bfs" if i % 3 else "reach"
+        if kind == "bfs":
+            srcs = [int(gg.sources(g, 1, 500 + i, min_degree=1)[0])]
+            out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        else:
+            srcs = list(gg.sources(g, 1 + i % 5, 600 + i, min_degree=1))
+            out = torch.empty(g.n, dtype=torch.int64, device="cuda")
+        rid = srv.submit(gid, kind, srcs, out=out, tag=i)
+        assert rid is not None
+        reqs.append((rid, g, kind, srcs, out))
+    srv.drain(60000)
+    comps = {c["id"]: c for c in srv.poll(1000)}
+    assert len(comps) == len(reqs)
+    for rid, g, kind, srcs, out in reqs:
+        assert comps[rid]["status"] == 0
+        if kind == "bfs":
+            assert np.array_equal(np_dist(out), oracle.bfs(g, srcs[0])), rid
+        else:
+            assert np.array_equal(np_mask(out)[:, None] if out.dim() == 1 else np_mask(out),
+                                  oracle.reach(g, srcs)), rid
+    srv.close()
+
+
+def test_server_tiny_budget_queues_admission(pg):
+    g = gg.grid(100, 100)
+    per_req = 4 * g.n + 4 * ((g.n + 31) // 32) + 512
+    srv = pg.Server(memory_budget=per_req + per_req // 2, max_slots=16, slice_rounds=8)
+    gid = srv.add_graph(dev(pg, g))
+    outs = []
+    for i in range(6):
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        s = int(gg.sources(g, 1, 40 + i)[0])
+        assert srv.submit(gid, "bfs", [s], out=out) is not None
+        outs.append((s, out))
+    srv.drain(60000)
+    comps = srv.poll(100)
+    assert len(comps) == 6 and all(c["status"] == 0 for c in comps)
+    # only one request fits at a time: admissions are serialized
+    comps.sort(key=lambda c: c["t_admit_ms"])
+    for a, b in zip(comps, comps[1:]):
+        assert b["t_admit_ms"] >= a["t_done_ms"] - 5.0
+    for s, out in outs:
+        assert np.array_equal(np_dist(out), oracle.bfs(g, s))
+    srv.close()
