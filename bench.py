@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Benchmark: VGC BFS + reachability on one MI355X.
+
+Workload (the headline configuration): a directed 5-NN graph of 10^7 seeded
+uniform points in [0,1)^2 (50,000,000 arcs, int32 CSR, Z-order vertex
+layout) and 16 seeded random sources. One step is the whole job for that
+batch of sources, inputs resident in HBM:
+  * 16 BFS queries (one per source) in one batched persistent VGC launch
+    (pasgal_batch_run, hipGraph-captured), and
+  * reachability from the 16 sources in one VGC launch with 16-bit masks
+    (pasgal_reach_ex, k = 16).
+value = traversed edges per second (GTEPS): per query, the arcs whose tail the
+source reaches (BFS and reach alike), summed over the 32 queries, over the
+wall time of the timed steps.
+
+The JSON line also carries
+  roofline      dominant kernel: the multi-query persistent VGC BFS kernel.
+                achieved = algorithmic bytes of one launch (16 B per reached
+                vertex + 8 B per arc of a reached vertex, per query) / the
+                launch's duration (HIP events recorded around the kernel on
+                its own stream, averaged over the timed steps); peak 8 TB/s;
+                traffic from committed rocprofv3 counter runs when they were
+                taken on the same kernel source and setting, else null.
+  cpu_baseline  the CPU oracle (sequential queue BFS / DFS reach, one host
+                thread) on a bounded sample of the same queries.
+  extras        single-source calls: plain (one launch per BFS level) vs VGC
+                per tau, sequential 16-query totals, and the reach kernel's
+                own roofline figure.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--tau T] [--window W]
+                [--layout morton|draw] [--no-extras] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "vgc_bfs_batched16_knn10m_counters.txt")
+
+
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kern.h"):
+        with open(os.path.join(ROOT, "paper_2404_17101_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tau", type=int, default=1024)
+    ap.add_argument("--window", type=int, default=32)
+    ap.add_argument("--wg", type=int, default=1024)
+    ap.add_argument("--bpc", type=int, default=1)
+    ap.add_argument("--points", type=int, default=10_000_000)
+    ap.add_argument("--sources", type=int, default=16)
+    ap.add_argument("--layout", default="morton", choices=["morton", "draw"])
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 3 times (counter calibration for rocprofv3 runs)")
+    args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_dispatch": nbytes,
+                          "bytes_written_per_dispatch": nbytes, "dispatches": 3}), flush=True)
+        return
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): every configuration fits one "
+              f"MI355X, and the multi-GPU partitioning exists as design only.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import graphgen as gg
+    import paper_2404_17101_amd as pg
+
+    pg.load()  # raises if the HIP library is missing: there is no fallback path
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    t0 = time.time()
+    g = gg.knn(args.points, 5, 2, layout=args.layout)
+    srcs = [int(s) for s in gg.sources(g, args.sources, 1002)]
+    log(f"generated knn n={g.n} m={g.m} in {time.time() - t0:.1f}s ({gg.threads()} threads)")
+    d = pg.DeviceGraph.from_graph(g)
+    n, nq = g.n, len(srcs)
+    stream = torch.cuda.current_stream()
+    vgc = dict(tau=args.tau, window=args.window, wg_size=args.wg, blocks_per_cu=args.bpc, stream=stream)
+
+    # outputs: 16 distance arrays (one batched launch) and one 16-bit mask word per vertex
+    dist16 = torch.empty(n * nq, dtype=torch.int32, device="cuda")
+    mask = torch.empty((n, 1), dtype=torch.int64, device="cuda")
+    vb = np.array([0, n], dtype=np.int32)
+    batch = pg.Batch(d, vb, np.zeros(nq, np.int32), np.array(srcs, np.int32), np.arange(nq, dtype=np.int64) * n,
+                     dist16, **vgc)
+    torch.cuda.synchronize()
+
+    def step(rec=None):
+        bst = batch.run()
+        _, rst = pg.reach(d, srcs, label_out=mask, stats=True, **vgc)
+        if rec is not None:
+            rec.append((bst, rst))
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+
+    # work per query from the results (reached vertices, arcs out of them)
+    deg = np.diff(g.offsets).astype(np.int64)
+    dd = dist16.view(nq, n).cpu().numpy()
+    mk = mask.cpu().numpy().view(np.uint64)[:, 0]
+    bfs_nr, bfs_mr, rch_mr = [], [], []
+    for i in range(nq):
+        r = dd[i] >= 0
+        bfs_nr.append(int(r.sum()))
+        bfs_mr.append(int(deg[r].sum()))
+        rr = ((mk >> np.uint64(i)) & np.uint64(1)).astype(bool)
+        rch_mr.append(int(deg[rr].sum()))
+    edges_per_step = sum(bfs_mr) + sum(rch_mr)
+
+    rec = []
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - ta
+    gteps = edges_per_step * args.steps / wall / 1e9
+
+    # roofline of the batched BFS kernel
+    alg_bytes = float(sum(16 * a + 8 * b for a, b in zip(bfs_nr, bfs_mr)))
+    kms = float(np.mean([b["kernel_ms"] for b, _ in rec]))
+    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    traffic, note = None, None
+    if os.path.exists(PROFILE_COUNTERS):
+        with open(PROFILE_COUNTERS) as f:
+            pc = json.load(f)
+        if (pc.get("kernel_hash") == kernel_source_hash() and pc.get("layout") == args.layout
+                and pc.get("tau") == args.tau and pc.get("window") == args.window):
+            traffic = pc.get("hbm_bytes_per_launch")
+        else:
+            note = "committed counter profile was taken on a different kernel source or setting"
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "kernel": "vgc_kernel<BFS, multi-query>", "kernel_ms_avg": round(kms, 4),
+                "alg_bytes_per_launch": int(alg_bytes)}
+    if note:
+        roofline["note"] = note
+    rch_alg = float(sum(20 * int(((mk >> np.uint64(i)) & np.uint64(1)).astype(bool).sum()) + 12 * rch_mr[i]
+                        for i in range(nq)))
+    rkms = float(np.mean([r["kernel_ms"] for _, r in rec]))
+    detail = {
+        "bfs_batched_ms": float(np.mean([b["device_ms"] for b, _ in rec])),
+        "bfs_kernel_ms": kms,
+        "bfs_rounds": float(np.mean([b["rounds"] for b, _ in rec])),
+        "bfs_expansions_per_reached": float(np.mean([b["expansions"] for b, _ in rec]) / sum(bfs_nr)),
+        "reach16_kernel_ms": rkms,
+        "reach16_rounds": float(np.mean([r["rounds"] for _, r in rec])),
+        "reach16_roofline_frac": round(rch_alg / (rkms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+        "reached_vertices_avg": float(np.mean(bfs_nr)),
+        "reached_arcs_avg": float(np.mean(bfs_mr)),
+        "queries_per_s": round(2 * nq * args.steps / wall, 2),
+    }
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        edges, calls, used = 0, 0, 0.0
+        for i, s in enumerate(srcs):
+            if used > args.cpu_seconds:
+                break
+            a = time.perf_counter()
+            oracle.bfs(g, s)
+            oracle.reach(g, [s])
+            used += time.perf_counter() - a
+            edges += bfs_mr[i] + rch_mr[i]
+            calls += 2
+        cpu = {"value": round(edges / used / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": f"{calls} of the {2 * nq} queries (BFS and reach from the first {calls // 2} sources) "
+                         f"in {used:.1f} s on one host thread"}
+
+    extras = {}
+    if not args.no_extras:
+        dist = torch.empty(n, dtype=torch.int32, device="cuda")
+        m1 = torch.empty((n, 1), dtype=torch.int64, device="cuda")
+        sub = srcs[:4]
+        e_sub = sum(bfs_mr[:4])
+        for label, kw in [("plain", dict(mode="plain")), ("tau1", dict(tau=1, window=0)),
+                          ("tau64", dict(tau=64, window=0)), ("tau256", dict(tau=256, window=0)),
+                          ("tau1024", dict(tau=1024, window=0)), ("tau4096", dict(tau=4096, window=0)),
+                          ("tau1024_window32", dict(tau=1024, window=32))]:
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            rounds, infl = [], []
+            for i, s in enumerate(sub):
+                _, st = pg.bfs(d, s, dist_out=dist, stats=True, stream=stream, **kw)
+                rounds.append(st["rounds"])
+                infl.append(st["expansions"] / bfs_nr[i])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - a
+            extras[f"bfs_single_{label}"] = {"gteps": round(e_sub / el / 1e9, 3),
+                                             "ms_per_query": round(el / len(sub) * 1e3, 3),
+                                             "rounds": float(np.mean(rounds)),
+                                             "expansions_per_reached": round(float(np.mean(infl)), 3)}
+        for label, kw in [("plain", dict(mode="plain")), ("tau256", dict(tau=256)), ("tau1024", dict(tau=1024)),
+                          ("tau4096", dict(tau=4096))]:
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for s in sub:
+                pg.reach(d, [s], label_out=m1, stream=stream, **kw)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - a
+            extras[f"reach_single_{label}"] = {"gteps": round(sum(rch_mr[:4]) / el / 1e9, 3),
+                                               "ms_per_query": round(el / len(sub) * 1e3, 3)}
+        plain_ms = extras["bfs_single_plain"]["ms_per_query"] + extras["reach_single_plain"]["ms_per_query"]
+        extras["job_plain_sequential_estimate"] = {
+            "gteps": round(edges_per_step / (plain_ms * nq * 1e-3) / 1e9, 3),
+            "note": "16 x (plain BFS + plain reach) per-query launches, from the 4-source means above"}
+
+    out = {
+        "metric": "GTEPS (16-source BFS + reachability job, VGC; directed 5-NN of 1e7 uniform points)",
+        "value": round(gteps, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"knn5 n={n} m={g.m} points uniform in [0,1)^2 (seed 2, {args.layout} layout), "
+                               f"{nq} sources (seed 1002); step = 16 BFS in one batched launch + "
+                               f"16-source reach in one launch",
+                   "tau": args.tau, "window": args.window, "wg_size": args.wg, "blocks_per_cu": args.bpc},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": detail,
+        "extras": extras,
+    }
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

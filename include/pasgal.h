@@ -65,11 +65,15 @@ typedef struct pasgal_csr {
 
 #define PASGAL_FLAG_VALIDATE 1u /* check the CSR on the device first (O(n+m)) */
 #define PASGAL_FLAG_ASYNC 2u    /* do not synchronize the stream before returning (VGC mode only) */
+#define PASGAL_FLAG_PREFETCH 4u   /* VGC: local-queue entries carry their vertex's arc range, loaded while the
+                                      relaxing atomic is in flight (default: loaded when the entry is expanded) */
+#define PASGAL_FLAG_TEST_FIRST 8u  /* VGC: read a target's state before the atomic and skip the atomic when
+                                      the relaxation cannot change it */
 
 typedef struct pasgal_opts {
   int32_t mode;              /* PASGAL_MODE_VGC or PASGAL_MODE_PLAIN */
   int32_t tau;               /* VGC: vertices a local search expands per frontier vertex before it
-                                publishes what is left (the paper's tau); <= 0 selects 256. tau = 1
+                                publishes what is left (the paper's tau); <= 0 selects 1024. tau = 1
                                 makes every round one BFS level inside the persistent kernel. */
   int32_t wg_size;           /* threads per workgroup: 64..1024, multiple of 64; <= 0 selects 1024 */
   int32_t blocks_per_cu;     /* persistent workgroups per compute unit; <= 0 selects 1 */
@@ -79,6 +83,11 @@ typedef struct pasgal_opts {
   uint32_t flags;            /* PASGAL_FLAG_* */
   int32_t timeout_ms;        /* bound on any device-side wait; <= 0 selects 20000 */
   void *stream;              /* hipStream_t to run on; NULL = the null stream */
+  int32_t window;            /* BFS, VGC: round r expands only distances below (r + 1) * window; larger
+                                ones wait in the frontier for their round (the paper's remedy of keeping
+                                unready vertices out of the current round). 0 selects 32; < 0 = no window. */
+  int32_t min_chunk;         /* VGC: frontier entries one wavefront takes at least per local search
+                                (1..64; <= 0 selects 1) */
 } pasgal_opts;
 
 /* Counters of one call (schedule dependent, never part of the result). */
@@ -91,7 +100,8 @@ typedef struct pasgal_stats {
   int64_t overflow;       /* entries that went to the dirty bitmap instead */
   int64_t stale;          /* popped entries skipped because a better value was already known */
   int64_t max_frontier;   /* largest global frontier */
-  double device_ms;       /* traversal time on the stream (events around the launches) */
+  double device_ms;       /* time on the stream from the state fill to the end of the traversal */
+  double kernel_ms;       /* time of the traversal launches alone (VGC: the persistent kernel) */
 } pasgal_stats;
 
 void pasgal_opts_default(pasgal_opts *opts);
@@ -181,6 +191,8 @@ typedef struct pasgal_server_opts {
   int32_t blocks_per_cu;   /* <= 0 selects 1 */
   int64_t frontier_capacity; /* per kind; <= 0 selects 64M entries */
   int32_t timeout_ms;
+  int32_t window;          /* BFS distance window per round (see pasgal_opts.window); < 0 selects none,
+                              0 selects 32 */
 } pasgal_server_opts;
 
 #define PASGAL_REQ_BFS 0

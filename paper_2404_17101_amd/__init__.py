@@ -86,8 +86,9 @@ def _stream_ptr(stream) -> int:
     return int(s.cuda_stream)
 
 
-def _opts(mode="vgc", tau=256, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
-          stream=None, asynchronous=False) -> L.Opts:
+def _opts(mode="vgc", tau=1024, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
+          stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=False, test_first=False) -> L.Opts:
+    """window: BFS distance window per round (0 or negative = none)."""
     o = L.Opts()
     L.load().pasgal_opts_default(ctypes.byref(o))
     o.mode = {"vgc": L.MODE_VGC, "plain": L.MODE_PLAIN}[mode]
@@ -95,9 +96,12 @@ def _opts(mode="vgc", tau=256, wg_size=1024, blocks_per_cu=1, frontier_capacity=
     o.wg_size = int(wg_size)
     o.blocks_per_cu = int(blocks_per_cu)
     o.frontier_capacity = int(frontier_capacity)
-    o.flags = (L.FLAG_VALIDATE if validate else 0) | (L.FLAG_ASYNC if asynchronous else 0)
+    o.flags = ((L.FLAG_VALIDATE if validate else 0) | (L.FLAG_ASYNC if asynchronous else 0) |
+               (L.FLAG_PREFETCH if prefetch else 0) | (L.FLAG_TEST_FIRST if test_first else 0))
     o.timeout_ms = int(timeout_ms)
     o.stream = _stream_ptr(stream)
+    o.window = int(window) if int(window) > 0 else -1
+    o.min_chunk = int(min_chunk)
     return o
 
 
@@ -216,9 +220,10 @@ class Server:
     pasgal_server_* in include/pasgal.h)."""
 
     def __init__(self, memory_budget: int = 0, max_slots: int = 0, slice_rounds: int = 0, tau: int = 0,
-                 wg_size: int = 0, blocks_per_cu: int = 0, frontier_capacity: int = 0, timeout_ms: int = 0):
+                 wg_size: int = 0, blocks_per_cu: int = 0, frontier_capacity: int = 0, timeout_ms: int = 0,
+                 window: int = 0):
         so = L.ServerOpts(int(memory_budget), int(max_slots), int(slice_rounds), int(tau), int(wg_size),
-                          int(blocks_per_cu), int(frontier_capacity), int(timeout_ms))
+                          int(blocks_per_cu), int(frontier_capacity), int(timeout_ms), int(window))
         h = ctypes.c_void_p()
         _check(L.load().pasgal_server_create(ctypes.byref(so), ctypes.byref(h)), "pasgal_server_create")
         self._h = h

@@ -13,7 +13,7 @@ ERRORS = {
     -8: "ENOTFOUND",
 }
 MODE_VGC, MODE_PLAIN = 0, 1
-FLAG_VALIDATE, FLAG_ASYNC = 1, 2
+FLAG_VALIDATE, FLAG_ASYNC, FLAG_PREFETCH, FLAG_TEST_FIRST = 1, 2, 4, 8
 BATCH_AUTOTUNE = 1
 REQ_BFS, REQ_REACH = 0, 1
 
@@ -35,13 +35,15 @@ class Csr(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tau", ctypes.c_int32), ("wg_size", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("frontier_capacity", ctypes.c_int64),
-                ("flags", ctypes.c_uint32), ("timeout_ms", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("flags", ctypes.c_uint32), ("timeout_ms", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("window", ctypes.c_int32), ("min_chunk", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("expansions", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64),
                 ("relax_success", ctypes.c_int64), ("published", ctypes.c_int64), ("overflow", ctypes.c_int64),
-                ("stale", ctypes.c_int64), ("max_frontier", ctypes.c_int64), ("device_ms", ctypes.c_double)]
+                ("stale", ctypes.c_int64), ("max_frontier", ctypes.c_int64), ("device_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -57,7 +59,7 @@ class BatchDesc(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("slice_rounds", ctypes.c_int32),
                 ("tau", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("frontier_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_int32)]
+                ("frontier_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_int32), ("window", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

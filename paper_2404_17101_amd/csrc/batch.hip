@@ -34,7 +34,7 @@ struct pasgal_batch {
   HBuf h_ctl;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr;
   VgcArgs args{};
   bool coop_in_graph = false;
 
@@ -48,6 +48,8 @@ struct pasgal_batch {
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);
     if (evc) hipEventDestroy(evc);
+    if (evk0) hipEventDestroy(evk0);
+    if (evk1) hipEventDestroy(evk1);
     if (stream) hipStreamDestroy(stream);
   }
 
@@ -68,7 +70,10 @@ struct pasgal_batch {
     if ((e = launch_fill_u32((uint32_t *)dirty.p, (uint64_t)words, 0u, s)) != hipSuccess) return e;
     if ((e = launch_fill_u32((uint32_t *)ctl.p, sizeof(Ctl) / 4, 0u, s)) != hipSuccess) return e;
     if ((e = launch_seed(KIND_BFS, args, (const SeedEnt *)seeds.p, (uint32_t)nq, 0, 0, s)) != hipSuccess) return e;
-    if ((e = launch_vgc(KIND_BFS, true, args, lg.grid, lg.block, lg.lds, cooperative, s)) != hipSuccess) return e;
+    if ((e = hipEventRecord(evk0, s)) != hipSuccess) return e;
+    if ((e = launch_vgc(KIND_BFS, true, lg.pf, args, lg.grid, lg.block, lg.lds, cooperative, s)) != hipSuccess)
+      return e;
+    if ((e = hipEventRecord(evk1, s)) != hipSuccess) return e;
     return hipMemcpyAsync(h_ctl.p, ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s);
   }
 
@@ -79,6 +84,9 @@ struct pasgal_batch {
     args.tau = o.tau;
     args.ring_cap = lg.ring;
     args.stage_cap = lg.stage;
+    args.min_chunk = o.min_chunk;
+    args.window = o.window;
+    args.test_first = o.test_first ? 1u : 0u;
     args.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
     return PASGAL_OK;
   }
@@ -166,6 +174,8 @@ int pasgal_batch_create(const pasgal_batch_desc *d, const pasgal_opts *opts, uin
     qi[q].dbase = words;
     qi[q].vbase = d->vbase[g];
     qi[q].nv = nv;
+    qi[q].r0 = 0;
+    qi[q].pad = 0;
     qword[q] = words;
     words += (nv + 31) / 32;
     segoff[q] = o;
@@ -195,6 +205,7 @@ int pasgal_batch_create(const pasgal_batch_desc *d, const pasgal_opts *opts, uin
   hipError_t e;
   if ((e = hipEventCreate(&b->ev0)) != hipSuccess || (e = hipEventCreate(&b->ev1)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&b->evc, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreate(&b->evk0)) != hipSuccess || (e = hipEventCreate(&b->evk1)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) {
     delete b;
     return hip_fail(e);
@@ -252,6 +263,7 @@ int pasgal_batch_create(const pasgal_batch_desc *d, const pasgal_opts *opts, uin
   a.fr.cap = (uint32_t)b->cap;
   a.start_buf = 0;
   a.max_rounds = 0xFFFFFFFFu;
+  a.round_base = 0;
   a.ctl = (Ctl *)b->ctl.p;
 
   if (batch_flags & PASGAL_BATCH_AUTOTUNE) {
@@ -316,9 +328,14 @@ int pasgal_batch_run(pasgal_batch *b, pasgal_stats *st) {
   if (c.abort) return PASGAL_ETIMEOUT;
   if (st) {
     fill_stats_from_ctl(c, st, false);
-    float ms = 0;
+    float ms = 0, kms = 0;
     hipEventElapsedTime(&ms, b->ev0, b->ev1);
+    if (hipEventElapsedTime(&kms, b->evk0, b->evk1) != hipSuccess) {
+      (void)hipGetLastError();  // event nodes inside the graph are not timeable here: use the graph time
+      kms = ms;
+    }
     st->device_ms = ms;
+    st->kernel_ms = kms;
   }
   return PASGAL_OK;
 }

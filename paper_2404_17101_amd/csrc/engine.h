@@ -38,25 +38,30 @@ struct Workspace {
   DBuf ctl, fv[2], fq[2], fval[2], dirty, qi, qword, seeds, pf[2], stamp, tmp_state, tscratch, plain_src;
   uint32_t cap = 0;
   HBuf h_ctl, h_stage;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;
   ~Workspace();
 };
 
 struct Opts {
   int mode = PASGAL_MODE_VGC;
-  uint32_t tau = 256;
+  uint32_t tau = 1024;
   int wg = 1024;
   int bpc = 1;
   int64_t cap = 0;
   uint32_t flags = 0;
   int timeout_ms = 20000;
   hipStream_t stream = nullptr;
+  uint32_t window = 32;
+  uint32_t min_chunk = 1;
+  bool prefetch = false;
+  bool test_first = false;
 };
 
 struct LaunchGeom {
   int grid = 0, block = 0;
   size_t lds = 0;
   uint32_t ring = 0, stage = 0;
+  bool pf = false;
 };
 
 extern thread_local int g_last_hip;

@@ -110,6 +110,7 @@ Workspace::~Workspace() {
   free_hbuf(h_ctl);
   free_hbuf(h_stage);
   if (ev0) hipEventDestroy(ev0);
+  if (evk) hipEventDestroy(evk);
   if (ev1) hipEventDestroy(ev1);
 }
 
@@ -126,7 +127,8 @@ Workspace *workspace_for(hipStream_t s) {
   Workspace *w = new (std::nothrow) Workspace();
   if (!w) return nullptr;
   w->stream = s;
-  if (hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess) {
+  if (hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->evk) != hipSuccess ||
+      hipEventCreate(&w->ev1) != hipSuccess) {
     delete w;
     return nullptr;
   }
@@ -140,13 +142,17 @@ Opts resolve_opts(const pasgal_opts *o) {
   pasgal_opts_default(&d);
   if (!o) o = &d;
   r.mode = o->mode;
-  r.tau = o->tau > 0 ? (uint32_t)o->tau : 256u;
+  r.tau = o->tau > 0 ? (uint32_t)o->tau : 1024u;
   r.wg = o->wg_size > 0 ? o->wg_size : 1024;
   r.bpc = o->blocks_per_cu > 0 ? o->blocks_per_cu : 1;
   r.cap = o->frontier_capacity;
   r.flags = o->flags;
   r.timeout_ms = o->timeout_ms > 0 ? o->timeout_ms : 20000;
   r.stream = (hipStream_t)o->stream;
+  r.window = o->window > 0 ? (uint32_t)o->window : (o->window == 0 ? 32u : 0u);
+  r.min_chunk = o->min_chunk > 0 ? (uint32_t)std::min(o->min_chunk, 64) : 1u;
+  r.prefetch = (o->flags & PASGAL_FLAG_PREFETCH) != 0;
+  r.test_first = (o->flags & PASGAL_FLAG_TEST_FIRST) != 0;
   return r;
 }
 
@@ -155,6 +161,7 @@ bool opts_valid(const pasgal_opts *o) {
   if (o->mode != PASGAL_MODE_VGC && o->mode != PASGAL_MODE_PLAIN) return false;
   if (o->wg_size > 0 && (o->wg_size % 64 != 0 || o->wg_size > 1024)) return false;
   if (o->blocks_per_cu > 32) return false;
+  if (o->min_chunk > 64) return false;
   return true;
 }
 
@@ -169,14 +176,16 @@ int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   const size_t lds_cap_block = std::min<size_t>(di.lds_per_cu / (size_t)o.bpc, di.lds_per_block);
   // stage 128 entries; ring = largest power of two that fits
   const uint32_t S = 128;
+  const bool pf = o.prefetch;
   uint32_t Q = 4096;
-  while (Q > 64 && vgc_lds_bytes(kind, multi, waves, Q, S) + 256 > lds_cap_block) Q >>= 1;
-  if (vgc_lds_bytes(kind, multi, waves, Q, S) + 256 > lds_cap_block) return PASGAL_EINVAL;
+  while (Q > 64 && vgc_lds_bytes(kind, multi, pf, waves, Q, S) + 512 > lds_cap_block) Q >>= 1;
+  if (vgc_lds_bytes(kind, multi, pf, waves, Q, S) + 512 > lds_cap_block) return PASGAL_EINVAL;
   lg.ring = Q;
   lg.stage = S;
   lg.block = o.wg;
-  lg.lds = vgc_lds_bytes(kind, multi, waves, Q, S);
-  const void *fn = vgc_kernel_ptr(kind, multi);
+  lg.pf = pf;
+  lg.lds = vgc_lds_bytes(kind, multi, pf, waves, Q, S);
+  const void *fn = vgc_kernel_ptr(kind, multi, pf);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lg.lds);
   if (e != hipSuccess) {
     hipGetLastError();
@@ -253,6 +262,8 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   hq->dbase = 0;
   hq->vbase = 0;
   hq->nv = g->n;
+  hq->r0 = 0;
+  hq->pad = 0;
   hw[0] = 0;
   hw[1] = (int64_t)words;
   for (int i = 0; i < nseed; i++) {
@@ -286,7 +297,11 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   a.max_rounds = 0xFFFFFFFFu;
   a.ring_cap = lg.ring;
   a.stage_cap = lg.stage;
+  a.min_chunk = o.min_chunk;
+  a.window = o.window;
   a.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
+  a.round_base = 0;
+  a.test_first = o.test_first ? 1u : 0u;
   a.ctl = (Ctl *)w.ctl.p;
 
   if ((e = hipEventRecord(w.ev0, s)) != hipSuccess) return hip_fail(e);
@@ -299,7 +314,8 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   if ((e = launch_fill_u32((uint32_t *)w.ctl.p, sizeof(Ctl) / 4, 0u, s)) != hipSuccess) return hip_fail(e);
   if ((e = launch_seed(kind, a, (const SeedEnt *)w.seeds.p, (uint32_t)nseed, 0, 0, s)) != hipSuccess)
     return hip_fail(e);
-  if ((e = launch_vgc(kind, false, a, lg.grid, lg.block, lg.lds, dev_info().coop != 0, s)) != hipSuccess)
+  if ((e = hipEventRecord(w.evk, s)) != hipSuccess) return hip_fail(e);
+  if ((e = launch_vgc(kind, false, lg.pf, a, lg.grid, lg.block, lg.lds, dev_info().coop != 0, s)) != hipSuccess)
     return hip_fail(e);
   if ((e = hipEventRecord(w.ev1, s)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpyAsync(w.h_ctl.p, w.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -310,9 +326,11 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   if (c.abort) return PASGAL_ETIMEOUT;
   if (st) {
     fill_stats_from_ctl(c, st, add_stats);
-    float ms = 0;
+    float ms = 0, kms = 0;
     hipEventElapsedTime(&ms, w.ev0, w.ev1);
+    hipEventElapsedTime(&kms, w.evk, w.ev1);
     st->device_ms += ms;
+    st->kernel_ms += kms;
   }
   return PASGAL_OK;
 }
@@ -362,6 +380,7 @@ static int run_plain(Workspace &w, int kind, const pasgal_csr *g, void *state, c
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
   uint32_t ncur = *hcnt;
   uint32_t level = 0;
+  if ((e = hipEventRecord(w.evk, s)) != hipSuccess) return hip_fail(e);
   int cur = 0;
   int64_t expansions = 0, maxf = 0;
   while (ncur > 0) {
@@ -396,9 +415,11 @@ static int run_plain(Workspace &w, int kind, const pasgal_csr *g, void *state, c
     st->relax_success += (int64_t)c.stats[ST_SUCCESS];
     st->published += (int64_t)c.stats[ST_SUCCESS];
     st->max_frontier = std::max<int64_t>(st->max_frontier, maxf);
-    float ms = 0;
+    float ms = 0, kms = 0;
     hipEventElapsedTime(&ms, w.ev0, w.ev1);
+    hipEventElapsedTime(&kms, w.evk, w.ev1);
     st->device_ms += ms;
+    st->kernel_ms += kms;
   }
   return PASGAL_OK;
 }
@@ -426,13 +447,15 @@ void pasgal_opts_default(pasgal_opts *o) {
   if (!o) return;
   memset(o, 0, sizeof(*o));
   o->mode = PASGAL_MODE_VGC;
-  o->tau = 256;
+  o->tau = 1024;
   o->wg_size = 1024;
   o->blocks_per_cu = 1;
   o->frontier_capacity = 0;
   o->flags = 0;
   o->timeout_ms = 20000;
   o->stream = nullptr;
+  o->window = 0;
+  o->min_chunk = 1;
 }
 
 const char *pasgal_strerror(int code) {

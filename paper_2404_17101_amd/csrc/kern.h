@@ -26,6 +26,8 @@ struct QInfo {
   int64_t dbase;  // dirty word of local vertex l is dbase + l/32
   int32_t vbase;  // first global vertex of the query's graph
   int32_t nv;     // vertices of the query's graph
+  uint32_t r0;    // absolute round in which the query was seeded (BFS window)
+  uint32_t pad;
 };
 
 enum StatIdx {
@@ -42,8 +44,6 @@ struct Ctl {
   uint32_t bar;       // grid-barrier arrivals within one launch
   uint32_t abort;     // set when a bounded wait expired
   uint32_t cnt[3];    // frontier tails: round r reads cnt[r%3], appends to cnt[(r+1)%3]
-  uint32_t claim[3];  // entries claimed from the current frontier
-  uint32_t dclaim[3]; // dirty words claimed
   uint32_t ovf[3];    // ovf[(r+1)%3] != 0: round r+1 must rescan the dirty bitmaps
   uint32_t rounds;    // rounds run by the launch (exit record)
   uint32_t final_cnt; // entries left in the last next-frontier
@@ -51,7 +51,7 @@ struct Ctl {
   uint32_t final_buf; // frontier buffer holding the leftover entries
   uint32_t max_frontier;
   uint32_t bad_csr;   // validation result
-  uint32_t pad[10];
+  uint32_t pad[13];
   unsigned long long stats[8];
 };
 
@@ -77,6 +77,11 @@ struct VgcArgs {
   uint32_t max_rounds;
   uint32_t ring_cap;      // LDS ring entries per wave (power of two)
   uint32_t stage_cap;     // LDS staging entries per wave
+  uint32_t min_chunk;     // frontier entries a wavefront takes at least per local search
+  uint32_t window;        // BFS: round r of query q expands only distances below
+                          // (round_base + r + 1 - qi[q].r0) * window; 0 = no limit
+  uint32_t round_base;    // absolute number of the launch's first round
+  uint32_t test_first;    // plain load before each atomic to skip relaxations that cannot succeed
   long long timeout_ticks;
   Ctl *ctl;
 };
@@ -91,10 +96,11 @@ struct SeedEnt {
 // LDS of a persistent launch: per wavefront a ring (local queue) of ring_cap
 // entries and a staging buffer of stage_cap entries ({v, val[, q]} each, SoA)
 // plus 64 words of scan scratch, 16-byte aligned.
-__host__ __device__ inline size_t vgc_lds_bytes(int kind, bool multi, int waves, uint32_t ring_cap,
+__host__ __device__ inline size_t vgc_lds_bytes(int kind, bool multi, bool pf, int waves, uint32_t ring_cap,
                                                 uint32_t stage_cap) {
   const size_t vsz = (kind == KIND_BFS) ? 4 : 8;
-  size_t per = (size_t)(ring_cap + stage_cap) * (vsz + 4 + (multi ? 4 : 0)) + 64 * 4;
+  size_t per = (size_t)(ring_cap + stage_cap) * (vsz + 4 + (multi ? 4 : 0)) + (pf ? 8 * (size_t)ring_cap : 0) +
+               64 * 4;
   per = (per + 15) & ~(size_t)15;
   return per * (size_t)waves;
 }
@@ -106,9 +112,9 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 // to the state (BFS: store val; REACH: OR val).
 hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_t nseed, uint32_t start_cnt,
                        uint32_t start_ovf, hipStream_t s);
-hipError_t launch_vgc(int kind, bool multi, const VgcArgs &a, int grid, int block, size_t lds, bool cooperative,
-                      hipStream_t s);
-const void *vgc_kernel_ptr(int kind, bool multi);
+hipError_t launch_vgc(int kind, bool multi, bool pf, const VgcArgs &a, int grid, int block, size_t lds,
+                      bool cooperative, hipStream_t s);
+const void *vgc_kernel_ptr(int kind, bool multi, bool pf);
 
 // Plain level-synchronous rounds (one launch per BFS level).
 hipError_t launch_plain_bfs_level(const int32_t *off, const int32_t *tgt, uint32_t *dist, const uint32_t *cur,

@@ -89,19 +89,29 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t x) {
   for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor(x, d));
   return x;
 }
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = min(x, (uint32_t)__shfl_xor(x, d));
+  return x;
+}
 __device__ __forceinline__ unsigned long long shfl64(unsigned long long x, int src) {
   uint32_t lo = __shfl((uint32_t)x, src), hi = __shfl((uint32_t)(x >> 32), src);
   return ((unsigned long long)hi << 32) | lo;
 }
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
+// Round state every workgroup needs after a barrier; read once per
+// workgroup by thread 0 and broadcast through LDS.
+struct RoundHdr {
+  uint32_t ncur, ovf, abort;
+};
+
 // Grid barrier for a persistent launch whose workgroups are all resident.
 // Fence-free: callers keep cross-workgroup data in agent-scope atomics.
-// Returns true when the launch must stop (a wait expired somewhere).
-__device__ bool grid_barrier(Ctl *ctl, uint32_t &epoch, long long deadline) {
+// After the wait, thread 0 reads the counters of slot `slot` for everyone.
+__device__ void grid_barrier(Ctl *ctl, uint32_t &epoch, long long deadline, uint32_t slot, RoundHdr *hdr) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  __shared__ uint32_t s_abort;
   if (threadIdx.x == 0) {
     epoch += 1;
     const uint32_t target = epoch * gridDim.x;
@@ -117,10 +127,11 @@ __device__ bool grid_barrier(Ctl *ctl, uint32_t &epoch, long long deadline) {
       __builtin_amdgcn_s_sleep(2);
     }
     if (ld_ag(&ctl->abort)) ab = 1;
-    s_abort = ab;
+    hdr->abort = ab;
+    hdr->ncur = ld_ag(&ctl->cnt[slot]);
+    hdr->ovf = ld_ag(&ctl->ovf[slot]);
   }
   __syncthreads();
-  return s_abort != 0;
 }
 
 // ------------------------------------------------------------ VGC engine --
@@ -132,23 +143,27 @@ struct ValT<KIND_BFS> { using T = uint32_t; };
 template <>
 struct ValT<KIND_REACH> { using T = unsigned long long; };
 
-template <int KIND, bool MULTI>
+template <int KIND, bool MULTI, bool PF>
 struct Wave {
   using Val = typename ValT<KIND>::T;
   static constexpr bool FIFO = (KIND == KIND_BFS);  // BFS: local BFS order; reach: LIFO (deep first)
+  // PF: local-queue entries carry their vertex's arc range, loaded while the
+  // relaxing atomic is in flight, so expanding them starts at the targets.
 
   const VgcArgs &a;
   Val *state;
   // per-wave LDS
   Val *rval, *sval;
   uint32_t *rv, *sv, *rq, *sq, *scan;
+  int32_t *rb, *re;
   uint32_t Q, S, ln;
   // wave-uniform
   uint32_t head, tail, scount;
   uint32_t nslot, nbuf;
-  unsigned long long st[ST_COUNT];
+  uint32_t rabs;   // absolute number of the current round (BFS window)
+  unsigned long long st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale;
 
-  __device__ Wave(const VgcArgs &args, uint8_t *lds_wave) : a(args) {
+  __device__ __forceinline__ Wave(const VgcArgs &args, uint8_t *lds_wave) : a(args) {
     state = (Val *)a.state;
     Q = a.ring_cap;
     S = a.stage_cap;
@@ -164,16 +179,31 @@ struct Wave {
     } else {
       rq = sq = nullptr;
     }
+    if (PF) {
+      rb = (int32_t *)p; p += 4 * Q;
+      re = (int32_t *)p; p += 4 * Q;
+    } else {
+      rb = re = nullptr;
+    }
     scan = (uint32_t *)p;
     head = tail = scount = 0;
     nslot = nbuf = 0;
-#pragma unroll
-    for (int i = 0; i < ST_COUNT; i++) st[i] = 0;
+    rabs = 0;
+    st_expand = st_arcs = st_success = st_publish = st_overflow = st_stale = 0;
   }
 
   __device__ __forceinline__ int64_t sbase_of(uint32_t q) const { return MULTI ? a.qi[q].sbase : 0; }
 
-  __device__ void mark_dirty(uint32_t v, uint32_t q) {
+  // BFS window: distances below the limit may be expanded in this round;
+  // the rest wait in the frontier (bucket width a.window per round).
+  __device__ __forceinline__ uint32_t limit_of(uint32_t q) const {
+    if (KIND != KIND_BFS || a.window == 0) return 0xFFFFFFFFu;
+    const uint32_t r0 = MULTI ? a.qi[q].r0 : 0u;
+    const uint64_t lim = (uint64_t)(rabs + 1u - r0) * a.window;
+    return lim > 0xFFFFFFFEull ? 0xFFFFFFFFu : (uint32_t)lim;
+  }
+
+  __device__ __forceinline__ void mark_dirty(uint32_t v, uint32_t q) {
     int64_t dbase = 0;
     uint32_t local = v;
     if (MULTI) {
@@ -184,15 +214,10 @@ struct Wave {
     or_ag(&a.dirty[dbase + (local >> 5)], 1u << (local & 31));
   }
 
-  // Write the staging buffer to the next global frontier: one reservation
-  // per buffer, coalesced agent-scope stores; entries past the capacity go
-  // to the dirty bitmap (never dropped).
-  __device__ void flush_stage() {
-    if (scount == 0) return;
-    wave_sync();
-    uint32_t base = 0;
-    if (ln == 0) base = add_ag(&a.ctl->cnt[nslot], scount);
-    base = __shfl(base, 0);
+  // Copy the staging buffer to the next global frontier at [base, base +
+  // scount): coalesced agent-scope stores; entries past the capacity go to
+  // the dirty bitmap (never dropped).
+  __device__ __forceinline__ void write_stage(uint32_t base) {
     bool ovf = false;
     for (uint32_t i = ln; i < scount; i += 64) {
       const uint32_t v = sv[i];
@@ -212,15 +237,68 @@ struct Wave {
     if (ob) {
       if (ln == 0) st_ag(&a.ctl->ovf[nslot], 1u);
     }
-    st[ST_OVERFLOW] += __popcll(ob);
-    st[ST_PUBLISH] += scount;
+    st_overflow += __popcll(ob);
+    st_publish += scount;
     scount = 0;
+  }
+
+  // Mid-round flush by one wavefront (its staging buffer is full).
+  __device__ __forceinline__ void flush_stage() {
+    if (scount == 0) return;
     wave_sync();
+    uint32_t base = 0;
+    if (ln == 0) base = add_ag(&a.ctl->cnt[nslot], scount);
+    base = __shfl(base, 0);
+    write_stage(base);
+    wave_sync();
+  }
+
+  // End-of-round flush, collective over the workgroup: one reservation per
+  // workgroup instead of one per wavefront.
+  __device__ __forceinline__ void flush_stage_block(uint32_t *s_cnt, uint32_t wid, uint32_t nw) {
+    wave_sync();
+    if (ln == 0) s_cnt[wid] = scount;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (uint32_t w = 0; w < nw; w++) {
+        const uint32_t c = s_cnt[w];
+        s_cnt[w] = tot;
+        tot += c;
+      }
+      s_cnt[nw] = tot ? add_ag(&a.ctl->cnt[nslot], tot) : 0u;
+    }
+    __syncthreads();
+    const uint32_t base = s_cnt[nw] + s_cnt[wid];
+    if (scount) write_stage(base);
+    __syncthreads();
+  }
+
+  // Wave-collective: lanes with p append (w, q, nv) to the staging buffer.
+  __device__ __forceinline__ void push_stage(bool p, uint32_t w, uint32_t q, Val nv) {
+    const unsigned long long bal = __ballot(p);
+    if (bal == 0) return;
+    const uint32_t c = __popcll(bal);
+    if (scount + c > S) flush_stage();
+    if (p) {
+      const uint32_t i = scount + mbcnt64(bal);
+      sv[i] = w;
+      sval[i] = nv;
+      if (MULTI) sq[i] = q;
+    }
+    scount += c;
   }
 
   // Wave-collective push: lanes with p hand (w, q, nv) to the local queue
   // when allowed and there is room, else to the staging buffer.
-  __device__ __forceinline__ void push(bool p, uint32_t w, uint32_t q, Val nv, bool ring_ok) {
+  __device__ __forceinline__ void push(bool p, uint32_t w, uint32_t q, Val nv, bool ring_ok, int32_t nb = 0,
+                                      int32_t ne = 0) {
+    // BFS window: values at or beyond the round's limit wait for a later round
+    if (KIND == KIND_BFS && a.window) {
+      const bool late = p && (uint32_t)nv >= limit_of(q);
+      push_stage(late, w, q, nv);
+      p = p && !late;
+    }
     const unsigned long long bal = __ballot(p);
     if (bal == 0) return;
     const uint32_t c = __popcll(bal);
@@ -231,6 +309,10 @@ struct Wave {
         rv[i] = w;
         rval[i] = nv;
         if (MULTI) rq[i] = q;
+        if (PF) {
+          rb[i] = nb;
+          re[i] = ne;
+        }
       }
       tail += c;
     } else {
@@ -246,26 +328,44 @@ struct Wave {
   }
 
   // Relax arc (., w) with value val of its tail; returns whether the state of
-  // w changed and the value to carry.
-  __device__ __forceinline__ bool relax(int64_t sb, uint32_t w, Val val, Val &nv) {
+  // w changed and the value to carry. With a.test_first, a plain load first
+  // rules out relaxations that cannot change anything (values only ever go
+  // down for BFS / gain bits for reach, so a stale read is still a safe
+  // filter). With PF the arc range of w is loaded alongside.
+  __device__ __forceinline__ bool relax(int64_t sb, uint32_t w, Val val, Val &nv, int32_t &nb, int32_t &ne) {
+    if (PF) {
+      nb = a.off[w];
+      ne = a.off[w + 1];
+    }
     if (KIND == KIND_BFS) {
       const uint32_t nd = (uint32_t)val + 1u;
-      const uint32_t old = min_ag((uint32_t *)&state[sb + w], nd);
       nv = (Val)nd;
+      uint32_t *p = (uint32_t *)&state[sb + w];
+      if (a.test_first && __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= nd) return false;
+      const uint32_t old = min_ag(p, nd);
       return nd < old;
     } else {
-      const unsigned long long old = or_ag((unsigned long long *)&state[sb + w], (unsigned long long)val);
-      nv = (Val)(old | (unsigned long long)val);
+      unsigned long long *p = (unsigned long long *)&state[sb + w];
+      const unsigned long long m = (unsigned long long)val;
+      if (a.test_first) {
+        const unsigned long long cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if ((cur & m) == m) {
+          nv = (Val)cur;
+          return false;
+        }
+      }
+      const unsigned long long old = or_ag(p, m);
+      nv = (Val)(old | m);
       return nv != (Val)old;
     }
   }
 
   // Expand the active lanes' entries: scan out-arcs, relax, push successes.
   // Returns the number of entries expanded (not stale).
-  __device__ uint32_t expand(bool act, uint32_t v, uint32_t q, Val val, bool ring_ok) {
+  __device__ __forceinline__ uint32_t expand(bool act, uint32_t v, uint32_t q, Val val, bool ring_ok, int32_t b = 0, int32_t e = 0,
+                             bool have_range = false) {
     const int64_t sb = (act && MULTI) ? sbase_of(q) : 0;
-    int32_t b = 0, e = 0;
-    if (act) {
+    if (act && !have_range) {
       b = a.off[v];
       e = a.off[v + 1];
     }
@@ -276,33 +376,35 @@ struct Wave {
     }
     const unsigned long long actb = __ballot(act);
     const uint32_t nexp = __popcll(actb);
-    st[ST_EXPAND] += nexp;
+    st_expand += nexp;
     const uint32_t deg = act ? (uint32_t)(e - b) : 0u;
     const uint32_t maxd = wave_max(deg);
     if (maxd == 0) return nexp;
     if (maxd <= 8) {
       int32_t w[8];
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) w[u] = ((uint32_t)u < deg) ? a.tgt[b + u] : 0;
       bool ok[8];
       Val nv[8];
-#pragma unroll
+      int32_t nb[8], ne[8];
+#pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) {
         ok[u] = false;
         nv[u] = 0;
-        if ((uint32_t)u < deg) ok[u] = relax(sb, (uint32_t)w[u], val, nv[u]);
+        nb[u] = ne[u] = 0;
+        if ((uint32_t)u < deg) ok[u] = relax(sb, (uint32_t)w[u], val, nv[u], nb[u], ne[u]);
       }
       uint32_t nsucc = 0, arcs = 0;
-#pragma unroll
+#pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) {
         if ((uint32_t)u < maxd) {
           arcs += __popcll(__ballot((uint32_t)u < deg));
           nsucc += __popcll(__ballot(ok[u]));
-          push(ok[u], (uint32_t)w[u], q, nv[u], ring_ok);
+          push(ok[u], (uint32_t)w[u], q, nv[u], ring_ok, nb[u], ne[u]);
         }
       }
-      st[ST_SUCCESS] += nsucc;
-      st[ST_ARCS] += arcs;
+      st_success += nsucc;
+      st_arcs += arcs;
       return nexp;
     }
     // Flattened: the wave's arcs are dealt out 64 at a time; each lane finds
@@ -312,7 +414,7 @@ struct Wave {
     const uint32_t excl = incl - deg;
     scan[ln] = incl;
     wave_sync();
-    st[ST_ARCS] += total;
+    st_arcs += total;
     uint32_t nsucc = 0;
     for (uint32_t j = 0; j < total; j += 64) {
       const uint32_t ai = j + ln;
@@ -334,44 +436,50 @@ struct Wave {
       uint32_t w = 0;
       bool ok = false;
       Val nv = 0;
+      int32_t nb = 0, ne = 0;
       if (okl) {
         w = (uint32_t)a.tgt[bo + (int32_t)(ai - eo)];
-        ok = relax(sbo, w, vo, nv);
+        ok = relax(sbo, w, vo, nv, nb, ne);
       }
       nsucc += __popcll(__ballot(ok));
-      push(ok, w, qo, nv, ring_ok);
+      push(ok, w, qo, nv, ring_ok, nb, ne);
     }
     wave_sync();
-    st[ST_SUCCESS] += nsucc;
+    st_success += nsucc;
     return nexp;
   }
 
   // Pop up to 64 entries from the local queue and expand them.
-  __device__ uint32_t step(bool ring_ok) {
+  __device__ __forceinline__ uint32_t step(bool ring_ok) {
     const uint32_t avail = tail - head;
     const uint32_t k = min(avail, 64u);
     const uint32_t idx = FIFO ? (head + ln) : (tail - k + ln);
     const bool act = ln < k;
     uint32_t v = 0, q = 0;
     Val val = 0;
+    int32_t b = 0, e = 0;
     if (act) {
       const uint32_t s = idx & (Q - 1);
       v = rv[s];
       val = rval[s];
       if (MULTI) q = rq[s];
+      if (PF) {
+        b = rb[s];
+        e = re[s];
+      }
     }
     wave_sync();
     if (FIFO)
       head += k;
     else
       tail -= k;
-    const uint32_t ne = expand(act, v, q, val, ring_ok);
-    st[ST_STALE] += (uint32_t)__popcll(__ballot(act)) - ne;
+    const uint32_t ne = expand(act, v, q, val, ring_ok, b, e, PF);
+    st_stale += (uint32_t)__popcll(__ballot(act)) - ne;
     return ne;
   }
 
   // Move whatever is left in the local queue to the staging buffer.
-  __device__ void spill_ring() {
+  __device__ __forceinline__ void spill_ring() {
     while (tail != head) {
       const uint32_t k = min(tail - head, 64u);
       const bool act = ln < k;
@@ -392,7 +500,7 @@ struct Wave {
 
   // One local search: the ring holds the roots; expand until the budget of
   // expanded vertices is spent or nothing is left, then publish the rest.
-  __device__ void local_search(uint32_t budget) {
+  __device__ __forceinline__ void local_search(uint32_t budget) {
     uint32_t expanded = 0;
     while (tail != head) {
       if (expanded >= budget) {
@@ -404,27 +512,33 @@ struct Wave {
     head = tail = 0;
   }
 
-  __device__ void load_roots(bool has, uint32_t v, uint32_t q, Val val) {
+  __device__ __forceinline__ void load_roots(bool has, uint32_t v, uint32_t q, Val val) {
     const unsigned long long bal = __ballot(has);
     const uint32_t pos = mbcnt64(bal);
     if (has) {
       rv[pos] = v;
       rval[pos] = val;
       if (MULTI) rq[pos] = q;
+      if (PF) {
+        rb[pos] = a.off[v];
+        re[pos] = a.off[v + 1];
+      }
     }
     wave_sync();
     head = 0;
     tail = __popcll(bal);
   }
 
-  __device__ void process_frontier(uint32_t cbuf, uint32_t cslot, uint32_t nproc, uint32_t chunk) {
-    while (true) {
-      uint32_t base = 0;
-      if (ln == 0) base = add_ag(&a.ctl->claim[cslot], chunk);
-      base = __shfl(base, 0);
-      if (base >= nproc) break;
+  // Frontier entries are dealt out statically: chunk c of `chunk` consecutive
+  // entries goes to wavefront c mod total (gw numbers wavefronts so that each
+  // XCD holds a contiguous range). Consecutive entries were published together
+  // by one local search, so a wavefront's roots are close in the graph.
+  __device__ __forceinline__ void process_frontier(uint32_t cbuf, uint32_t nproc, uint32_t chunk, uint32_t gw, uint32_t total) {
+    const uint32_t nchunks = (nproc + chunk - 1) / chunk;
+    for (uint32_t c = gw; c < nchunks; c += total) {
+      const uint32_t base = c * chunk;
       const uint32_t cnt = min(chunk, nproc - base);
-      const bool has = ln < cnt;
+      bool has = ln < cnt;
       uint32_t v = 0, q = 0;
       Val val = 0;
       if (has) {
@@ -432,18 +546,21 @@ struct Wave {
         if (MULTI) q = ld_ag(&a.fr.q[cbuf][base + ln]);
         val = (Val)ld_ag(&a.fr.val[cbuf][base + ln]);
       }
+      if (KIND == KIND_BFS && a.window) {  // roots beyond the window wait for a later round
+        const bool defer = has && (uint32_t)val >= limit_of(q);
+        push_stage(defer, v, q, val);
+        has = has && !defer;
+      }
+      const uint32_t nroots = __popcll(__ballot(has));
+      if (nroots == 0) continue;
       load_roots(has, v, q, val);
-      local_search(a.tau * cnt);
+      local_search(a.tau * nroots);
     }
   }
 
   // Re-expand vertices whose frontier entries overflowed last round.
-  __device__ void process_dirty(uint32_t cslot) {
-    while (true) {
-      uint32_t base = 0;
-      if (ln == 0) base = add_ag(&a.ctl->dclaim[cslot], 64u);
-      base = __shfl(base, 0);
-      if ((int64_t)base >= a.dirty_words) break;
+  __device__ __forceinline__ void process_dirty(uint32_t gw, uint32_t total) {
+    for (int64_t base = (int64_t)gw * 64; base < a.dirty_words; base += (int64_t)total * 64) {
       // virtual word index -> (query, word of that query's bitmap)
       const int64_t widx = (int64_t)base + ln;
       uint32_t q = 0;
@@ -480,58 +597,78 @@ struct Wave {
           v = (uint32_t)vbase + (uint32_t)(lw * 32 + bit);
           val = ld_ag(&state[sb + v]);
         }
-        const uint32_t c = __popcll(__ballot(has));
-        load_roots(has, v, q, val);
+        bool go = has;
+        if (KIND == KIND_BFS && a.window) {
+          const bool defer = has && (uint32_t)val >= limit_of(q);
+          push_stage(defer, v, q, val);
+          go = has && !defer;
+        }
+        const uint32_t c = __popcll(__ballot(go));
+        if (c == 0) continue;
+        load_roots(go, v, q, val);
         local_search(a.tau * c);
       }
     }
   }
 
-  __device__ void flush_stats() {
+  __device__ __forceinline__ void flush_stats() {
     if (ln == 0) {
-#pragma unroll
+      const unsigned long long vals[ST_COUNT] = {st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale};
+#pragma clang loop unroll(full)
       for (int i = 0; i < ST_COUNT; i++)
-        if (st[i]) add_ag(&a.ctl->stats[i], st[i]);
+        if (vals[i]) add_ag(&a.ctl->stats[i], vals[i]);
     }
   }
 };
 
-template <int KIND, bool MULTI>
+template <int KIND, bool MULTI, bool PF>
 __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ RoundHdr hdr;
+  __shared__ uint32_t s_cnt[17];
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wid = threadIdx.x >> 6;
-  const size_t per_wave = vgc_lds_bytes(KIND, MULTI, 1, a.ring_cap, a.stage_cap);
-  Wave<KIND, MULTI> wv(a, smem + per_wave * wid);
+  const size_t per_wave = vgc_lds_bytes(KIND, MULTI, PF, 1, a.ring_cap, a.stage_cap);
+  Wave<KIND, MULTI, PF> wv(a, smem + per_wave * wid);
   const uint32_t total_waves = gridDim.x * nw;
+  // XCD-aware numbering: workgroups are dispatched round-robin over the 8
+  // XCDs; give each XCD a contiguous range of logical workgroups.
+  uint32_t lblock = blockIdx.x;
+  if ((gridDim.x & 7u) == 0) lblock = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const uint32_t gw = lblock * nw + wid;
   const long long deadline = wall_clock64() + a.timeout_ticks;
   uint32_t epoch = 0;
   uint32_t cbuf = a.start_buf;
-  uint32_t ncur = ld_ag(&a.ctl->cnt[0]);
-  uint32_t ovf = ld_ag(&a.ctl->ovf[0]);
+  if (threadIdx.x == 0) {
+    hdr.ncur = ld_ag(&a.ctl->cnt[0]);
+    hdr.ovf = ld_ag(&a.ctl->ovf[0]);
+    hdr.abort = 0;
+  }
+  __syncthreads();
+  uint32_t ncur = hdr.ncur, ovf = hdr.ovf;
   uint32_t maxf = 0;
   uint32_t r = 0;
   for (; r < a.max_rounds; ++r) {
     if (ncur == 0 && ovf == 0) break;
     maxf = max(maxf, ncur);
-    const uint32_t cslot = r % 3, nslot = (r + 1) % 3, fslot = (r + 2) % 3;
+    const uint32_t nslot = (r + 1) % 3, fslot = (r + 2) % 3;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st_ag(&a.ctl->cnt[fslot], 0u);
-      st_ag(&a.ctl->claim[fslot], 0u);
-      st_ag(&a.ctl->dclaim[fslot], 0u);
       st_ag(&a.ctl->ovf[fslot], 0u);
     }
     wv.nslot = nslot;
     wv.nbuf = cbuf ^ 1u;
-    if (ovf) wv.process_dirty(cslot);
+    wv.rabs = a.round_base + r;
+    if (ovf) wv.process_dirty(gw, total_waves);
     const uint32_t nproc = min(ncur, a.fr.cap);
     uint32_t chunk = (nproc + total_waves - 1) / total_waves;
-    chunk = min(max(chunk, 1u), 64u);
-    wv.process_frontier(cbuf, cslot, nproc, chunk);
-    wv.flush_stage();
-    if (grid_barrier(a.ctl, epoch, deadline)) break;
-    ncur = ld_ag(&a.ctl->cnt[nslot]);
-    ovf = ld_ag(&a.ctl->ovf[nslot]);
+    chunk = min(max(chunk, max(a.min_chunk, 1u)), 64u);
+    wv.process_frontier(cbuf, nproc, chunk, gw, total_waves);
+    wv.flush_stage_block(s_cnt, wid, nw);
+    grid_barrier(a.ctl, epoch, deadline, nslot, &hdr);
+    if (hdr.abort) break;
+    ncur = hdr.ncur;
+    ovf = hdr.ovf;
     cbuf ^= 1u;
   }
   wv.flush_stats();
@@ -602,11 +739,13 @@ static int fill_grid(uint64_t n) {
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t val, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, val);
   return hipGetLastError();
 }
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long val, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u64_kernel, dim3(fill_grid(4 * n)), dim3(256), 0, s, p, n, val);
   return hipGetLastError();
@@ -614,6 +753,7 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 
 hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_t nseed, uint32_t start_cnt,
                        uint32_t start_ovf, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   const int grid = (int)((nseed + 255) / 256) > 0 ? (int)((nseed + 255) / 256) : 1;
   if (kind == KIND_BFS)
     hipLaunchKernelGGL(seed_kernel<KIND_BFS>, dim3(grid), dim3(256), 0, s, a, seeds, nseed, start_cnt, start_ovf);
@@ -622,14 +762,20 @@ hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_
   return hipGetLastError();
 }
 
-const void *vgc_kernel_ptr(int kind, bool multi) {
-  if (kind == KIND_BFS) return multi ? (const void *)vgc_kernel<KIND_BFS, true> : (const void *)vgc_kernel<KIND_BFS, false>;
-  return multi ? (const void *)vgc_kernel<KIND_REACH, true> : (const void *)vgc_kernel<KIND_REACH, false>;
+const void *vgc_kernel_ptr(int kind, bool multi, bool pf) {
+  if (kind == KIND_BFS) {
+    if (multi) return pf ? (const void *)vgc_kernel<KIND_BFS, true, true> : (const void *)vgc_kernel<KIND_BFS, true, false>;
+    return pf ? (const void *)vgc_kernel<KIND_BFS, false, true> : (const void *)vgc_kernel<KIND_BFS, false, false>;
+  }
+  if (multi)
+    return pf ? (const void *)vgc_kernel<KIND_REACH, true, true> : (const void *)vgc_kernel<KIND_REACH, true, false>;
+  return pf ? (const void *)vgc_kernel<KIND_REACH, false, true> : (const void *)vgc_kernel<KIND_REACH, false, false>;
 }
 
-hipError_t launch_vgc(int kind, bool multi, const VgcArgs &a, int grid, int block, size_t lds, bool cooperative,
-                      hipStream_t s) {
-  const void *fn = vgc_kernel_ptr(kind, multi);
+hipError_t launch_vgc(int kind, bool multi, bool pf, const VgcArgs &a, int grid, int block, size_t lds,
+                      bool cooperative, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
+  const void *fn = vgc_kernel_ptr(kind, multi, pf);
   VgcArgs copy = a;
   void *args[] = {&copy};
   if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, s);
@@ -713,6 +859,7 @@ __global__ void __launch_bounds__(256) plain_level_kernel(const int32_t *off, co
 hipError_t launch_plain_bfs_level(const int32_t *off, const int32_t *tgt, uint32_t *dist, const uint32_t *cur,
                                   uint32_t ncur, uint32_t *nxt, uint32_t *cnt, uint32_t level, Ctl *ctl,
                                   hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   uint32_t waves = (ncur + 63) / 64;
   uint32_t blocks = (waves + 3) / 4;
   if (blocks < 1) blocks = 1;
@@ -725,6 +872,7 @@ hipError_t launch_plain_bfs_level(const int32_t *off, const int32_t *tgt, uint32
 hipError_t launch_plain_reach_level(const int32_t *off, const int32_t *tgt, unsigned long long *mask,
                                     uint32_t *stamp, const uint32_t *cur, uint32_t ncur, uint32_t *nxt,
                                     uint32_t *cnt, uint32_t level, Ctl *ctl, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   uint32_t waves = (ncur + 63) / 64;
   uint32_t blocks = (waves + 3) / 4;
   if (blocks < 1) blocks = 1;
@@ -753,6 +901,7 @@ __global__ void plain_seed_kernel(int kind, void *state, uint32_t *frontier, uin
 
 hipError_t launch_plain_seed(int kind, void *state, uint32_t *frontier, uint32_t *cnt_slots, uint32_t *stamp,
                              const uint32_t *srcs, const unsigned long long *vals, uint32_t nsrc, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   hipLaunchKernelGGL(plain_seed_kernel, dim3((nsrc + 255) / 256), dim3(256), 0, s, kind, state, frontier, cnt_slots,
                      stamp, srcs, vals, nsrc);
   return hipGetLastError();
@@ -878,6 +1027,7 @@ size_t transpose_scratch_elems(int32_t n) {
 
 hipError_t launch_transpose(const int32_t *off, const int32_t *tgt, int32_t n, int32_t m, int32_t *t_off,
                             int32_t *t_tgt, int32_t *scratch, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   int32_t *cnt = scratch;                 // n+1 (histogram, then cursor)
   const int64_t len = (int64_t)n + 1;
   const int64_t tiles = (len + SCAN_TILE - 1) / SCAN_TILE;
@@ -922,6 +1072,7 @@ __global__ void validate_kernel(const int32_t *off, const int32_t *tgt, int32_t 
 }
 
 hipError_t launch_validate(const int32_t *off, const int32_t *tgt, int32_t n, int32_t m, Ctl *ctl, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   int64_t work = (int64_t)n > (int64_t)m ? (int64_t)n : (int64_t)m;
   int g = (int)((work + 255) / 256);
   if (g < 1) g = 1;
@@ -955,6 +1106,7 @@ __global__ void census_kernel(const uint32_t *fq, uint32_t cnt, uint32_t *counts
 hipError_t launch_census(const uint32_t *fq, uint32_t cnt, uint32_t cap, uint32_t *counts, const QInfo *qi,
                          const int64_t *qword, const uint32_t *dirty, int32_t nq, uint32_t *dirty_any,
                          hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   const uint32_t c = cnt < cap ? cnt : cap;
   int g = (int)((c + 255) / 256);
   if (g < 64) g = 64;
@@ -975,6 +1127,7 @@ __global__ void strided_u64_kernel(unsigned long long *dst, int stride, int word
 
 hipError_t launch_strided_u64(unsigned long long *dst, int stride, int word, const unsigned long long *src,
                               uint64_t n, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   hipLaunchKernelGGL(strided_u64_kernel, dim3(fill_grid(4 * n)), dim3(256), 0, s, dst, stride, word, src, n);
   return hipGetLastError();
 }
@@ -992,6 +1145,7 @@ __global__ void fill_segments_kernel(T *base, const int64_t *seg_off, const int6
 
 hipError_t launch_fill_segments_u32(uint32_t *base, const int64_t *seg_off, const int64_t *seg_len, int32_t nseg,
                                     uint32_t val, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   if (nseg <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_segments_kernel<uint32_t>, dim3(nseg < 65536 ? nseg : 65536), dim3(1024), 0, s, base,
                      seg_off, seg_len, nseg, val);
@@ -999,6 +1153,7 @@ hipError_t launch_fill_segments_u32(uint32_t *base, const int64_t *seg_off, cons
 }
 hipError_t launch_fill_segments_u64(unsigned long long *base, const int64_t *seg_off, const int64_t *seg_len,
                                     int32_t nseg, unsigned long long val, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   if (nseg <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_segments_kernel<unsigned long long>, dim3(nseg < 65536 ? nseg : 65536), dim3(1024), 0, s,
                      base, seg_off, seg_len, nseg, val);
@@ -1011,6 +1166,7 @@ __global__ void add_const_kernel(int32_t *dst, const int32_t *src, int64_t n, in
 }
 
 hipError_t launch_add_const(int32_t *dst, const int32_t *src, int64_t n, int32_t c, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(add_const_kernel, dim3(fill_grid(4 * (uint64_t)n)), dim3(256), 0, s, dst, src, n, c);
   return hipGetLastError();

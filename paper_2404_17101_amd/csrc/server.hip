@@ -91,6 +91,7 @@ struct Req {
   double t_submit = 0, t_admit = 0;
   int64_t rounds = 0;
   int slot = -1;
+  uint32_t r0 = 0;  // lane round in which the request was seeded
   int64_t off = -1, bytes = 0, dirty_off = 0;
   int32_t vbase = 0, nv = 0;
 };
@@ -102,6 +103,7 @@ struct Lane {
   DBuf fv[2], fq[2], fval[2], ctl, qi, qword, seeds, counts, dany;
   HBuf h_ctl, h_counts, h_dany, h_stage;
   uint32_t cur_buf = 0, cur_cnt = 0, cur_ovf = 0;
+  uint32_t round_abs = 0;  // rounds run so far by this lane (BFS window origin of each request)
   std::vector<Req *> slots;  // slot -> request (nullptr = free)
   std::vector<Req *> fresh;  // admitted, not yet seeded
   std::atomic<int> active{0};
@@ -258,15 +260,19 @@ struct pasgal_server {
         qi[i].dbase = r->dirty_off / 4;
         qi[i].vbase = r->vbase;
         qi[i].nv = r->nv;
+        qi[i].r0 = r->r0;
+        qi[i].pad = 0;
         words += (r->nv + 31) / 32;
       } else {
-        qi[i] = QInfo{0, 0, 0, 0};
+        qi[i] = QInfo{0, 0, 0, 0, 0, 0};
       }
     }
     qword[nslots] = words;
     std::vector<SeedEnt> seeds;
     std::vector<int64_t> segoff, seglen, doff, dlen;
     for (Req *r : L.fresh) {
+      r->r0 = L.round_abs;
+      qi[r->slot].r0 = r->r0;
       for (int k = 0; k < r->r.nsources; k++) {
         SeedEnt e;
         e.v = (uint32_t)(r->vbase + r->r.sources[k]);
@@ -334,13 +340,18 @@ struct pasgal_server {
     a.max_rounds = (uint32_t)opts.slice_rounds;
     a.ring_cap = L.lg.ring;
     a.stage_cap = L.lg.stage;
+    a.min_chunk = vopts.min_chunk;
+    a.window = vopts.window;
+    a.round_base = L.round_abs;
+    a.test_first = vopts.test_first ? 1u : 0u;
     a.timeout_ticks = (long long)vopts.timeout_ms * (long long)dev_info().wall_khz;
     a.ctl = (Ctl *)L.ctl.p;
     if ((e = launch_fill_u32((uint32_t *)L.ctl.p, sizeof(Ctl) / 4, 0u, s)) != hipSuccess) return hip_fail(e);
     if ((e = launch_seed(kind, a, (const SeedEnt *)L.seeds.p, (uint32_t)nseed, L.cur_cnt, L.cur_ovf, s)) !=
         hipSuccess)
       return hip_fail(e);
-    if ((e = launch_vgc(kind, true, a, L.lg.grid, L.lg.block, L.lg.lds, dev_info().coop != 0, s)) != hipSuccess)
+    if ((e = launch_vgc(kind, true, L.lg.pf, a, L.lg.grid, L.lg.block, L.lg.lds, dev_info().coop != 0, s)) !=
+        hipSuccess)
       return hip_fail(e);
     if ((e = hipMemcpyAsync(L.h_ctl.p, L.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s)) != hipSuccess)
       return hip_fail(e);
@@ -351,6 +362,7 @@ struct pasgal_server {
     L.cur_buf = c.final_buf;
     L.cur_cnt = c.final_cnt;
     L.cur_ovf = c.final_ovf;
+    L.round_abs += c.rounds;
     for (Req *r : L.slots)
       if (r) r->rounds += c.rounds;
     // census: which requests still have frontier entries or dirty bits
@@ -447,6 +459,7 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
   if (so.wg_size > 0) po.wg_size = so.wg_size;
   if (so.blocks_per_cu > 0) po.blocks_per_cu = so.blocks_per_cu;
   po.timeout_ms = so.timeout_ms;
+  po.window = so.window;
   if (!opts_valid(&po)) {
     delete s;
     return PASGAL_EINVAL;

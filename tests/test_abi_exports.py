@@ -55,12 +55,12 @@ def test_host_only_calls(lib):
     from paper_2404_17101_amd import _lib as L
     o = L.Opts()
     lib.pasgal_opts_default(ctypes.byref(o))
-    assert (o.mode, o.tau, o.wg_size, o.blocks_per_cu, o.timeout_ms) == (0, 256, 1024, 1, 20000)
+    assert (o.mode, o.tau, o.wg_size, o.blocks_per_cu, o.timeout_ms) == (0, 1024, 1024, 1, 20000)
 
 
 def test_struct_layouts_match_header():
     from paper_2404_17101_amd import _lib as L
     assert ctypes.sizeof(L.Csr) == 24
-    assert ctypes.sizeof(L.Opts) == 40
-    assert ctypes.sizeof(L.Stats) == 72
+    assert ctypes.sizeof(L.Opts) == 48
+    assert ctypes.sizeof(L.Stats) == 80
     assert ctypes.sizeof(L.Request) == 4 * 3 + 64 * 4 + 4 + 8 + 8
