@@ -78,7 +78,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (counter calibration for rocprofv3 runs)")
+    ap.add_argument("--suite", choices=["c1", "c3", "c4", "c5"], default=None,
+                    help="run one of the other configurations instead of the headline job (one JSON line)")
+    ap.add_argument("--rates", default="5,10,20,40,100,300,1000,3000,10000", help="c5: Poisson arrival rates (q/s)")
     args = ap.parse_args()
+
+    if args.suite:
+        import bench_suites
+
+        bench_suites.run(args.suite, args)
+        return
 
     if args.calibrate_copy:
         import torch

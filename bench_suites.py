@@ -1,0 +1,279 @@
+"""The benchmark's other configurations (bench.py --suite c1|c3|c4|c5).
+
+Each suite prints one JSON line. All inputs come from the seeded generators;
+all traversal work runs in libpasgal.so through its C ABI.
+
+  c1  256x256 4-neighbour grid from vertex 0: plain level-synchronous BFS (one
+      launch per level) against the persistent VGC kernel at several tau.
+  c3  4096x4096 road-like directed grid, 64 pivots: forward reach on G and
+      backward reach on G^T (one 64-bit mask word), plain vs VGC; transpose
+      timed separately as preprocessing.
+  c4  256 uneven graphs (128 grids 64..2048 per side, 128 5-NN graphs of 10^4..
+      10^6 points) packed into one CSR, 1024 BFS queries: one autotuned,
+      hipGraph-captured persistent launch vs 1024 plain per-query launches.
+  c5  resident 8192x8192 grid + RMAT scale 24 (edge factor 16, symmetrised):
+      Poisson arrivals of BFS / reach requests from random sources, served by
+      the continuous-batching server; p50/p99 latency and achieved q/s per
+      arrival rate, and one-request-at-a-time throughput for comparison.
+"""
+from __future__ import annotations
+
+import json
+import sys
+import threading
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    sys.stderr.write(f"[suite] {msg}\n")
+    sys.stderr.flush()
+
+
+def _work(offsets, dist):
+    deg = np.diff(offsets).astype(np.int64)
+    r = dist >= 0
+    return int(r.sum()), int(deg[r].sum())
+
+
+def suite_c1(args, pg, gg, torch):
+    g = gg.grid(256, 256)
+    d = pg.DeviceGraph.from_graph(g)
+    out = {}
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    pg.bfs(d, 0, dist_out=dist)
+    nr, mr = _work(g.offsets, dist.cpu().numpy())
+    alg = 16 * nr + 8 * mr
+    for label, kw in [("plain", dict(mode="plain")), ("tau1", dict(tau=1, window=0)),
+                      ("tau64", dict(tau=64, window=0)), ("tau256", dict(tau=256, window=0)),
+                      ("tau1024", dict(tau=1024, window=0)), ("tau4096", dict(tau=4096, window=0)),
+                      ("tau1024_window32", dict(tau=1024, window=32))]:
+        ts, ks = [], []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            _, st = pg.bfs(d, 0, dist_out=dist, stats=True, **kw)
+            ts.append(time.perf_counter() - a)
+            ks.append(st["kernel_ms"])
+        t = float(np.median(ts))
+        out[label] = {"ms": round(t * 1e3, 3), "gteps": round(mr / t / 1e9, 4), "rounds": st["rounds"],
+                      "kernel_ms": round(float(np.median(ks)), 4),
+                      "roofline_frac": round(alg / (float(np.median(ks)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
+    return {"suite": "c1", "workload": "grid 256x256, src 0, BFS", "n": g.n, "m": g.m, "reached_arcs": mr,
+            "results": out}
+
+
+def suite_c3(args, pg, gg, torch):
+    g = gg.road(4096, 3)
+    d = pg.DeviceGraph.from_graph(g)
+    pivots = gg.sources(g, 64, 1003)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    t = pg.transpose(d)
+    torch.cuda.synchronize()
+    t_ms = (time.perf_counter() - a) * 1e3
+    deg = np.diff(g.offsets).astype(np.int64)
+    tdeg = np.diff(t.offsets.cpu().numpy()).astype(np.int64)
+    fw = pg.reach(d, pivots).cpu().numpy().view(np.uint64)[:, 0]
+    bw = pg.reach(t, pivots).cpu().numpy().view(np.uint64)[:, 0]
+    credit = 0
+    for i in range(64):
+        credit += int(deg[((fw >> np.uint64(i)) & np.uint64(1)).astype(bool)].sum())
+        credit += int(tdeg[((bw >> np.uint64(i)) & np.uint64(1)).astype(bool)].sum())
+    out = {}
+    for label, kw in [("plain", dict(mode="plain")), ("tau256", dict(tau=256)), ("tau1024", dict(tau=1024)),
+                      ("tau4096", dict(tau=4096))]:
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            pg.reach(d, pivots, **kw)
+            pg.reach(t, pivots, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - a)
+        el = float(np.median(ts))
+        out[label] = {"ms_forward_plus_backward": round(el * 1e3, 3), "gteps": round(credit / el / 1e9, 3)}
+    return {"suite": "c3", "workload": "road grid 4096x4096 (seed 3), 64 pivots, forward + backward reach",
+            "n": g.n, "m": g.m, "transpose_ms": round(t_ms, 3), "teps_credit_arcs": credit, "results": out}
+
+
+def suite_c4(args, pg, gg, torch):
+    rec = gg.batch_recipe()
+    a = time.perf_counter()
+    graphs = gg.batch_graphs(rec)
+    packed = gg.pack(graphs)
+    _log(f"c4 generated {len(graphs)} graphs n={packed.n} m={packed.m} in {time.perf_counter() - a:.1f}s")
+    pd = pg.DeviceGraph.from_numpy(packed.offsets, packed.targets)
+    qg, qs, qo = [], [], []
+    off = 0
+    for gi, g in enumerate(graphs):
+        for s in gg.sources(g, 4, 1004 + gi):
+            qg.append(gi)
+            qs.append(int(s))
+            qo.append(off)
+            off += g.n
+    nq = len(qg)
+    dist = torch.empty(off, dtype=torch.int32, device="cuda")
+    a = time.perf_counter()
+    b = pg.Batch(pd, packed.vbase, np.array(qg), np.array(qs), np.array(qo, dtype=np.int64), dist, autotune=True)
+    tune_s = time.perf_counter() - a
+    cfg = b.config()
+    b.run()
+    got = dist.cpu().numpy()
+    arcs = 0
+    nverts = 0
+    for j in range(nq):
+        gi = qg[j]
+        r = got[qo[j]:qo[j] + graphs[gi].n] >= 0
+        arcs += int(np.diff(graphs[gi].offsets)[r].sum())
+        nverts += int(r.sum())
+    ts = []
+    for _ in range(3):
+        st = b.run()
+        ts.append(st["device_ms"])
+    b.close()
+    batched_ms = float(np.median(ts))
+    # plain per-query launches: every query through pasgal_bfs in plain mode
+    dgs = [pg.DeviceGraph.from_graph(g) for g in graphs]
+    outs = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g in graphs]
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for j in range(nq):
+        pg.bfs(dgs[qg[j]], qs[j], dist_out=outs[qg[j]], mode="plain")
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - a
+    # the same queries one VGC call at a time
+    a = time.perf_counter()
+    for j in range(nq):
+        pg.bfs(dgs[qg[j]], qs[j], dist_out=outs[qg[j]])
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - a
+    alg = 16 * nverts + 8 * arcs
+    return {"suite": "c4", "workload": "256 graphs (128 grids 64..2048, 128 5-NN 1e4..1e6 points, seed 4), "
+                                       "1024 BFS queries (seed 1004)",
+            "n": packed.n, "m": packed.m, "queries": nq, "autotune_s": round(tune_s, 2), "chosen": cfg,
+            "batched": {"ms": round(batched_ms, 3), "queries_per_s": round(nq / batched_ms * 1e3, 1),
+                        "gteps": round(arcs / batched_ms / 1e6, 3),
+                        "roofline_frac": round(alg / (batched_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
+            "plain_per_query": {"s": round(plain_s, 3), "queries_per_s": round(nq / plain_s, 1),
+                                "gteps": round(arcs / plain_s / 1e9, 3)},
+            "vgc_per_query": {"s": round(single_s, 3), "queries_per_s": round(nq / single_s, 1),
+                              "gteps": round(arcs / single_s / 1e9, 3)},
+            "speedup_batched_vs_plain": round(plain_s * 1e3 / batched_ms, 1)}
+
+
+def suite_c5(args, pg, gg, torch):
+    a = time.perf_counter()
+    grid = gg.grid(8192, 8192)
+    rmat = gg.rmat(24, 16, 5)
+    _log(f"c5 generated grid m={grid.m} rmat m={rmat.m} in {time.perf_counter() - a:.1f}s")
+    dg, dr = pg.DeviceGraph.from_graph(grid), pg.DeviceGraph.from_graph(rmat)
+    graphs = [grid, rmat]
+    rng = np.random.default_rng(1005)
+    deg_r = np.diff(rmat.offsets)
+    pool_r = np.flatnonzero(deg_r > 0)
+
+    def draw(k):
+        reqs = []
+        for _ in range(k):
+            gi = int(rng.integers(2))
+            kind = "bfs" if rng.integers(2) == 0 else "reach"
+            src = int(rng.integers(grid.n)) if gi == 0 else int(pool_r[rng.integers(pool_r.size)])
+            reqs.append((gi, kind, src))
+        return reqs
+
+    # one request at a time through the single-query entry points
+    outs = {(0, "bfs"): torch.empty(grid.n, dtype=torch.int32, device="cuda"),
+            (0, "reach"): torch.empty((grid.n, 1), dtype=torch.int64, device="cuda"),
+            (1, "bfs"): torch.empty(rmat.n, dtype=torch.int32, device="cuda"),
+            (1, "reach"): torch.empty((rmat.n, 1), dtype=torch.int64, device="cuda")}
+    serial = draw(24)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    lat = []
+    for gi, kind, src in serial:
+        t0 = time.perf_counter()
+        dd = dg if gi == 0 else dr
+        if kind == "bfs":
+            pg.bfs(dd, src, dist_out=outs[(gi, kind)])
+        else:
+            pg.reach(dd, [src], label_out=outs[(gi, kind)])
+        lat.append(time.perf_counter() - t0)
+    serial_s = time.perf_counter() - a
+    result = {"suite": "c5", "workload": "resident grid 8192x8192 + RMAT-24 (ef 16, a=0.57, b=c=0.19, seed 5); "
+                                         "50% BFS / 50% reach, 50% per graph, Poisson arrivals (seed 1005)",
+              "one_at_a_time": {"queries_per_s": round(len(serial) / serial_s, 2),
+                                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2)},
+              "rates": []}
+    del outs
+    torch.cuda.empty_cache()
+    srv = pg.Server(max_slots=256, slice_rounds=16)
+    gids = [srv.add_graph(dg), srv.add_graph(dr)]
+    # a few output buffers per (graph, kind), reused round robin: results are copied out like a real reply
+    bufs = {}
+    for gi, g in enumerate(graphs):
+        bufs[(gi, "bfs")] = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(4)]
+        bufs[(gi, "reach")] = [torch.empty(g.n, dtype=torch.int64, device="cuda") for _ in range(4)]
+    rates = [float(x) for x in args.rates.split(",") if x]
+    for rate in rates:
+        count = int(min(max(rate * 3.0, 60), 600))
+        reqs = draw(count)
+        gaps = rng.exponential(1.0 / rate, size=count)
+        done = []
+        t_start = time.perf_counter()
+        submitted = [0]
+
+        def submitter():
+            t = time.perf_counter()
+            for i, (gi, kind, src) in enumerate(reqs):
+                t += gaps[i]
+                while True:
+                    now = time.perf_counter()
+                    if now >= t:
+                        break
+                    time.sleep(min(t - now, 0.002))
+                out = bufs[(gi, kind)][i % 4]
+                while srv.submit(gids[gi], kind, [src], out=out, tag=i) is None:
+                    time.sleep(0.001)
+                submitted[0] += 1
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        deadline = time.perf_counter() + 120.0
+        while (len(done) < count) and time.perf_counter() < deadline:
+            done.extend(srv.poll(4096))
+            time.sleep(0.002)
+        th.join()
+        elapsed = time.perf_counter() - t_start
+        ok = [c for c in done if c["status"] == 0]
+        lats = np.array([c["t_done_ms"] - c["t_submit_ms"] for c in ok])
+        entry = {"offered_qps": rate, "requests": count, "completed": len(ok),
+                 "achieved_qps": round(len(ok) / elapsed, 2),
+                 "p50_ms": round(float(np.percentile(lats, 50)), 2) if lats.size else None,
+                 "p99_ms": round(float(np.percentile(lats, 99)), 2) if lats.size else None,
+                 "queue_wait_p50_ms": round(float(np.percentile([c["t_admit_ms"] - c["t_submit_ms"] for c in ok], 50)),
+                                            2) if ok else None}
+        result["rates"].append(entry)
+        _log(f"c5 rate {rate}: {entry}")
+        if len(done) < count:
+            _log("c5: drain timed out; stopping the sweep")
+            break
+    srv.close()
+    return result
+
+
+def run(name, args):
+    import torch
+
+    import graphgen as gg
+    import paper_2404_17101_amd as pg
+
+    pg.load()
+    torch.cuda.set_device(0)
+    fn = {"c1": suite_c1, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5}[name]
+    out = fn(args, pg, gg, torch)
+    print(json.dumps(out), flush=True)

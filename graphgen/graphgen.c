@@ -453,18 +453,23 @@ int gg_road(int64_t side, double p_del, double p_both, double p_diag, uint64_t s
 /* ----------------------------------------------------------------- RMAT -- */
 
 /* RMAT (Chakrabarti, Zhan, Faloutsos, SDM 2004): m0 = edge_factor * 2^scale
- * edges; for edge e and level l the quadrant is drawn from u01(seed,10,
- * e*scale+l) against (a, a+b, a+b+c). Self-loops dropped, symmetrised,
- * duplicates removed, then vertex ids relabelled by a seeded Fisher-Yates
- * permutation (stream 11). */
-static void rmat_edge(int32_t scale, double a, double b, double c, uint64_t seed, int64_t e, int64_t *u, int64_t *v) {
+ * edges; at each of the scale levels an edge picks a quadrant with
+ * probabilities (a, b, c, 1-a-b-c). Level l of edge e uses the 16-bit field
+ * (l % 4) of rng64(seed, 10, e*ceil(scale/4) + l/4) as a uniform draw in
+ * units of 2^-16. Self-loops dropped, symmetrised, duplicates removed, then
+ * vertex ids relabelled by a seeded Fisher-Yates permutation (stream 11). */
+static void rmat_edge(int32_t scale, uint32_t ta, uint32_t tb, uint32_t tc, uint64_t seed, int64_t e, int64_t *u,
+                      int64_t *v) {
   int64_t uu = 0, vv = 0;
+  const int64_t words = (scale + 3) / 4;
+  uint64_t r = 0;
   for (int l = 0; l < scale; l++) {
-    double p = u01(seed, 10, (uint64_t)e * (uint64_t)scale + (uint64_t)l);
+    if ((l & 3) == 0) r = gg_rng64(seed, 10, (uint64_t)e * (uint64_t)words + (uint64_t)(l >> 2));
+    const uint32_t p = (uint32_t)((r >> (16 * (l & 3))) & 0xFFFFu);
     int bu, bv;
-    if (p < a) { bu = 0; bv = 0; }
-    else if (p < a + b) { bu = 0; bv = 1; }
-    else if (p < a + b + c) { bu = 1; bv = 0; }
+    if (p < ta) { bu = 0; bv = 0; }
+    else if (p < tb) { bu = 0; bv = 1; }
+    else if (p < tc) { bu = 1; bv = 0; }
     else { bu = 1; bv = 1; }
     uu = (uu << 1) | bu;
     vv = (vv << 1) | bv;
@@ -475,48 +480,89 @@ static void rmat_edge(int32_t scale, double a, double b, double c, uint64_t seed
 
 int gg_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c, uint64_t seed, gg_graph *g) {
   memset(g, 0, sizeof(*g));
-  if (scale < 1 || scale > 30 || edge_factor < 1) return -3;
+  if (scale < 1 || scale > 30 || edge_factor < 1 || a < 0 || b < 0 || c < 0 || a + b + c > 1.0) return -3;
   int64_t n = (int64_t)1 << scale;
   int64_t m0 = (int64_t)edge_factor * n;
   if (2 * m0 > ((int64_t)1 << 33)) return -3;
+  const uint32_t ta = (uint32_t)(a * 65536.0 + 0.5), tb = (uint32_t)((a + b) * 65536.0 + 0.5),
+                 tc = (uint32_t)((a + b + c) * 65536.0 + 0.5);
   int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   int64_t *deg = (int64_t *)calloc((size_t)n, sizeof(int64_t));
   int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-  if (!perm || !deg || !start) { free(perm); free(deg); free(start); return -1; }
+  int32_t *eu = (int32_t *)malloc(sizeof(int32_t) * (size_t)m0);
+  int32_t *ev = (int32_t *)malloc(sizeof(int32_t) * (size_t)m0);
+  if (!perm || !deg || !start || !eu || !ev) {
+    free(perm); free(deg); free(start); free(eu); free(ev);
+    return -1;
+  }
   for (int64_t i = 0; i < n; i++) perm[i] = (int32_t)i;
   for (int64_t i = n - 1; i > 0; i--) {
     int64_t j = (int64_t)(gg_rng64(seed, 11, (uint64_t)i) % (uint64_t)(i + 1));
     int32_t t = perm[i]; perm[i] = perm[j]; perm[j] = t;
   }
-  int64_t e;
+  /* per-thread degree histograms: thread t owns edge chunk t in both passes,
+   * so arcs land at precomputed offsets without atomics */
+  int nt = 1;
+#ifdef _OPENMP
+  nt = omp_get_max_threads();
+#endif
+  int32_t *cnt = (int32_t *)calloc((size_t)nt * (size_t)n, sizeof(int32_t));
+  if (!cnt) { free(perm); free(deg); free(start); free(eu); free(ev); return -1; }
+#pragma omp parallel num_threads(nt)
+  {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    const int64_t lo = m0 * t / nt, hi = m0 * (t + 1) / nt;
+    int32_t *ct = cnt + (size_t)t * (size_t)n;
+    for (int64_t e = lo; e < hi; e++) {
+      int64_t u, v;
+      rmat_edge(scale, ta, tb, tc, seed, e, &u, &v);
+      if (u == v) {
+        eu[e] = -1;
+        ev[e] = -1;
+        continue;
+      }
+      eu[e] = perm[u];
+      ev[e] = perm[v];
+      ct[eu[e]]++;
+      ct[ev[e]]++;
+    }
+  }
+  int64_t v0;
 #pragma omp parallel for schedule(static)
-  for (e = 0; e < m0; e++) {
-    int64_t u, v;
-    rmat_edge(scale, a, b, c, seed, e, &u, &v);
-    if (u == v) continue;
-    u = perm[u]; v = perm[v];
-#pragma omp atomic
-    deg[u]++;
-#pragma omp atomic
-    deg[v]++;
+  for (v0 = 0; v0 < n; v0++) {
+    int64_t acc = 0;
+    for (int t = 0; t < nt; t++) {
+      const int32_t c = cnt[(size_t)t * (size_t)n + v0];
+      cnt[(size_t)t * (size_t)n + v0] = (int32_t)acc;
+      acc += c;
+    }
+    deg[v0] = acc;
   }
   int64_t acc = 0;
-  for (int64_t v = 0; v < n; v++) { start[v] = acc; acc += deg[v]; deg[v] = 0; }
+  for (int64_t v = 0; v < n; v++) { start[v] = acc; acc += deg[v]; }
   int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(acc > 0 ? acc : 1));
-  if (!buf) { free(perm); free(deg); free(start); return -1; }
-#pragma omp parallel for schedule(static)
-  for (e = 0; e < m0; e++) {
-    int64_t u, v, pu, pv;
-    rmat_edge(scale, a, b, c, seed, e, &u, &v);
-    if (u == v) continue;
-    u = perm[u]; v = perm[v];
-#pragma omp atomic capture
-    pu = deg[u]++;
-#pragma omp atomic capture
-    pv = deg[v]++;
-    buf[start[u] + pu] = (int32_t)v;
-    buf[start[v] + pv] = (int32_t)u;
+  if (!buf) { free(perm); free(deg); free(start); free(eu); free(ev); free(cnt); return -1; }
+#pragma omp parallel num_threads(nt)
+  {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    const int64_t lo = m0 * t / nt, hi = m0 * (t + 1) / nt;
+    int32_t *ct = cnt + (size_t)t * (size_t)n;
+    for (int64_t e = lo; e < hi; e++) {
+      const int32_t u = eu[e], v = ev[e];
+      if (u < 0) continue;
+      buf[start[u] + ct[u]++] = v;
+      buf[start[v] + ct[v]++] = u;
+    }
   }
+  free(cnt);
+  free(eu);
+  free(ev);
   int rc = compact_rows(n, start, deg, buf, g);
   free(perm); free(deg); free(start); free(buf);
   return rc;

@@ -1,0 +1,165 @@
+"""GPU parity at the full configuration sizes, in the launch configurations
+the benchmark times (tau 1024, window 32, 1024-thread workgroups, one per CU).
+
+Where the oracle is too slow for every query at full size, the check is on
+sampled queries against the oracle plus, for every query, a property that
+holds at any size and characterises the exact answer (closed-form grid
+distances, the BFS certificate, reachability closure).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests import pins
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(300)]
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    sys.stdout.write(f"[case] {msg}\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pg():
+    import paper_2404_17101_amd as pg_
+    pg_.load()
+    return pg_
+
+
+@pytest.fixture(scope="module")
+def knn10m():
+    return gg.knn(10_000_000, 5, 2, layout="morton")
+
+
+def test_c2_knn10m_batched16_and_reach16(pg, knn10m):
+    g = knn10m
+    srcs = [int(s) for s in gg.sources(g, 16, 1002)]
+    d = pg.DeviceGraph.from_graph(g)
+    n = g.n
+    dist16 = torch.empty(16 * n, dtype=torch.int32, device="cuda")
+    _say("c2 batched16")
+    b = pg.Batch(d, np.array([0, n], np.int32), np.zeros(16, np.int32), np.array(srcs, np.int32),
+                 np.arange(16, dtype=np.int64) * n, dist16)
+    b.run()
+    got = dist16.view(16, n).cpu().numpy()
+    b.close()
+    _say("c2 reach16")
+    mask = pg.reach(d, srcs).cpu().numpy().view(np.uint64)[:, 0]
+    for i in range(3):
+        _say(f"c2 oracle source {i}")
+        exp = oracle.bfs(g, srcs[i])
+        assert np.array_equal(got[i], exp), i
+        assert np.array_equal(((mask >> np.uint64(i)) & np.uint64(1)).astype(bool), exp >= 0), i
+    for i in range(16):
+        assert pins.bfs_certificate_ok(g, srcs[i], got[i]), i
+        # reach bit i is exactly the BFS-reached set of source i
+        assert np.array_equal(((mask >> np.uint64(i)) & np.uint64(1)).astype(bool), got[i] >= 0), i
+    assert pins.reach_closure_ok(g, srcs, mask.reshape(-1, 1))
+
+
+def test_c2_knn10m_single_source_calls(pg, knn10m):
+    g = knn10m
+    s = int(gg.sources(g, 16, 1002)[5])
+    d = pg.DeviceGraph.from_graph(g)
+    exp = oracle.bfs(g, s)
+    for kw in [dict(), dict(tau=4096, window=64), dict(mode="plain")]:
+        _say(f"c2 single {kw}")
+        assert np.array_equal(pg.bfs(d, s, **kw).cpu().numpy(), exp)
+    assert np.array_equal(pg.reach(d, [s]).cpu().numpy().view(np.uint64)[:, 0] == 1, exp >= 0)
+
+
+def test_c3_road4096_forward_backward_scc(pg):
+    g = gg.road(4096, 3)
+    d = pg.DeviceGraph.from_graph(g)
+    _say("c3 transpose")
+    t = pg.transpose(d)
+    t_off, t_tgt = oracle.transpose(g)
+    assert np.array_equal(t.offsets.cpu().numpy(), t_off)
+    gt = gg.Graph(t_off, t_tgt)
+    pivots = gg.sources(g, 64, 1003)
+    _say("c3 forward/backward reach")
+    fw = pg.reach(d, pivots).cpu().numpy().view(np.uint64)[:, 0]
+    bw = pg.reach(t, pivots).cpu().numpy().view(np.uint64)[:, 0]
+    # sampled pivots against the oracle, all pivots through closure + SCC partition
+    for i in [0, 17, 63]:
+        _say(f"c3 oracle pivot {i}")
+        ef = oracle.bfs(g, int(pivots[i])) >= 0
+        eb = oracle.bfs(gt, int(pivots[i])) >= 0
+        assert np.array_equal(((fw >> np.uint64(i)) & np.uint64(1)).astype(bool), ef), i
+        assert np.array_equal(((bw >> np.uint64(i)) & np.uint64(1)).astype(bool), eb), i
+    assert pins.reach_closure_ok(g, pivots, fw.reshape(-1, 1))
+    assert pins.reach_closure_ok(gt, pivots, bw.reshape(-1, 1))
+    _say("c3 tarjan")
+    comp = oracle.scc(g)
+    both = fw & bw
+    for i, p in enumerate(pivots):
+        sel = ((both >> np.uint64(i)) & np.uint64(1)).astype(bool)
+        assert np.array_equal(sel, comp == comp[p]), i
+
+
+def test_c4_batch_1024_queries_uneven_graphs(pg):
+    rec = gg.batch_recipe()
+    _say("c4 generate")
+    graphs = gg.batch_graphs(rec)
+    packed = gg.pack(graphs)
+    pd = pg.DeviceGraph.from_numpy(packed.offsets, packed.targets)
+    qg, qs, qo = [], [], []
+    off = 0
+    for gi, g in enumerate(graphs):
+        for s in gg.sources(g, 4, 1004 + gi):
+            qg.append(gi)
+            qs.append(int(s))
+            qo.append(off)
+            off += g.n
+    dist = torch.empty(off, dtype=torch.int32, device="cuda")
+    _say(f"c4 batch of {len(qg)} queries, {packed.n} vertices, {packed.m} arcs")
+    b = pg.Batch(pd, packed.vbase, np.array(qg), np.array(qs), np.array(qo, dtype=np.int64), dist)
+    b.run()
+    got = dist.cpu().numpy()
+    b.close()
+    checked = 0
+    for j in range(len(qg)):
+        kind = rec[qg[j]]
+        g = graphs[qg[j]]
+        out = got[qo[j]:qo[j] + g.n]
+        if kind[0] == "grid":
+            side = kind[1]
+            r, c = np.divmod(np.arange(g.n), side)
+            r0, c0 = divmod(qs[j], side)
+            assert np.array_equal(out, np.abs(r - r0) + np.abs(c - c0)), j
+        elif j % 16 == 0 or g.n < 30000:
+            assert np.array_equal(out, oracle.bfs(g, qs[j])), j
+            checked += 1
+        else:
+            assert pins.bfs_certificate_ok(g, qs[j], out), j
+    assert checked > 0
+
+
+def test_c5_grid8192_closed_form_and_rmat24_sample(pg):
+    side = 8192
+    g = gg.grid(side, side)
+    assert (g.n, g.m) == (67108864, 268402688)
+    d = pg.DeviceGraph.from_graph(g)
+    r, c = np.divmod(np.arange(g.n, dtype=np.int64), side)
+    for s in [0, int(gg.sources(g, 1, 1005)[0])]:
+        _say(f"c5 grid src={s}")
+        got = pg.bfs(d, s).cpu().numpy()
+        r0, c0 = divmod(s, side)
+        assert np.array_equal(got, (np.abs(r - r0) + np.abs(c - c0)).astype(np.int32)), s
+    del d, g, r, c
+    torch.cuda.empty_cache()
+    _say("c5 rmat24 generate")
+    x = gg.rmat(24, 16, 5)
+    dx = pg.DeviceGraph.from_graph(x)
+    s = int(gg.sources(x, 1, 1005, min_degree=1)[0])
+    _say(f"c5 rmat24 src={s} n={x.n} m={x.m}")
+    exp = oracle.bfs(x, s)
+    assert np.array_equal(pg.bfs(dx, s).cpu().numpy(), exp)
+    assert np.array_equal(pg.bfs(dx, s, mode="plain").cpu().numpy(), exp)
+    got = pg.reach(dx, [s]).cpu().numpy().view(np.uint64)[:, 0]
+    assert np.array_equal(got == 1, exp >= 0)
