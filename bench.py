@@ -61,6 +61,88 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def _counter_means(path):
+    import collections
+    import csv
+
+    agg = collections.defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def summarize_profiles(d, args):
+    """Turn the rocprofv3 CSVs of the trace, counter and copy-calibration runs
+    into the committed summaries under profiles/."""
+    import csv
+
+    kb = "void pg::vgc_kernel<0, true, false>(pg::VgcArgs)"
+    kr = "void pg::vgc_kernel<1, false, false>(pg::VgcArgs)"
+    cp = "__amd_rocclr_copyBuffer"
+    rows = list(csv.DictReader(open(os.path.join(d, "prof_trace", "run_kernel_stats.csv"))))
+    F = _counter_means(os.path.join(d, "prof_fetch", "run_counter_collection.csv"))
+    W = _counter_means(os.path.join(d, "prof_write", "run_counter_collection.csv"))
+    CF = _counter_means(os.path.join(d, "prof_cfetch", "run_counter_collection.csv"))
+    CW = _counter_means(os.path.join(d, "prof_cwrite", "run_counter_collection.csv"))
+    f_scale = (1 << 30) / (CF[cp] * 1024)
+    w_scale = (1 << 30) / (CW[cp] * 1024)
+    traffic_b = F[kb] * 1024 * f_scale + W[kb] * 1024 * w_scale
+    traffic_r = F[kr] * 1024 * f_scale + W[kr] * 1024 * w_scale
+    avg = {r["Name"]: float(r["AverageNs"]) / 1e6 for r in rows}
+    out = {"kernel": kb, "kernel_hash": kernel_source_hash(), "layout": args.layout, "tau": args.tau,
+           "window": args.window, "fetch_kib_per_dispatch": round(F[kb], 1), "write_kib_per_dispatch": round(W[kb], 1),
+           "copy_calibration": {"fetch_kib_per_1GiB_copy": round(CF[cp], 1), "write_kib_per_1GiB_copy": round(CW[cp], 1),
+                                "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)},
+           "hbm_bytes_per_launch": int(traffic_b), "kernel_avg_ms": round(avg.get(kb, 0.0), 4),
+           "reach16_kernel": kr, "reach16_fetch_kib": round(F[kr], 1), "reach16_write_kib": round(W[kr], 1),
+           "reach16_hbm_bytes_per_launch": int(traffic_r), "reach16_avg_ms": round(avg.get(kr, 0.0), 4)}
+    prof = os.path.join(ROOT, "profiles")
+    with open(os.path.join(prof, "vgc_bfs_batched16_knn10m_counters.txt"), "w") as f:
+        f.write(json.dumps(out, indent=1) + "\n")
+    lines = ["# Kernel trace: batched 16-source BFS + 16-source reach on the 10M-point 5-NN graph", "",
+             "Command (GPU host, `TMPDIR=/tmp`, run from `/tmp`):", "", "```",
+             "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_trace -o run -- \\",
+             "    python3 <repo>/bench.py --steps 2 --warmup 1 --no-extras --no-cpu", "```", "",
+             f"Summarised by `python bench.py --summarize-profiles <out>`. Workload: directed 5-NN graph of 10^7 "
+             f"uniform points ({args.layout} layout), 16 sources; each step is one batched VGC BFS launch (16 "
+             f"queries, tau {args.tau}, window {args.window}) and one 16-source VGC reach launch; 1 warm-up + 2 "
+             f"timed steps. rocprofv3 may end with a segmentation fault in its own exit handler after the "
+             f"program's last line; the CSV files were complete.", "",
+             "| kernel | calls | avg (ms) | min (ms) | max (ms) | share |", "|---|---|---|---|---|---|"]
+    for r in rows[:8]:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 70:
+            name = name[:67] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                     f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |")
+    lines += ["", "`vgc_kernel<0, true, false>` is the multi-query BFS kernel (kind 0 = BFS, multi-query, no arc-range "
+                  "prefetch); `vgc_kernel<1, false, false>` is the single-query reach kernel, run with a 16-bit mask. "
+                  "`__amd_rocclr_copyBuffer` dispatches are the graph upload before the timed steps."]
+    with open(os.path.join(prof, "vgc_bfs_batched16_knn10m_trace.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    lines = ["# HBM traffic counters: batched 16-source BFS kernel and 16-source reach kernel", "",
+             "Commands (GPU host, `TMPDIR=/tmp`, run from `/tmp`; one counter per pass):", "", "```",
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/prof_fetch -o run -- \\",
+             "    python3 <repo>/bench.py --steps 1 --warmup 1 --no-extras --no-cpu",
+             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/prof_write -o run -- \\",
+             "    python3 <repo>/bench.py --steps 1 --warmup 1 --no-extras --no-cpu",
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/prof_cfetch -o run -- python3 <repo>/bench.py --calibrate-copy",
+             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/prof_cwrite -o run -- python3 <repo>/bench.py --calibrate-copy",
+             "```", "", "Per dispatch (KiB as reported), averaged over the dispatches of each kernel:", "",
+             "| kernel | FETCH_SIZE | WRITE_SIZE | HBM bytes (calibrated) |", "|---|---|---|---|",
+             f"| `vgc_kernel<0, true, false>` (BFS, 16 queries) | {F[kb]:,.1f} | {W[kb]:,.1f} | {traffic_b / 1e9:.2f} GB |",
+             f"| `vgc_kernel<1, false, false>` (reach, k = 16) | {F[kr]:,.1f} | {W[kr]:,.1f} | {traffic_r / 1e9:.2f} GB |",
+             f"| `{cp}`, 1 GiB copy (calibration) | {CF[cp]:,.1f} | {CW[cp]:,.1f} | 2.15 GB |", "",
+             f"Calibration: a plain 1 GiB copy reads and writes 1 GiB; the counters report {CF[cp] / 1048576:.3f} GiB and "
+             f"{CW[cp] / 1048576:.3f} GiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.",
+             "", "`vgc_bfs_batched16_knn10m_counters.txt` holds these figures with the hash of the kernel source they "
+                 "were taken on; bench.py reports `traffic` only while that hash matches the current source."]
+    with open(os.path.join(prof, "vgc_bfs_batched16_knn10m_counters.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,7 +163,14 @@ def main():
     ap.add_argument("--suite", choices=["c1", "c3", "c4", "c5"], default=None,
                     help="run one of the other configurations instead of the headline job (one JSON line)")
     ap.add_argument("--rates", default="5,10,20,40,100,300,1000,3000,10000", help="c5: Poisson arrival rates (q/s)")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="write profiles/ summaries from rocprofv3 CSV output under DIR (prof_trace, prof_fetch, "
+                         "prof_write, prof_cfetch, prof_cwrite)")
     args = ap.parse_args()
+
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args)
+        return
 
     if args.suite:
         import bench_suites

@@ -69,6 +69,9 @@ typedef struct pasgal_csr {
                                       relaxing atomic is in flight (default: loaded when the entry is expanded) */
 #define PASGAL_FLAG_TEST_FIRST 8u  /* VGC: read a target's state before the atomic and skip the atomic when
                                       the relaxation cannot change it */
+#define PASGAL_FLAG_ROW_PER_LANE 16u /* VGC: scan rows of <= 8 arcs lane by lane instead of dealing every
+                                        vertex's arcs out across the wavefront (default: consecutive lanes take
+                                        consecutive arcs, so one memory instruction touches few cache lines) */
 
 typedef struct pasgal_opts {
   int32_t mode;              /* PASGAL_MODE_VGC or PASGAL_MODE_PLAIN */

@@ -87,7 +87,8 @@ def _stream_ptr(stream) -> int:
 
 
 def _opts(mode="vgc", tau=1024, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
-          stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=False, test_first=False) -> L.Opts:
+          stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=False, test_first=False,
+          spread_arcs=True) -> L.Opts:
     """window: BFS distance window per round (0 or negative = none)."""
     o = L.Opts()
     L.load().pasgal_opts_default(ctypes.byref(o))
@@ -97,7 +98,8 @@ def _opts(mode="vgc", tau=1024, wg_size=1024, blocks_per_cu=1, frontier_capacity
     o.blocks_per_cu = int(blocks_per_cu)
     o.frontier_capacity = int(frontier_capacity)
     o.flags = ((L.FLAG_VALIDATE if validate else 0) | (L.FLAG_ASYNC if asynchronous else 0) |
-               (L.FLAG_PREFETCH if prefetch else 0) | (L.FLAG_TEST_FIRST if test_first else 0))
+               (L.FLAG_PREFETCH if prefetch else 0) | (L.FLAG_TEST_FIRST if test_first else 0) |
+               (0 if spread_arcs else L.FLAG_ROW_PER_LANE))
     o.timeout_ms = int(timeout_ms)
     o.stream = _stream_ptr(stream)
     o.window = int(window) if int(window) > 0 else -1

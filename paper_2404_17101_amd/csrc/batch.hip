@@ -87,6 +87,7 @@ struct pasgal_batch {
     args.min_chunk = o.min_chunk;
     args.window = o.window;
     args.test_first = o.test_first ? 1u : 0u;
+    args.lane_arcs = o.lane_arcs;
     args.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
     return PASGAL_OK;
   }

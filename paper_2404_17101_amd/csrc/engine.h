@@ -55,6 +55,7 @@ struct Opts {
   uint32_t min_chunk = 1;
   bool prefetch = false;
   bool test_first = false;
+  uint32_t lane_arcs = 0;
 };
 
 struct LaunchGeom {

@@ -153,6 +153,7 @@ Opts resolve_opts(const pasgal_opts *o) {
   r.min_chunk = o->min_chunk > 0 ? (uint32_t)std::min(o->min_chunk, 64) : 1u;
   r.prefetch = (o->flags & PASGAL_FLAG_PREFETCH) != 0;
   r.test_first = (o->flags & PASGAL_FLAG_TEST_FIRST) != 0;
+  r.lane_arcs = (o->flags & PASGAL_FLAG_ROW_PER_LANE) ? 8u : 0u;
   return r;
 }
 
@@ -302,6 +303,7 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   a.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
   a.round_base = 0;
   a.test_first = o.test_first ? 1u : 0u;
+  a.lane_arcs = o.lane_arcs;
   a.ctl = (Ctl *)w.ctl.p;
 
   if ((e = hipEventRecord(w.ev0, s)) != hipSuccess) return hip_fail(e);

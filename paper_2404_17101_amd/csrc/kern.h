@@ -82,6 +82,9 @@ struct VgcArgs {
                           // (round_base + r + 1 - qi[q].r0) * window; 0 = no limit
   uint32_t round_base;    // absolute number of the launch's first round
   uint32_t test_first;    // plain load before each atomic to skip relaxations that cannot succeed
+  uint32_t lane_arcs;     // rows of at most this many arcs (<= 8) are scanned lane by lane; longer rows, or
+                          // every row when 0, are dealt out across the wavefront (consecutive lanes take
+                          // consecutive arcs)
   long long timeout_ticks;
   Ctl *ctl;
 };

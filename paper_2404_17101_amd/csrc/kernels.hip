@@ -161,6 +161,7 @@ struct Wave {
   uint32_t head, tail, scount;
   uint32_t nslot, nbuf;
   uint32_t rabs;   // absolute number of the current round (BFS window)
+  uint32_t root_end;  // local-queue positions below this hold the current search's roots
   unsigned long long st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale;
 
   __device__ __forceinline__ Wave(const VgcArgs &args, uint8_t *lds_wave) : a(args) {
@@ -189,6 +190,7 @@ struct Wave {
     head = tail = scount = 0;
     nslot = nbuf = 0;
     rabs = 0;
+    root_end = 0;
     st_expand = st_arcs = st_success = st_publish = st_overflow = st_stale = 0;
   }
 
@@ -328,10 +330,11 @@ struct Wave {
   }
 
   // Relax arc (., w) with value val of its tail; returns whether the state of
-  // w changed and the value to carry. With a.test_first, a plain load first
-  // rules out relaxations that cannot change anything (values only ever go
-  // down for BFS / gain bits for reach, so a stale read is still a safe
-  // filter). With PF the arc range of w is loaded alongside.
+  // w changed and the value to carry. With a.test_first, a coherent load
+  // first rules out relaxations that cannot change anything (values only
+  // ever go down for BFS / gain bits for reach, so a value read before a
+  // concurrent update is still a safe filter): loads sustain about 2.5x the
+  // rate of atomics. With PF the arc range of w is loaded alongside.
   __device__ __forceinline__ bool relax(int64_t sb, uint32_t w, Val val, Val &nv, int32_t &nb, int32_t &ne) {
     if (PF) {
       nb = a.off[w];
@@ -341,14 +344,14 @@ struct Wave {
       const uint32_t nd = (uint32_t)val + 1u;
       nv = (Val)nd;
       uint32_t *p = (uint32_t *)&state[sb + w];
-      if (a.test_first && __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= nd) return false;
+      if (a.test_first && ld_ag(p) <= nd) return false;
       const uint32_t old = min_ag(p, nd);
       return nd < old;
     } else {
       unsigned long long *p = (unsigned long long *)&state[sb + w];
       const unsigned long long m = (unsigned long long)val;
       if (a.test_first) {
-        const unsigned long long cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const unsigned long long cur = ld_ag(p);
         if ((cur & m) == m) {
           nv = (Val)cur;
           return false;
@@ -363,13 +366,13 @@ struct Wave {
   // Expand the active lanes' entries: scan out-arcs, relax, push successes.
   // Returns the number of entries expanded (not stale).
   __device__ __forceinline__ uint32_t expand(bool act, uint32_t v, uint32_t q, Val val, bool ring_ok, int32_t b = 0, int32_t e = 0,
-                             bool have_range = false) {
+                             bool have_range = false, bool check_stale = true) {
     const int64_t sb = (act && MULTI) ? sbase_of(q) : 0;
     if (act && !have_range) {
       b = a.off[v];
       e = a.off[v + 1];
     }
-    if (KIND == KIND_BFS && act) {
+    if (KIND == KIND_BFS && act && check_stale) {
       // a smaller distance is already known: another entry carries it
       const uint32_t cur = ld_ag((uint32_t *)&state[sb + v]);
       if (cur < (uint32_t)val) act = false;
@@ -380,7 +383,7 @@ struct Wave {
     const uint32_t deg = act ? (uint32_t)(e - b) : 0u;
     const uint32_t maxd = wave_max(deg);
     if (maxd == 0) return nexp;
-    if (maxd <= 8) {
+    if (maxd <= a.lane_arcs) {
       int32_t w[8];
 #pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) w[u] = ((uint32_t)u < deg) ? a.tgt[b + u] : 0;
@@ -473,7 +476,11 @@ struct Wave {
       head += k;
     else
       tail -= k;
-    const uint32_t ne = expand(act, v, q, val, ring_ok, b, e, PF);
+    // With the window, entries pushed by this very search are rarely stale;
+    // the coherent re-read of the distance is kept for roots and for the
+    // windowless schedule, where overlapping searches make staleness common.
+    const bool chk = (a.window == 0) || (idx < root_end);
+    const uint32_t ne = expand(act, v, q, val, ring_ok, b, e, PF, chk);
     st_stale += (uint32_t)__popcll(__ballot(act)) - ne;
     return ne;
   }
@@ -512,6 +519,23 @@ struct Wave {
     head = tail = 0;
   }
 
+  // Append the lanes' roots to the (not yet wrapped) local queue.
+  __device__ __forceinline__ void append_roots(bool has, uint32_t v, uint32_t q, Val val) {
+    const unsigned long long bal = __ballot(has);
+    const uint32_t pos = tail + mbcnt64(bal);
+    if (has) {
+      rv[pos] = v;
+      rval[pos] = val;
+      if (MULTI) rq[pos] = q;
+      if (PF) {
+        rb[pos] = a.off[v];
+        re[pos] = a.off[v + 1];
+      }
+    }
+    wave_sync();
+    tail += __popcll(bal);
+  }
+
   __device__ __forceinline__ void load_roots(bool has, uint32_t v, uint32_t q, Val val) {
     const unsigned long long bal = __ballot(has);
     const uint32_t pos = mbcnt64(bal);
@@ -532,28 +556,36 @@ struct Wave {
   // Frontier entries are dealt out statically: chunk c of `chunk` consecutive
   // entries goes to wavefront c mod total (gw numbers wavefronts so that each
   // XCD holds a contiguous range). Consecutive entries were published together
-  // by one local search, so a wavefront's roots are close in the graph.
-  __device__ __forceinline__ void process_frontier(uint32_t cbuf, uint32_t nproc, uint32_t chunk, uint32_t gw, uint32_t total) {
+  // by one local search, so a wavefront's roots are close in the graph. A
+  // chunk may hold more roots than lanes (up to half the ring): they all start
+  // one local search, which then advances a wide front per step instead of
+  // several narrow searches one after another.
+  __device__ __forceinline__ void process_frontier(uint32_t cbuf, uint32_t nproc, uint32_t chunk, uint32_t gw,
+                                                   uint32_t total) {
     const uint32_t nchunks = (nproc + chunk - 1) / chunk;
     for (uint32_t c = gw; c < nchunks; c += total) {
       const uint32_t base = c * chunk;
       const uint32_t cnt = min(chunk, nproc - base);
-      bool has = ln < cnt;
-      uint32_t v = 0, q = 0;
-      Val val = 0;
-      if (has) {
-        v = ld_ag(&a.fr.v[cbuf][base + ln]);
-        if (MULTI) q = ld_ag(&a.fr.q[cbuf][base + ln]);
-        val = (Val)ld_ag(&a.fr.val[cbuf][base + ln]);
+      head = tail = 0;
+      for (uint32_t j = 0; j < cnt; j += 64) {
+        bool has = j + ln < cnt;
+        uint32_t v = 0, q = 0;
+        Val val = 0;
+        if (has) {
+          v = ld_ag(&a.fr.v[cbuf][base + j + ln]);
+          if (MULTI) q = ld_ag(&a.fr.q[cbuf][base + j + ln]);
+          val = (Val)ld_ag(&a.fr.val[cbuf][base + j + ln]);
+        }
+        if (KIND == KIND_BFS && a.window) {  // roots beyond the window wait for a later round
+          const bool defer = has && (uint32_t)val >= limit_of(q);
+          push_stage(defer, v, q, val);
+          has = has && !defer;
+        }
+        append_roots(has, v, q, val);
       }
-      if (KIND == KIND_BFS && a.window) {  // roots beyond the window wait for a later round
-        const bool defer = has && (uint32_t)val >= limit_of(q);
-        push_stage(defer, v, q, val);
-        has = has && !defer;
-      }
-      const uint32_t nroots = __popcll(__ballot(has));
+      const uint32_t nroots = tail - head;
       if (nroots == 0) continue;
-      load_roots(has, v, q, val);
+      root_end = tail;
       local_search(a.tau * nroots);
     }
   }
@@ -606,6 +638,7 @@ struct Wave {
         const uint32_t c = __popcll(__ballot(go));
         if (c == 0) continue;
         load_roots(go, v, q, val);
+        root_end = tail;
         local_search(a.tau * c);
       }
     }
@@ -662,7 +695,7 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
     if (ovf) wv.process_dirty(gw, total_waves);
     const uint32_t nproc = min(ncur, a.fr.cap);
     uint32_t chunk = (nproc + total_waves - 1) / total_waves;
-    chunk = min(max(chunk, max(a.min_chunk, 1u)), 64u);
+    chunk = min(max(chunk, max(a.min_chunk, 1u)), a.ring_cap / 2);
     wv.process_frontier(cbuf, nproc, chunk, gw, total_waves);
     wv.flush_stage_block(s_cnt, wid, nw);
     grid_barrier(a.ctl, epoch, deadline, nslot, &hdr);

@@ -344,6 +344,7 @@ struct pasgal_server {
     a.window = vopts.window;
     a.round_base = L.round_abs;
     a.test_first = vopts.test_first ? 1u : 0u;
+    a.lane_arcs = vopts.lane_arcs;
     a.timeout_ticks = (long long)vopts.timeout_ms * (long long)dev_info().wall_khz;
     a.ctl = (Ctl *)L.ctl.p;
     if ((e = launch_fill_u32((uint32_t *)L.ctl.p, sizeof(Ctl) / 4, 0u, s)) != hipSuccess) return hip_fail(e);
