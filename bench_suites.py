@@ -11,6 +11,11 @@ all traversal work runs in libpasgal.so through its C ABI.
   c4  256 uneven graphs (128 grids 64..2048 per side, 128 5-NN graphs of 10^4..
       10^6 points) packed into one CSR, 1024 BFS queries: one autotuned,
       hipGraph-captured persistent launch vs 1024 plain per-query launches.
+  scc strongly connected components (batched forward/backward VGC reach) of
+      the c3 road graph, the c2 10M-point 5-NN graph and an RMAT-20 graph:
+      VGC against tau = 1 (one BFS level per round), and with the trimming and
+      weak-connectivity additions switched off; Tarjan's sequential algorithm
+      (the CPU oracle, one core) is timed beside it as the CPU baseline.
   c5  resident 8192x8192 grid + RMAT scale 24 (edge factor 16, symmetrised):
       Poisson arrivals of BFS / reach requests from random sources, served by
       the continuous-batching server; p50/p99 latency and achieved q/s per
@@ -98,6 +103,54 @@ def suite_c3(args, pg, gg, torch):
         out[label] = {"ms_forward_plus_backward": round(el * 1e3, 3), "gteps": round(credit / el / 1e9, 3)}
     return {"suite": "c3", "workload": "road grid 4096x4096 (seed 3), 64 pivots, forward + backward reach",
             "n": g.n, "m": g.m, "transpose_ms": round(t_ms, 3), "teps_credit_arcs": credit, "results": out}
+
+
+def _cpu_baseline_scc(g):
+    """Tarjan's algorithm from the CPU oracle, one core: the baseline column."""
+    import oracle
+
+    a = time.perf_counter()
+    comp = oracle.scc_min_label(g)
+    return time.perf_counter() - a, comp
+
+
+def suite_scc(args, pg, gg, torch):
+    graphs = [("road4096", lambda: gg.road(4096, 3)), ("knn10m", lambda: gg.knn(10_000_000, 5, 2, layout="morton")),
+              ("rmat20", lambda: gg.rmat(20, 16, 5))]
+    res = []
+    for name, make in graphs:
+        g = make()
+        d = pg.DeviceGraph.from_graph(g)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        t = pg.transpose(d)
+        torch.cuda.synchronize()
+        t_ms = (time.perf_counter() - a) * 1e3
+        cpu_s, exp = _cpu_baseline_scc(g)
+        entry = {"graph": name, "n": g.n, "m": g.m, "transpose_ms": round(t_ms, 3),
+                 "cpu_baseline": {"tarjan_ms": round(cpu_s * 1e3, 1), "cores": 1, "kind": "oracle"}, "gpu": {}}
+        for label, kw in [("vgc", dict()), ("tau1", dict(mode="plain")), ("no_trim", dict(trim_rounds=0)),
+                          ("no_split", dict(split=False))]:
+            ts, st = [], None
+            for _ in range(3):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                comp, st = pg.scc(d, transpose=t, stats=True, **kw)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - a)
+            ok = bool(np.array_equal(comp.cpu().numpy(), exp))
+            el = float(np.median(ts))
+            entry["gpu"][label] = {"ms": round(el * 1e3, 2), "matches_oracle": ok,
+                                   "speedup_vs_tarjan": round(cpu_s / el, 2),
+                                   "reach_ms": round(st["reach_ms"], 2), "batches": st["batches"],
+                                   "pivots": st["pivots"], "rounds": st["rounds"], "trimmed": st["trimmed"],
+                                   "components": st["components"]}
+            _log(f"scc {name} {label}: {entry['gpu'][label]}")
+        res.append(entry)
+        del d, t
+        torch.cuda.empty_cache()
+    return {"suite": "scc", "workload": "SCC of road4096 (seed 3), knn 10M/5 (seed 2), RMAT-20 (ef 16, seed 5)",
+            "results": res}
 
 
 def suite_c4(args, pg, gg, torch):
@@ -274,6 +327,6 @@ def run(name, args):
 
     pg.load()
     torch.cuda.set_device(0)
-    fn = {"c1": suite_c1, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5}[name]
+    fn = {"c1": suite_c1, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "scc": suite_scc}[name]
     out = fn(args, pg, gg, torch)
     print(json.dumps(out), flush=True)

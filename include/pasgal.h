@@ -50,6 +50,7 @@ extern "C" {
 #define PASGAL_EAGAIN (-6)    /* server: no room for the request right now (non-blocking submit) */
 #define PASGAL_ETIMEOUT (-7)  /* a device-side bounded wait expired (e.g. grid barrier); results invalid */
 #define PASGAL_ENOTFOUND (-8) /* server: unknown request or graph id */
+#define PASGAL_EINTERNAL (-9) /* an internal consistency check failed (a library bug); outputs invalid */
 
 /* Graph in device memory. */
 typedef struct pasgal_csr {
@@ -139,6 +140,57 @@ int pasgal_transpose(const pasgal_csr *g, int32_t *t_offsets, int32_t *t_targets
 /* Device-side CSR check (monotone offsets, offsets[0]=0, offsets[n]=m,
  * targets in range). Returns PASGAL_OK or PASGAL_ECSR. */
 int pasgal_validate(const pasgal_csr *g, const pasgal_opts *opts);
+
+/* --------------------------------------------------------------------- SCC --
+ * Strongly connected components (Parallel SCC section): reachability searches
+ * from batches of pivots. Pivots are taken in a random vertex order, in
+ * batches of 1, 2, 4, ... positions (a settled vertex is skipped). For every
+ * pivot p a forward search (along out-arcs) and a backward search (along
+ * in-arcs) run; a vertex found both ways from p belongs to p's component.
+ * Every other vertex moves to the subproblem named by its old subproblem and
+ * the sets of pivots that reached it forward and backward; vertices of one
+ * component always agree on these, and later searches stay inside one
+ * subproblem. All forward and backward searches of a batch run together in
+ * one persistent VGC reach launch (PASGAL_MODE_PLAIN: tau = 1, one BFS level
+ * per round, in the same launch). Trimming, an addition to the paper's
+ * description: a vertex with no in-arc or no out-arc left inside its
+ * subproblem is a component by itself. */
+typedef struct pasgal_scc_stats {
+  int64_t components;   /* strongly connected components */
+  int64_t trimmed;      /* vertices settled by trimming */
+  int64_t pivots;       /* pivots whose forward and backward searches ran */
+  int64_t batches;      /* reach launches (pivot batches, repeats included) */
+  int64_t rounds;       /* VGC rounds summed over the reach launches */
+  int64_t arcs_scanned; /* arcs relaxed by the searches */
+  double device_ms;     /* whole call on the stream, transpose included when built here */
+  double reach_ms;      /* inside the reach launches */
+} pasgal_scc_stats;
+
+#define PASGAL_SCC_NO_SPLIT 1u /* keep subproblems whole instead of cutting each into its weakly connected
+                                  pieces after every batch (an addition to the paper's description: a
+                                  component never spans two pieces, and small pieces each get their own
+                                  64 pivots per batch) */
+
+typedef struct pasgal_scc_opts {
+  int32_t trim_rounds; /* trimming passes before the first batch (the loop stops at a pass that settles
+                          nothing), plus one pass after every batch; < 0 selects 8, 0 disables trimming */
+  uint32_t flags;      /* PASGAL_SCC_* */
+  uint32_t seed;       /* key of the random pivot order; 0 selects a fixed default. The result does not
+                          depend on it. */
+  int32_t reserved;    /* 0 */
+} pasgal_scc_opts;
+
+/* comp_out: device, n int32, written entirely: comp_out[v] = the smallest
+ * vertex id of v's strongly connected component (so comp_out[v] <= v, and
+ * comp_out[v] == v for exactly one vertex per component). gt: G^T as
+ * pasgal_transpose builds it, or NULL to build it inside the call (4(n+1)+4m
+ * bytes more). scc_opts, opts and stats may be NULL (defaults). Limits:
+ * n < 2^30 and m < 2^30 (the forward and backward graphs are packed into one
+ * CSR of 2n vertices). Device memory used: about 80n + 16m bytes plus the
+ * frontier buffers (24 bytes per entry, 4n entries by default). Synchronous
+ * on opts->stream (PASGAL_FLAG_ASYNC is rejected). */
+int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *comp_out, const pasgal_scc_opts *scc_opts,
+               const pasgal_opts *opts, pasgal_scc_stats *stats);
 
 /* ------------------------------------------------------------ batched form --
  * Many BFS queries over many graphs in ONE persistent launch, captured once

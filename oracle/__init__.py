@@ -13,6 +13,9 @@ What each function computes (plain definitions; see oracle.c):
                        reaches v (reachability search, Parallel SCC section);
                        iterative DFS per source.
   scc(g)               Tarjan's SCC labels (the paper's SCC baseline).
+  scc_min_label(g)     the same components, each named by its smallest
+                       vertex (a unique labelling, the form the GPU SCC
+                       call returns).
   transpose(g)         G^T with rows sorted ascending (stable counting sort).
 
 Parity status of each function is recorded in tests/test_oracle.py: every one
@@ -104,6 +107,18 @@ def scc(g) -> np.ndarray:
     if rc < 0:
         raise ValueError(f"oracle_scc failed ({rc})")
     return comp
+
+
+def scc_min_label(g) -> np.ndarray:
+    """Strongly connected components (Parallel SCC section) with each vertex
+    labelled by the smallest vertex of its component: Tarjan's component
+    numbers, then the minimum vertex id per component."""
+    comp = scc(g)
+    n = comp.size
+    _, idx = np.unique(comp, return_inverse=True)
+    smallest = np.full(idx.max() + 1 if n else 0, n, dtype=np.int64)
+    np.minimum.at(smallest, idx, np.arange(n, dtype=np.int64))
+    return smallest[idx].astype(np.int32)
 
 
 def transpose(g):

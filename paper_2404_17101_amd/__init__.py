@@ -8,7 +8,9 @@ raise.
 
 Operations (PASGAL, SPAA'24): BFS hop distances with vertical granularity
 control (Parallel BFS), multi-source reachability (Parallel SCC section), the
-transpose G^T for backward reachability, a batched form and a served form.
+transpose G^T for backward reachability, strongly connected components by
+batched forward/backward reachability (Parallel SCC section), a batched form
+and a served form.
 """
 from __future__ import annotations
 
@@ -19,7 +21,8 @@ import numpy as np
 
 from . import _lib as L
 
-__all__ = ["DeviceGraph", "PasgalError", "bfs", "reach", "transpose", "validate", "Batch", "Server", "load"]
+__all__ = ["DeviceGraph", "PasgalError", "bfs", "reach", "transpose", "validate", "scc", "Batch", "Server",
+           "load"]
 
 load = L.load
 
@@ -161,6 +164,28 @@ def validate(g: DeviceGraph, **opts) -> bool:
         return False
     _check(rc, "pasgal_validate")
     return True
+
+
+def scc(g: DeviceGraph, transpose: DeviceGraph | None = None, comp_out=None, trim_rounds: int = -1,
+        split: bool = True, seed: int = 0, stats: bool = False, **opts):
+    """Strongly connected components: int32 tensor [n], entry v = the smallest
+    vertex of v's component. transpose: G^T if already built (else built
+    inside the call). trim_rounds < 0 selects the default, 0 disables
+    trimming; split=False keeps subproblems whole (no weak-connectivity cut);
+    seed keys the random pivot order (0 = default; the result does not depend
+    on it). With stats=True also returns the call's counters as a dict."""
+    torch = _torch()
+    if comp_out is None:
+        comp_out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    csr = g.csr()
+    tcsr = transpose.csr() if transpose is not None else None
+    o = _opts(**opts)
+    so = L.SccOpts(int(trim_rounds), 0 if split else L.SCC_NO_SPLIT, int(seed) & 0xFFFFFFFF, 0)
+    st = L.SccStats()
+    _check(L.load().pasgal_scc(ctypes.byref(csr), ctypes.byref(tcsr) if tcsr is not None else None,
+                               comp_out.data_ptr(), ctypes.byref(so), ctypes.byref(o), ctypes.byref(st)),
+           "pasgal_scc")
+    return (comp_out, st.as_dict()) if stats else comp_out
 
 
 def _i32p(a: np.ndarray):

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(PKG, "libpasgal.so")
 PASGAL_OK = 0
 ERRORS = {
     -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECSR", -5: "ECAPACITY", -6: "EAGAIN", -7: "ETIMEOUT",
-    -8: "ENOTFOUND",
+    -8: "ENOTFOUND", -9: "EINTERNAL",
 }
 MODE_VGC, MODE_PLAIN = 0, 1
 FLAG_VALIDATE, FLAG_ASYNC, FLAG_PREFETCH, FLAG_TEST_FIRST, FLAG_ROW_PER_LANE = 1, 2, 4, 8, 16
@@ -21,7 +21,7 @@ REQ_BFS, REQ_REACH = 0, 1
 EXPORTS = [
     "pasgal_opts_default", "pasgal_strerror", "pasgal_last_hip_error", "pasgal_version",
     "pasgal_bfs", "pasgal_bfs_ex", "pasgal_reach", "pasgal_reach_ex", "pasgal_transpose", "pasgal_validate",
-    "pasgal_batch_create", "pasgal_batch_run", "pasgal_batch_config", "pasgal_batch_destroy",
+    "pasgal_scc", "pasgal_batch_create", "pasgal_batch_run", "pasgal_batch_config", "pasgal_batch_destroy",
     "pasgal_server_create", "pasgal_server_add_graph", "pasgal_server_submit", "pasgal_server_poll",
     "pasgal_server_drain", "pasgal_server_load", "pasgal_server_destroy",
 ]
@@ -44,6 +44,23 @@ class Stats(ctypes.Structure):
                 ("relax_success", ctypes.c_int64), ("published", ctypes.c_int64), ("overflow", ctypes.c_int64),
                 ("stale", ctypes.c_int64), ("max_frontier", ctypes.c_int64), ("device_ms", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SCC_NO_SPLIT = 1
+
+
+class SccOpts(ctypes.Structure):
+    _fields_ = [("trim_rounds", ctypes.c_int32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+class SccStats(ctypes.Structure):
+    _fields_ = [("components", ctypes.c_int64), ("trimmed", ctypes.c_int64), ("pivots", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("rounds", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64),
+                ("device_ms", ctypes.c_double), ("reach_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,6 +116,7 @@ def load(path: str = LIB_PATH):
     lib.pasgal_reach_ex.argtypes = [P(Csr), P(i32), i32, vp, P(Opts), P(Stats)]
     lib.pasgal_transpose.argtypes = [P(Csr), vp, vp, P(Opts)]
     lib.pasgal_validate.argtypes = [P(Csr), P(Opts)]
+    lib.pasgal_scc.argtypes = [P(Csr), P(Csr), vp, P(SccOpts), P(Opts), P(SccStats)]
     lib.pasgal_batch_create.argtypes = [P(BatchDesc), P(Opts), ctypes.c_uint32, P(vp)]
     lib.pasgal_batch_run.argtypes = [vp, P(Stats)]
     lib.pasgal_batch_config.argtypes = [vp, P(Opts)]
@@ -113,7 +131,7 @@ def load(path: str = LIB_PATH):
     lib.pasgal_server_destroy.argtypes = [vp]
     lib.pasgal_server_destroy.restype = None
     for f in ("pasgal_bfs", "pasgal_bfs_ex", "pasgal_reach", "pasgal_reach_ex", "pasgal_transpose",
-              "pasgal_validate", "pasgal_batch_create", "pasgal_batch_run", "pasgal_batch_config",
+              "pasgal_validate", "pasgal_scc", "pasgal_batch_create", "pasgal_batch_run", "pasgal_batch_config",
               "pasgal_server_create", "pasgal_server_add_graph", "pasgal_server_submit", "pasgal_server_poll",
               "pasgal_server_drain", "pasgal_server_load"):
         getattr(lib, f).restype = c_int

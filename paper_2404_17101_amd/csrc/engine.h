@@ -39,6 +39,8 @@ struct Workspace {
   uint32_t cap = 0;
   HBuf h_ctl, h_stage;
   hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;
+  void *ext = nullptr;                   // buffers of a larger driver (SCC), freed by ext_free
+  void (*ext_free)(void *) = nullptr;
   ~Workspace();
 };
 
@@ -78,6 +80,7 @@ bool opts_valid(const pasgal_opts *o);
 bool csr_valid(const pasgal_csr *g);
 int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg);
 uint64_t default_cap(int64_t requested, uint64_t nvert);
+int ensure_frontier(Workspace &w, uint64_t cap, bool multi);
 void fill_stats_from_ctl(const Ctl &c, pasgal_stats *st, bool add);
 int validate_csr_device(Workspace &w, const pasgal_csr *g, hipStream_t s);
 

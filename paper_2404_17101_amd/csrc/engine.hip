@@ -109,6 +109,7 @@ Workspace::~Workspace() {
     free_buf(*b);
   free_hbuf(h_ctl);
   free_hbuf(h_stage);
+  if (ext_free) ext_free(ext);
   if (ev0) hipEventDestroy(ev0);
   if (evk) hipEventDestroy(evk);
   if (ev1) hipEventDestroy(ev1);
@@ -471,6 +472,7 @@ const char *pasgal_strerror(int code) {
     case PASGAL_EAGAIN: return "resource busy, try again";
     case PASGAL_ETIMEOUT: return "device-side wait timed out";
     case PASGAL_ENOTFOUND: return "not found";
+    case PASGAL_EINTERNAL: return "internal consistency check failed";
     default: return "unknown error";
   }
 }

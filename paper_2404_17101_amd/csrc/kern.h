@@ -129,6 +129,11 @@ hipError_t launch_plain_reach_level(const int32_t *off, const int32_t *tgt, unsi
 hipError_t launch_plain_seed(int kind, void *state, uint32_t *frontier, uint32_t *cnt_slots, uint32_t *stamp,
                              const uint32_t *srcs, const unsigned long long *vals, uint32_t nsrc, hipStream_t s);
 
+// Exclusive prefix sum: out[i] = in[0] + ... + in[i-1] for i in [0, len], so
+// out has len+1 entries. sums needs excl_scan_tiles(len) entries of scratch.
+int64_t excl_scan_tiles(int64_t len);
+hipError_t launch_excl_scan(const int32_t *in, int64_t len, int32_t *sums, int32_t *out, hipStream_t s);
+
 // Transpose (counting sort by target).
 hipError_t launch_transpose(const int32_t *off, const int32_t *tgt, int32_t n, int32_t m, int32_t *t_off,
                             int32_t *t_tgt, int32_t *scratch /* n+1 + block sums */, hipStream_t s);

@@ -31,74 +31,11 @@
 #include <stdint.h>
 #include <type_traits>
 
+#include "devutil.h"
 #include "engine.h"
 #include "kern.h"
 
 namespace pg {
-
-#define AG __HIP_MEMORY_SCOPE_AGENT
-constexpr uint32_t INF32 = 0xFFFFFFFFu;
-
-template <class T>
-__device__ __forceinline__ T ld_ag(T *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, AG);
-}
-template <class T>
-__device__ __forceinline__ void st_ag(T *p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, AG);
-}
-template <class T>
-__device__ __forceinline__ T add_ag(T *p, T v) {
-  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, AG);
-}
-template <class T>
-__device__ __forceinline__ T or_ag(T *p, T v) {
-  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, AG);
-}
-template <class T>
-__device__ __forceinline__ T min_ag(T *p, T v) {
-  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, AG);
-}
-template <class T>
-__device__ __forceinline__ T max_ag(T *p, T v) {
-  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, AG);
-}
-template <class T>
-__device__ __forceinline__ T xchg_ag(T *p, T v) {
-  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, AG);
-}
-__device__ __forceinline__ uint32_t cas_ag(uint32_t *p, uint32_t expect, uint32_t desired) {
-  __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED, AG);
-  return expect;  // old value
-}
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-__device__ __forceinline__ uint32_t mbcnt64(unsigned long long m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, uint32_t ln) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(x, d);
-    if (ln >= (uint32_t)d) x += y;
-  }
-  return x;
-}
-__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor(x, d));
-  return x;
-}
-__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x = min(x, (uint32_t)__shfl_xor(x, d));
-  return x;
-}
-__device__ __forceinline__ unsigned long long shfl64(unsigned long long x, int src) {
-  uint32_t lo = __shfl((uint32_t)x, src), hi = __shfl((uint32_t)(x >> 32), src);
-  return ((unsigned long long)hi << 32) | lo;
-}
-__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // Round state every workgroup needs after a barrier; read once per
 // workgroup by thread 0 and broadcast through LDS.
@@ -951,22 +888,6 @@ __global__ void hist_kernel(const int32_t *tgt, int32_t m, int32_t *cnt) {
 
 constexpr int SCAN_TILE = 1024;  // elements per block (256 threads x 4)
 
-__device__ int32_t block_excl_scan_256(int32_t x, int32_t &total) {
-  __shared__ int32_t wsum[4];
-  const uint32_t ln = lane_id(), wid = threadIdx.x >> 6;
-  int32_t incl = (int32_t)wave_incl_scan((uint32_t)x, ln);
-  if (ln == 63) wsum[wid] = incl;
-  __syncthreads();
-  int32_t off = 0, tot = 0;
-  for (uint32_t w = 0; w < 4; w++) {
-    if (w < wid) off += wsum[w];
-    tot += wsum[w];
-  }
-  __syncthreads();
-  total = tot;
-  return off + incl - x;
-}
-
 // tile sums of in[0..len)
 __global__ void scan_tiles_kernel(const int32_t *in, int64_t len, int32_t *sums) {
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 4;
@@ -1053,6 +974,17 @@ __global__ void __launch_bounds__(256) scatter_kernel(const int32_t *off, const 
   }
 }
 
+int64_t excl_scan_tiles(int64_t len) { return (len + 1 + SCAN_TILE - 1) / SCAN_TILE; }
+
+hipError_t launch_excl_scan(const int32_t *in, int64_t len, int32_t *sums, int32_t *out, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
+  const int64_t tiles = excl_scan_tiles(len);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(256), 0, s, in, len, sums);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, sums, tiles);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(256), 0, s, in, len, sums, out);
+  return hipGetLastError();
+}
+
 size_t transpose_scratch_elems(int32_t n) {
   const int64_t tiles = ((int64_t)n + 1 + SCAN_TILE - 1) / SCAN_TILE;
   return (size_t)n + 1 + (size_t)tiles + 16;
@@ -1063,8 +995,7 @@ hipError_t launch_transpose(const int32_t *off, const int32_t *tgt, int32_t n, i
   (void)hipGetLastError();  // report only this launch's error
   int32_t *cnt = scratch;                 // n+1 (histogram, then cursor)
   const int64_t len = (int64_t)n + 1;
-  const int64_t tiles = (len + SCAN_TILE - 1) / SCAN_TILE;
-  int32_t *sums = scratch + n + 1;        // tiles
+  int32_t *sums = scratch + n + 1;        // scan tiles
   hipError_t e = launch_fill_u32((uint32_t *)cnt, (uint64_t)len, 0u, s);
   if (e != hipSuccess) return e;
   if (m > 0) {
@@ -1073,9 +1004,7 @@ hipError_t launch_transpose(const int32_t *off, const int32_t *tgt, int32_t n, i
     hipLaunchKernelGGL(hist_kernel, dim3(g), dim3(256), 0, s, tgt, m, cnt);
   }
   // counts live at cnt[0..n); scan them into t_off[0..n]
-  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(256), 0, s, cnt, (int64_t)n, sums);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, sums, tiles);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(256), 0, s, cnt, (int64_t)n, sums, t_off);
+  if ((e = launch_excl_scan(cnt, (int64_t)n, sums, t_off, s)) != hipSuccess) return e;
   e = hipMemcpyAsync(cnt, t_off, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
   if (m > 0) {

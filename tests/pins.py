@@ -253,6 +253,26 @@ def pin_scc(scc):
         assert partition_equal(scc(g), np.argmax(r & r.T, axis=1)), bits
 
 
+def pin_scc_min_label(scc_min):
+    """Exact labels, not just the partition: the brute-force class of v
+    (mutual reachability by Warshall closure) named by its smallest vertex."""
+    n = 40
+    assert np.array_equal(scc_min(gg.simple("dcycle", n)), np.zeros(n, np.int32))
+    assert np.array_equal(scc_min(gg.simple("dchain", n)), np.arange(n, dtype=np.int32))
+    assert np.array_equal(scc_min(gg.simple("empty", 9)), np.arange(9, dtype=np.int32))
+    assert np.array_equal(scc_min(gg.grid(20, 30)), np.zeros(600, np.int32))
+    for t in range(25):
+        nn = 3 + 3 * t
+        g = gg.random_graph(nn, int(1.5 * nn), seed=900 + t)
+        r = warshall_closure(dense_adj(g))
+        assert np.array_equal(scc_min(g), np.argmax(r & r.T, axis=1).astype(np.int32)), t
+    pairs = [(u, v) for u in range(4) for v in range(4) if u != v]
+    for bits in range(1, 1 << 12, 5):
+        g = graph_from_arcs(4, [pairs[i] for i in range(12) if (bits >> i) & 1])
+        r = warshall_closure(dense_adj(g))
+        assert np.array_equal(scc_min(g), np.argmax(r & r.T, axis=1).astype(np.int32)), bits
+
+
 def pin_transpose(transpose):
     for g in [gg.random_graph(60, 200, 3), gg.road(20, 4), gg.knn(500, 5, 1, layout="draw"), gg.simple("empty", 5)]:
         t_off, t_tgt = transpose(g)

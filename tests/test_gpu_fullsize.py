@@ -102,6 +102,20 @@ def test_c3_road4096_forward_backward_scc(pg):
         assert np.array_equal(sel, comp == comp[p]), i
 
 
+def test_c3_road4096_scc_against_tarjan(pg):
+    """Whole SCC labelling of the 4096^2 road graph, element by element."""
+    g = gg.road(4096, 3)
+    d = pg.DeviceGraph.from_graph(g)
+    _say("c3 scc oracle")
+    exp = oracle.scc_min_label(g)
+    t = pg.transpose(d)
+    for kw in [dict(), dict(mode="plain"), dict(split=False, seed=3)]:
+        _say(f"c3 scc {kw}")
+        got, st = pg.scc(d, transpose=t, stats=True, **kw)
+        assert np.array_equal(got.cpu().numpy(), exp), kw
+        assert st["components"] == 1716206
+
+
 def test_c4_batch_1024_queries_uneven_graphs(pg):
     rec = gg.batch_recipe()
     _say("c4 generate")

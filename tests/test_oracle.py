@@ -49,6 +49,10 @@ def test_scc_pins():
     pins.pin_scc(oracle.scc)
 
 
+def test_scc_min_label_pins():
+    pins.pin_scc_min_label(oracle.scc_min_label)
+
+
 def test_transpose_pins():
     pins.pin_transpose(oracle.transpose)
 
