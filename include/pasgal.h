@@ -123,6 +123,24 @@ int pasgal_bfs(const pasgal_csr *g, int32_t src, int32_t *dist_out);
 int pasgal_bfs_ex(const pasgal_csr *g, int32_t src, int32_t *dist_out, const pasgal_opts *opts,
                   pasgal_stats *stats);
 
+/* Direction-optimizing BFS (Parallel BFS paragraph: the paper's BFS also uses
+ * the direction optimization of Beamer et al.). Level-synchronous: a level is
+ * expanded top-down (frontier vertices relax their out-arcs) while the
+ * frontier is small, and bottom-up (every unreached vertex scans its in-arcs
+ * and stops at the first in-neighbour in the frontier) while it is large.
+ * Suited to low-diameter graphs; on high-diameter graphs use pasgal_bfs_ex.
+ * gt: G^T (device CSR of the in-arcs, as pasgal_transpose builds it), or NULL
+ * when g is symmetric (every arc u->v has its reverse v->u), in which case g
+ * serves as its own transpose; a NULL gt with a directed g gives wrong
+ * distances. alpha: go bottom-up when the arcs out of the frontier exceed
+ * 1/alpha of the arcs out of unreached vertices (0 selects 14, < 0 never);
+ * beta: go back top-down when the frontier holds fewer than n/beta vertices
+ * (0 selects 24, < 0 never). Output exactly as pasgal_bfs. Synchronous on
+ * opts->stream (PASGAL_FLAG_ASYNC is rejected); opts->mode, tau and window are
+ * ignored; opts and stats may be NULL. stats->rounds counts levels. */
+int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t src, int32_t *dist_out, int32_t alpha,
+                  int32_t beta, const pasgal_opts *opts, pasgal_stats *stats);
+
 /* Multi-source reachability. sources: HOST array of k vertex ids (repeats
  * allowed), k >= 1. label_out: device, n * W uint64 with W = ceil(k/64);
  * bit (i % 64) of label_out[v*W + i/64] is set iff sources[i] reaches v

@@ -21,8 +21,8 @@ import numpy as np
 
 from . import _lib as L
 
-__all__ = ["DeviceGraph", "PasgalError", "bfs", "reach", "transpose", "validate", "scc", "Batch", "Server",
-           "load"]
+__all__ = ["DeviceGraph", "PasgalError", "bfs", "bfs_do", "reach", "transpose", "validate", "scc", "Batch",
+           "Server", "load"]
 
 load = L.load
 
@@ -121,6 +121,24 @@ def bfs(g: DeviceGraph, src: int, dist_out=None, stats: bool = False, **opts):
     st = L.Stats()
     _check(L.load().pasgal_bfs_ex(ctypes.byref(csr), int(src), dist_out.data_ptr(), ctypes.byref(o),
                                   ctypes.byref(st)), "pasgal_bfs")
+    return (dist_out, st.as_dict()) if stats else dist_out
+
+
+def bfs_do(g: DeviceGraph, src: int, transpose: DeviceGraph | None = None, dist_out=None, alpha: int = 0,
+           beta: int = 0, stats: bool = False, **opts):
+    """Direction-optimizing BFS (top-down / bottom-up levels). transpose: G^T;
+    None only when g is symmetric. alpha / beta: switching thresholds (0 =
+    defaults 14 / 24, negative = never switch that way). Same output as bfs."""
+    torch = _torch()
+    if dist_out is None:
+        dist_out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    csr = g.csr()
+    tcsr = transpose.csr() if transpose is not None else None
+    o = _opts(**opts)
+    st = L.Stats()
+    _check(L.load().pasgal_bfs_do(ctypes.byref(csr), ctypes.byref(tcsr) if tcsr is not None else None, int(src),
+                                  dist_out.data_ptr(), int(alpha), int(beta), ctypes.byref(o), ctypes.byref(st)),
+           "pasgal_bfs_do")
     return (dist_out, st.as_dict()) if stats else dist_out
 
 

@@ -35,9 +35,9 @@ struct HBuf {
 struct Workspace {
   std::mutex mu;
   hipStream_t stream = nullptr;
-  DBuf ctl, fv[2], fq[2], fval[2], dirty, qi, qword, seeds, pf[2], stamp, tmp_state, tscratch, plain_src;
+  DBuf ctl, fv[2], fq[2], fval[2], dirty, qi, qword, seeds, pf[2], stamp, tmp_state, tscratch, plain_src, aux;
   uint32_t cap = 0;
-  HBuf h_ctl, h_stage;
+  HBuf h_ctl, h_stage, h_aux;
   hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;
   void *ext = nullptr;                   // buffers of a larger driver (SCC), freed by ext_free
   void (*ext_free)(void *) = nullptr;

@@ -105,10 +105,11 @@ void free_hbuf(HBuf &b) {
 
 Workspace::~Workspace() {
   for (DBuf *b : {&ctl, &fv[0], &fv[1], &fq[0], &fq[1], &fval[0], &fval[1], &dirty, &qi, &qword, &seeds, &pf[0],
-                  &pf[1], &stamp, &tmp_state, &tscratch, &plain_src})
+                  &pf[1], &stamp, &tmp_state, &tscratch, &plain_src, &aux})
     free_buf(*b);
   free_hbuf(h_ctl);
   free_hbuf(h_stage);
+  free_hbuf(h_aux);
   if (ext_free) ext_free(ext);
   if (ev0) hipEventDestroy(ev0);
   if (evk) hipEventDestroy(evk);

@@ -267,11 +267,14 @@ struct Wave {
   }
 
   // Relax arc (., w) with value val of its tail; returns whether the state of
-  // w changed and the value to carry. With a.test_first, a coherent load
-  // first rules out relaxations that cannot change anything (values only
-  // ever go down for BFS / gain bits for reach, so a value read before a
-  // concurrent update is still a safe filter): loads sustain about 2.5x the
-  // rate of atomics. With PF the arc range of w is loaded alongside.
+  // w changed and the value to carry. With a.test_first, a plain load first
+  // rules out relaxations that cannot change anything. The load may be served
+  // by this XCD's L2 and be stale, but values only ever go down for BFS and
+  // only gain bits for reach, so a stale value is an upper bound (a subset)
+  // of the current one: when it already rules the relaxation out, so would
+  // the current value. Cached loads cost far less than the agent-scope
+  // atomic, which is performed past the L2. With PF the arc range of w is
+  // loaded alongside.
   __device__ __forceinline__ bool relax(int64_t sb, uint32_t w, Val val, Val &nv, int32_t &nb, int32_t &ne) {
     if (PF) {
       nb = a.off[w];
@@ -281,14 +284,14 @@ struct Wave {
       const uint32_t nd = (uint32_t)val + 1u;
       nv = (Val)nd;
       uint32_t *p = (uint32_t *)&state[sb + w];
-      if (a.test_first && ld_ag(p) <= nd) return false;
+      if (a.test_first && *(const uint32_t *)p <= nd) return false;
       const uint32_t old = min_ag(p, nd);
       return nd < old;
     } else {
       unsigned long long *p = (unsigned long long *)&state[sb + w];
       const unsigned long long m = (unsigned long long)val;
       if (a.test_first) {
-        const unsigned long long cur = ld_ag(p);
+        const unsigned long long cur = *(const unsigned long long *)p;
         if ((cur & m) == m) {
           nv = (Val)cur;
           return false;

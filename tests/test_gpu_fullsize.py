@@ -175,5 +175,7 @@ def test_c5_grid8192_closed_form_and_rmat24_sample(pg):
     exp = oracle.bfs(x, s)
     assert np.array_equal(pg.bfs(dx, s).cpu().numpy(), exp)
     assert np.array_equal(pg.bfs(dx, s, mode="plain").cpu().numpy(), exp)
+    _say("c5 rmat24 direction-optimizing")
+    assert np.array_equal(pg.bfs_do(dx, s).cpu().numpy(), exp)
     got = pg.reach(dx, [s]).cpu().numpy().view(np.uint64)[:, 0]
     assert np.array_equal(got == 1, exp >= 0)
