@@ -92,6 +92,11 @@ typedef struct pasgal_opts {
                                 unready vertices out of the current round). 0 selects 32; < 0 = no window. */
   int32_t min_chunk;         /* VGC: frontier entries one wavefront takes at least per local search
                                 (1..64; <= 0 selects 1) */
+  int32_t heavy_arcs;        /* VGC: a vertex with more out-arcs than this is not scanned by the one
+                                wavefront that expands it: its arcs are cut into slices of this many and
+                                dealt one per wavefront in the next round (skewed degrees, e.g. RMAT).
+                                0 selects 512; < 0 never cuts. */
+  int32_t reserved;          /* 0 */
 } pasgal_opts;
 
 /* Counters of one call (schedule dependent, never part of the result). */

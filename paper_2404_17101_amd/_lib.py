@@ -36,7 +36,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tau", ctypes.c_int32), ("wg_size", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("frontier_capacity", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("timeout_ms", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("window", ctypes.c_int32), ("min_chunk", ctypes.c_int32)]
+                ("window", ctypes.c_int32), ("min_chunk", ctypes.c_int32), ("heavy_arcs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -37,6 +37,8 @@ struct pasgal_batch {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr;
   VgcArgs args{};
   bool coop_in_graph = false;
+  SliceBufs slices;
+  uint32_t hcap = 0;
 
   ~pasgal_batch() {
     if (exec) hipGraphExecDestroy(exec);
@@ -89,6 +91,7 @@ struct pasgal_batch {
     args.test_first = o.test_first ? 1u : 0u;
     args.lane_arcs = o.lane_arcs;
     args.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
+    slices.apply(args, o.heavy, hcap, true);
     return PASGAL_OK;
   }
 
@@ -226,6 +229,9 @@ int pasgal_batch_create(const pasgal_batch_desc *d, const pasgal_opts *opts, uin
   if (!rc) rc = grow(b->seg_off, sizeof(int64_t) * nq);
   if (!rc) rc = grow(b->seg_len, sizeof(int64_t) * nq);
   if (!rc) rc = grow_host(b->h_ctl, sizeof(Ctl));
+  // a hub may be cut once per query that expands it
+  b->hcap = slice_capacity((uint64_t)d->packed.m * (uint64_t)std::min(nq, 8), o.heavy, b->cap);
+  if (!rc) rc = b->slices.ensure(b->hcap, true);
   if (rc) {
     delete b;
     return rc;

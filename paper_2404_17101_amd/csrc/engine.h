@@ -30,6 +30,19 @@ struct HBuf {
   size_t bytes = 0;
 };
 
+// Slice buffers for heavy rows (VgcArgs::heavy): two of `cap` entries each.
+struct SliceBufs {
+  DBuf v[2], q[2], val[2], b[2];
+  uint64_t cap = 0;
+  int ensure(uint64_t entries, bool multi);
+  // Point a's slice fields at these buffers; hcap 0 (or heavy 0) turns cutting off.
+  void apply(VgcArgs &a, uint32_t heavy, uint32_t hcap, bool multi) const;
+  ~SliceBufs();
+};
+// Slice capacity for a graph of m arcs: room for every arc twice over, at
+// most the frontier capacity (0 when heavy is 0).
+uint32_t slice_capacity(uint64_t m, uint32_t heavy, uint64_t frontier_cap);
+
 // Library-owned scratch of one stream: frontier buffers, dirty bitmap,
 // control block, query tables, plain-mode frontiers, pinned staging.
 struct Workspace {
@@ -38,6 +51,7 @@ struct Workspace {
   DBuf ctl, fv[2], fq[2], fval[2], dirty, qi, qword, seeds, pf[2], stamp, tmp_state, tscratch, plain_src, aux;
   uint32_t cap = 0;
   HBuf h_ctl, h_stage, h_aux;
+  SliceBufs slices;
   hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;
   void *ext = nullptr;                   // buffers of a larger driver (SCC), freed by ext_free
   void (*ext_free)(void *) = nullptr;
@@ -58,6 +72,7 @@ struct Opts {
   bool prefetch = false;
   bool test_first = false;
   uint32_t lane_arcs = 0;
+  uint32_t heavy = 512;  // 0 = never cut heavy rows
 };
 
 struct LaunchGeom {

@@ -156,7 +156,43 @@ Opts resolve_opts(const pasgal_opts *o) {
   r.prefetch = (o->flags & PASGAL_FLAG_PREFETCH) != 0;
   r.test_first = (o->flags & PASGAL_FLAG_TEST_FIRST) != 0;
   r.lane_arcs = (o->flags & PASGAL_FLAG_ROW_PER_LANE) ? 8u : 0u;
+  r.heavy = o->heavy_arcs > 0 ? (uint32_t)o->heavy_arcs : (o->heavy_arcs == 0 ? 512u : 0u);
   return r;
+}
+
+int SliceBufs::ensure(uint64_t entries, bool multi) {
+  if (entries == 0) return PASGAL_OK;
+  int rc;
+  for (int i = 0; i < 2; i++) {
+    if ((rc = grow(v[i], 4 * entries)) || (rc = grow(val[i], 8 * entries)) || (rc = grow(b[i], 4 * entries)))
+      return rc;
+    if (multi && (rc = grow(q[i], 4 * entries))) return rc;
+  }
+  cap = std::max<uint64_t>(cap, entries);
+  return PASGAL_OK;
+}
+
+void SliceBufs::apply(VgcArgs &a, uint32_t heavy, uint32_t hcap, bool multi) const {
+  a.heavy = hcap ? heavy : 0u;
+  a.hcap = a.heavy ? hcap : 0u;
+  for (int i = 0; i < 2; i++) {
+    a.hv[i] = (uint32_t *)v[i].p;
+    a.hq[i] = multi ? (uint32_t *)q[i].p : nullptr;
+    a.hval[i] = (unsigned long long *)val[i].p;
+    a.hb[i] = (int32_t *)b[i].p;
+  }
+}
+
+SliceBufs::~SliceBufs() {
+  for (int i = 0; i < 2; i++)
+    for (DBuf *d : {&v[i], &q[i], &val[i], &b[i]}) free_buf(*d);
+}
+
+uint32_t slice_capacity(uint64_t m, uint32_t heavy, uint64_t frontier_cap) {
+  if (heavy == 0) return 0;
+  uint64_t c = 2 * m / heavy + 4096;
+  c = std::min<uint64_t>(c, std::max<uint64_t>(frontier_cap, 64));
+  return (uint32_t)std::min<uint64_t>(c, 0x7FFFFFFFull);
 }
 
 bool opts_valid(const pasgal_opts *o) {
@@ -165,6 +201,7 @@ bool opts_valid(const pasgal_opts *o) {
   if (o->wg_size > 0 && (o->wg_size % 64 != 0 || o->wg_size > 1024)) return false;
   if (o->blocks_per_cu > 32) return false;
   if (o->min_chunk > 64) return false;
+  if (o->reserved != 0) return false;
   return true;
 }
 
@@ -251,6 +288,8 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   if ((rc = grow(w.qword, 2 * sizeof(int64_t)))) return rc;
   if ((rc = grow(w.seeds, sizeof(SeedEnt) * (size_t)nseed))) return rc;
   if ((rc = grow_host(w.h_ctl, sizeof(Ctl)))) return rc;
+  const uint32_t hcap = slice_capacity((uint64_t)g->m, o.heavy, cap);
+  if ((rc = w.slices.ensure(hcap, false))) return rc;
   const size_t stage_bytes = sizeof(QInfo) + 2 * sizeof(int64_t) + sizeof(SeedEnt) * (size_t)nseed;
   if ((rc = grow_host(w.h_stage, stage_bytes))) return rc;
   // host staging (pinned) -> device tables
@@ -307,6 +346,7 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   a.test_first = o.test_first ? 1u : 0u;
   a.lane_arcs = o.lane_arcs;
   a.ctl = (Ctl *)w.ctl.p;
+  w.slices.apply(a, o.heavy, hcap, false);
 
   if ((e = hipEventRecord(w.ev0, s)) != hipSuccess) return hip_fail(e);
   if (kind == KIND_BFS)
@@ -460,6 +500,7 @@ void pasgal_opts_default(pasgal_opts *o) {
   o->stream = nullptr;
   o->window = 0;
   o->min_chunk = 1;
+  o->heavy_arcs = 512;
 }
 
 const char *pasgal_strerror(int code) {

@@ -10,9 +10,11 @@
 //              set for a vertex whose frontier entry did not fit.
 //   frontier   two buffers (current / next) of entries {v, q, val}, SoA:
 //              v uint32, q uint32, val uint64 (dist or mask), capacity cap.
+//   slices     two buffers of heavy-row slices {v, q, val, first arc}, SoA,
+//              capacity hcap (see VgcArgs::heavy).
 //   ctl        control block: barrier counter, abort flag, frontier tails,
-//              claim counters and overflow flags rotating over 3 rounds,
-//              exit record and 64-bit statistics.
+//              claim counters, overflow flags and slice counts rotating over
+//              3 rounds, exit record and 64-bit statistics.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -51,7 +53,8 @@ struct Ctl {
   uint32_t final_buf; // frontier buffer holding the leftover entries
   uint32_t max_frontier;
   uint32_t bad_csr;   // validation result
-  uint32_t pad[13];
+  uint32_t hcnt[3];   // heavy-row slices: round r reads hcnt[r%3], appends to hcnt[(r+1)%3]
+  uint32_t pad[10];
   unsigned long long stats[8];
 };
 
@@ -87,6 +90,15 @@ struct VgcArgs {
                           // consecutive arcs)
   long long timeout_ticks;
   Ctl *ctl;
+  // Heavy rows: an expanded vertex with more than `heavy` out-arcs (0 = never)
+  // is cut into slices of `heavy` arcs {v, q, val, first arc}, written to
+  // slice buffer (round parity ^ 1) and dealt one per wavefront next round.
+  uint32_t heavy;
+  uint32_t hcap;          // slices per buffer; slices that do not fit are expanded in place
+  uint32_t *hv[2];
+  uint32_t *hq[2];
+  unsigned long long *hval[2];
+  int32_t *hb[2];
 };
 
 // Initial frontier entries for a launch (host-built, uploaded).

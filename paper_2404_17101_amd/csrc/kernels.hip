@@ -40,7 +40,7 @@ namespace pg {
 // Round state every workgroup needs after a barrier; read once per
 // workgroup by thread 0 and broadcast through LDS.
 struct RoundHdr {
-  uint32_t ncur, ovf, abort;
+  uint32_t ncur, ovf, nheavy, abort;
 };
 
 // Grid barrier for a persistent launch whose workgroups are all resident.
@@ -67,6 +67,7 @@ __device__ void grid_barrier(Ctl *ctl, uint32_t &epoch, long long deadline, uint
     hdr->abort = ab;
     hdr->ncur = ld_ag(&ctl->cnt[slot]);
     hdr->ovf = ld_ag(&ctl->ovf[slot]);
+    hdr->nheavy = ld_ag(&ctl->hcnt[slot]);
   }
   __syncthreads();
 }
@@ -99,6 +100,7 @@ struct Wave {
   uint32_t nslot, nbuf;
   uint32_t rabs;   // absolute number of the current round (BFS window)
   uint32_t root_end;  // local-queue positions below this hold the current search's roots
+  uint32_t slice_ok;  // heavy rows may be cut into slices this round
   unsigned long long st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale;
 
   __device__ __forceinline__ Wave(const VgcArgs &args, uint8_t *lds_wave) : a(args) {
@@ -128,6 +130,7 @@ struct Wave {
     nslot = nbuf = 0;
     rabs = 0;
     root_end = 0;
+    slice_ok = 0;
     st_expand = st_arcs = st_success = st_publish = st_overflow = st_stale = 0;
   }
 
@@ -303,6 +306,59 @@ struct Wave {
     }
   }
 
+  // Heavy rows: a lane whose row has more than a.heavy arcs hands them to the
+  // next round as slices of a.heavy arcs (one wavefront per slice there)
+  // instead of scanning them all with this one wavefront. One reservation
+  // per wavefront; slices past the buffer's capacity are not written and the
+  // lane keeps those arcs ([b, e) shrinks to them), so every reserved index
+  // below the capacity holds a slice.
+  __device__ __forceinline__ void cut_heavy(bool act, uint32_t v, uint32_t q, Val val, int32_t &b, int32_t &e) {
+    const bool hv = act && (uint32_t)(e - b) > a.heavy;
+    if (!__ballot(hv)) return;
+    const uint32_t k = hv ? ((uint32_t)(e - b) + a.heavy - 1) / a.heavy : 0u;
+    const uint32_t incl = wave_incl_scan(k, ln);
+    const uint32_t tot = __shfl(incl, 63);
+    uint32_t base = 0;
+    if (ln == 0) base = add_ag(&a.ctl->hcnt[nslot], tot);
+    base = __shfl(base, 0);
+    if (hv) {
+      const uint32_t s0 = base + incl - k;
+      const uint32_t fit = s0 >= a.hcap ? 0u : min(k, a.hcap - s0);
+      for (uint32_t i = 0; i < fit; i++) {
+        const uint32_t idx = s0 + i;
+        st_ag(&a.hv[nbuf][idx], v);
+        if (MULTI) st_ag(&a.hq[nbuf][idx], q);
+        st_ag(&a.hval[nbuf][idx], (unsigned long long)val);
+        st_ag(&a.hb[nbuf][idx], b + (int32_t)(i * a.heavy));
+      }
+      b = min(e, b + (int32_t)(fit * a.heavy));
+    }
+  }
+
+  // Slices cut last round: slice s goes to wavefront s mod total; its arcs
+  // are relaxed across the wavefront and a local search continues from what
+  // they reached.
+  __device__ __forceinline__ void process_heavy(uint32_t cbuf, uint32_t nheavy, uint32_t gw, uint32_t total) {
+    for (uint32_t s = gw; s < nheavy; s += total) {
+      const bool has = ln == 0;
+      uint32_t v = 0, q = 0;
+      Val val = 0;
+      int32_t b = 0, e = 0;
+      if (has) {
+        v = ld_ag(&a.hv[cbuf][s]);
+        if (MULTI) q = ld_ag(&a.hq[cbuf][s]);
+        val = (Val)ld_ag(&a.hval[cbuf][s]);
+        b = ld_ag(&a.hb[cbuf][s]);
+        e = min(a.off[v + 1], b + (int32_t)a.heavy);
+      }
+      head = tail = 0;
+      root_end = 0;
+      const uint32_t ne = expand(has, v, q, val, true, b, e, true, true);
+      if (ne) local_search(a.tau);
+      head = tail = 0;
+    }
+  }
+
   // Expand the active lanes' entries: scan out-arcs, relax, push successes.
   // Returns the number of entries expanded (not stale).
   __device__ __forceinline__ uint32_t expand(bool act, uint32_t v, uint32_t q, Val val, bool ring_ok, int32_t b = 0, int32_t e = 0,
@@ -320,6 +376,7 @@ struct Wave {
     const unsigned long long actb = __ballot(act);
     const uint32_t nexp = __popcll(actb);
     st_expand += nexp;
+    if (slice_ok) cut_heavy(act, v, q, val, b, e);
     const uint32_t deg = act ? (uint32_t)(e - b) : 0u;
     const uint32_t maxd = wave_max(deg);
     if (maxd == 0) return nexp;
@@ -621,17 +678,23 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
   uint32_t ncur = hdr.ncur, ovf = hdr.ovf;
   uint32_t maxf = 0;
   uint32_t r = 0;
+  uint32_t nheavy = 0;
   for (; r < a.max_rounds; ++r) {
-    if (ncur == 0 && ovf == 0) break;
+    if (ncur == 0 && ovf == 0 && nheavy == 0) break;
     maxf = max(maxf, ncur);
     const uint32_t nslot = (r + 1) % 3, fslot = (r + 2) % 3;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st_ag(&a.ctl->cnt[fslot], 0u);
       st_ag(&a.ctl->ovf[fslot], 0u);
+      st_ag(&a.ctl->hcnt[fslot], 0u);
     }
     wv.nslot = nslot;
     wv.nbuf = cbuf ^ 1u;
     wv.rabs = a.round_base + r;
+    // no slices in a launch's last allowed round: nothing may be left in the
+    // slice buffer when the launch returns
+    wv.slice_ok = (a.heavy != 0 && r + 1 < a.max_rounds) ? 1u : 0u;
+    if (nheavy) wv.process_heavy(cbuf, min(nheavy, a.hcap), gw, total_waves);
     if (ovf) wv.process_dirty(gw, total_waves);
     const uint32_t nproc = min(ncur, a.fr.cap);
     uint32_t chunk = (nproc + total_waves - 1) / total_waves;
@@ -642,6 +705,7 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
     if (hdr.abort) break;
     ncur = hdr.ncur;
     ovf = hdr.ovf;
+    nheavy = hdr.nheavy;
     cbuf ^= 1u;
   }
   wv.flush_stats();

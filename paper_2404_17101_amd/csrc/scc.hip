@@ -660,6 +660,9 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
   a.lane_arcs = o.lane_arcs;
   a.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
   a.ctl = (Ctl *)w->ctl.p;
+  const uint32_t hcap = slice_capacity(m2, o.heavy, cap);
+  if ((rc = w->slices.ensure(hcap, false))) return rc;
+  w->slices.apply(a, o.heavy, hcap, false);
 
   auto fail = [&](hipError_t err) { return hip_fail(err); };
   auto read_counters = [&]() -> hipError_t {

@@ -101,6 +101,7 @@ struct Lane {
   int kind = KIND_BFS;
   uint64_t cap = 0;
   DBuf fv[2], fq[2], fval[2], ctl, qi, qword, seeds, counts, dany;
+  SliceBufs slices;
   HBuf h_ctl, h_counts, h_dany, h_stage;
   uint32_t cur_buf = 0, cur_cnt = 0, cur_ovf = 0;
   uint32_t round_abs = 0;  // rounds run so far by this lane (BFS window origin of each request)
@@ -347,6 +348,10 @@ struct pasgal_server {
     a.lane_arcs = vopts.lane_arcs;
     a.timeout_ticks = (long long)vopts.timeout_ms * (long long)dev_info().wall_khz;
     a.ctl = (Ctl *)L.ctl.p;
+    // a hub may be cut once per request that expands it
+    const uint32_t hcap = slice_capacity((uint64_t)m_total * 8, vopts.heavy, L.cap);
+    if (int rc2 = L.slices.ensure(hcap, true)) return rc2;
+    L.slices.apply(a, vopts.heavy, hcap, true);
     if ((e = launch_fill_u32((uint32_t *)L.ctl.p, sizeof(Ctl) / 4, 0u, s)) != hipSuccess) return hip_fail(e);
     if ((e = launch_seed(kind, a, (const SeedEnt *)L.seeds.p, (uint32_t)nseed, L.cur_cnt, L.cur_ovf, s)) !=
         hipSuccess)

@@ -58,9 +58,29 @@ def test_host_only_calls(lib):
     assert (o.mode, o.tau, o.wg_size, o.blocks_per_cu, o.timeout_ms) == (0, 1024, 1024, 1, 20000)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets that a C compiler
+    gives the structs of include/pasgal.h."""
+    import subprocess
     from paper_2404_17101_amd import _lib as L
-    assert ctypes.sizeof(L.Csr) == 24
-    assert ctypes.sizeof(L.Opts) == 48
-    assert ctypes.sizeof(L.Stats) == 80
-    assert ctypes.sizeof(L.Request) == 4 * 3 + 64 * 4 + 4 + 8 + 8
+    mirrors = {"pasgal_csr": L.Csr, "pasgal_opts": L.Opts, "pasgal_stats": L.Stats, "pasgal_scc_opts": L.SccOpts,
+               "pasgal_scc_stats": L.SccStats, "pasgal_batch_desc": L.BatchDesc,
+               "pasgal_server_opts": L.ServerOpts, "pasgal_request": L.Request, "pasgal_completion": L.Completion}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pasgal.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -391,3 +391,95 @@ def test_server_tiny_budget_queues_admission(pg):
     for s, out in outs:
         assert np.array_equal(np_dist(out), oracle.bfs(g, s))
     srv.close()
+
+
+# ------------------------------------------------------ heavy-row slices ---
+
+def _hub_graph(n_leaves, extra_seed):
+    """Symmetric star (hub 0, degree n_leaves) plus a sprinkle of random
+    symmetric arcs among the leaves, so searches run on after the hub."""
+    r = gg.random_graph(n_leaves + 1, 2 * n_leaves, extra_seed, symmetric=True)
+    u = np.repeat(np.arange(r.n), np.diff(r.offsets))
+    leaves = np.arange(1, n_leaves + 1)
+    eu = np.concatenate([u, np.zeros(n_leaves, np.int64), leaves])
+    ew = np.concatenate([r.targets, leaves, np.zeros(n_leaves, np.int64)])
+    key = np.unique(eu.astype(np.int64) * (n_leaves + 1) + ew)
+    eu, ew = key // (n_leaves + 1), key % (n_leaves + 1)
+    off = np.zeros(n_leaves + 2, dtype=np.int64)
+    np.add.at(off, eu + 1, 1)
+    return gg.Graph(np.cumsum(off).astype(np.int32), ew.astype(np.int32))
+
+
+@pytest.mark.parametrize("heavy", [16, 64, 1000])
+def test_heavy_rows_cut_into_slices_bfs_reach(pg, heavy):
+    """Rows longer than heavy_arcs are dealt out as slices; results stay exact
+    (RMAT hubs, a star hub, and a slice buffer too small for the slices)."""
+    for g in [gg.rmat(13, 16, 4), _hub_graph(20000, 71)]:
+        d = dev(pg, g)
+        srcs = [int(s) for s in gg.sources(g, 3, 72, min_degree=1)]
+        for kw in [dict(heavy_arcs=heavy), dict(heavy_arcs=heavy, frontier_capacity=64),
+                   dict(heavy_arcs=heavy, tau=16, window=0)]:
+            for s in srcs:
+                _say(f"heavy bfs {g.name} n={g.n} src={s} {kw}")
+                assert np.array_equal(np_dist(pg.bfs(d, s, **kw)), oracle.bfs(g, s)), (s, kw)
+            _say(f"heavy reach {g.name} {kw}")
+            assert np.array_equal(np_mask(pg.reach(d, srcs, **kw)), oracle.reach(g, srcs)), kw
+
+
+def test_heavy_rows_batch_scc_and_server(pg):
+    g = _hub_graph(30000, 73)
+    x = gg.rmat(12, 16, 6)
+    graphs = [g, x]
+    packed = gg.pack(graphs)
+    pd = pg.DeviceGraph.from_numpy(packed.offsets, packed.targets)
+    qg, qs, qo, off = [], [], [], 0
+    for gi, gr in enumerate(graphs):
+        for s in gg.sources(gr, 6, 74 + gi, min_degree=1):
+            qg.append(gi)
+            qs.append(int(s))
+            qo.append(off)
+            off += gr.n
+    dist = torch.empty(off, dtype=torch.int32, device="cuda")
+    for heavy in [32, 0]:
+        _say(f"heavy batch heavy={heavy}")
+        b = pg.Batch(pd, packed.vbase, np.array(qg), np.array(qs), np.array(qo, dtype=np.int64), dist,
+                     heavy_arcs=heavy)
+        b.run()
+        got = dist.cpu().numpy()
+        b.close()
+        for j in range(len(qg)):
+            gr = graphs[qg[j]]
+            assert np.array_equal(got[qo[j]:qo[j] + gr.n], oracle.bfs(gr, qs[j])), (heavy, j)
+    # SCC over a directed graph with hubs
+    y = gg.rmat(12, 16, 7)
+    keep = np.random.default_rng(75).random(y.m) < 0.6
+    u = np.repeat(np.arange(y.n), np.diff(y.offsets))[keep]
+    off2 = np.zeros(y.n + 1, dtype=np.int64)
+    np.add.at(off2, u + 1, 1)
+    yd = gg.Graph(np.cumsum(off2).astype(np.int32), y.targets[keep].astype(np.int32))
+    for heavy in [8, 0]:
+        _say(f"heavy scc heavy={heavy}")
+        got = pg.scc(dev(pg, yd), heavy_arcs=heavy).cpu().numpy()
+        assert np.array_equal(got, oracle.scc_min_label(yd)), heavy
+    # the served form stops launches after slice_rounds (hub degree 30000 >
+    # the default 4096); no slice may be left behind at a launch's end
+    for rounds in [1, 2, 3]:
+        _say(f"heavy server slice_rounds={rounds}")
+        srv = pg.Server(max_slots=8, slice_rounds=rounds, tau=64)
+        gid = srv.add_graph(dev(pg, g))
+        reqs = []
+        for i in range(6):
+            s = int(gg.sources(g, 1, 76 + i, min_degree=1)[0])
+            kind = "bfs" if i % 2 == 0 else "reach"
+            out = torch.empty(g.n, dtype=torch.int32 if kind == "bfs" else torch.int64, device="cuda")
+            assert srv.submit(gid, kind, [s], out=out) is not None
+            reqs.append((s, kind, out))
+        srv.drain(60000)
+        comps = srv.poll(100)
+        assert len(comps) == 6 and all(c["status"] == 0 for c in comps)
+        for s, kind, out in reqs:
+            if kind == "bfs":
+                assert np.array_equal(np_dist(out), oracle.bfs(g, s)), (rounds, s)
+            else:
+                assert np.array_equal(np_mask(out)[:, None], oracle.reach(g, [s])), (rounds, s)
+        srv.close()
