@@ -61,6 +61,8 @@ def _load():
         lib.gg_rmat.argtypes = [i32, i32, dbl, dbl, dbl, u64, P]
         lib.gg_points_ordered.argtypes = [i64, u64, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]
         lib.gg_points_ordered.restype = None
+        lib.gg_weights.argtypes = [i64, u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+        lib.gg_weights.restype = None
         lib.gg_free.argtypes = [P]
         lib.gg_free.restype = None
         lib.gg_rng64.argtypes = [u64, u64, u64]
@@ -103,6 +105,16 @@ def _take(fn, *args, name="", **meta) -> Graph:
     finally:
         lib.gg_free(ctypes.byref(g))
     return Graph(off, tgt, name=name, meta=dict(meta))
+
+
+def weights(g: Graph, seed: int, lo: int = 1, hi: int = 1000) -> np.ndarray:
+    """uint32 weight per arc of g (parallel to g.targets), uniform integers in
+    [lo, hi] from counter-based stream 70 of `seed`."""
+    if not (0 <= lo <= hi < 2**32):
+        raise ValueError("weights need 0 <= lo <= hi < 2^32")
+    w = np.empty(max(g.m, 1), dtype=np.uint32)
+    _load().gg_weights(g.m, seed, lo, hi, w.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return w[:g.m]
 
 
 def grid(a: int, b: int, torus: bool = False) -> Graph:

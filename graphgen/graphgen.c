@@ -568,6 +568,15 @@ int gg_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c, ui
   return rc;
 }
 
+/* Arc weights for weighted shortest paths: w[e] = lo + (draw of stream 70 at
+ * counter e) mod (hi - lo + 1), independent per arc (modulo bias below
+ * 2^-40 for hi - lo < 2^24). */
+void gg_weights(int64_t m, uint64_t seed, uint32_t lo, uint32_t hi, uint32_t *w) {
+  const uint64_t span = (uint64_t)(hi - lo) + 1;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m; e++) w[e] = lo + (uint32_t)(gg_rng64(seed, 70, (uint64_t)e) % span);
+}
+
 int gg_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

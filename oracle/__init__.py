@@ -17,6 +17,10 @@ What each function computes (plain definitions; see oracle.c):
                        vertex (a unique labelling, the form the GPU SCC
                        call returns).
   transpose(g)         G^T with rows sorted ascending (stable counting sort).
+  sssp(g, w, src)      shortest-path distances with non-negative integer arc
+                       weights w (parallel to g.targets), int64, -1 if
+                       unreachable; Dijkstra with a binary heap (Parallel
+                       SSSP paragraph).
 
 Parity status of each function is recorded in tests/test_oracle.py: every one
 is pinned against closed forms, brute force or an independent certificate.
@@ -58,7 +62,9 @@ def _load():
         lib.oracle_reach.argtypes = [ctypes.c_int32, _I32P, _I32P, ctypes.c_int32, _I32P, ctypes.c_int32, _U64P]
         lib.oracle_scc.argtypes = [ctypes.c_int32, _I32P, _I32P, _I32P]
         lib.oracle_transpose.argtypes = [ctypes.c_int32, _I32P, _I32P, _I32P, _I32P]
-        for f in ("oracle_bfs", "oracle_reach", "oracle_scc", "oracle_transpose"):
+        lib.oracle_sssp.argtypes = [ctypes.c_int32, _I32P, _I32P, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int64)]
+        for f in ("oracle_bfs", "oracle_reach", "oracle_scc", "oracle_transpose", "oracle_sssp"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -107,6 +113,22 @@ def scc(g) -> np.ndarray:
     if rc < 0:
         raise ValueError(f"oracle_scc failed ({rc})")
     return comp
+
+
+def sssp(g, weights, src: int) -> np.ndarray:
+    off, tgt = _csr(g)
+    n = off.size - 1
+    w = np.ascontiguousarray(weights, dtype=np.uint32)
+    if w.size != int(off[-1]):
+        raise ValueError("one weight per arc")
+    if w.size == 0:
+        w = np.zeros(1, dtype=np.uint32)
+    dist = np.empty(n, dtype=np.int64)
+    rc = _load().oracle_sssp(n, _p(off), _p(tgt), w.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), int(src),
+                             dist.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise ValueError(f"oracle_sssp failed ({rc})")
+    return dist
 
 
 def scc_min_label(g) -> np.ndarray:

@@ -21,6 +21,11 @@
  *                 index of v's component in the order Tarjan completes them.
  *  oracle_transpose  G^T by a stable counting sort of the arcs by target, so
  *                 every row of G^T lists its sources in ascending order.
+ *  oracle_sssp    single-source shortest-path distances with non-negative
+ *                 integer arc weights (Parallel SSSP paragraph: the stepping
+ *                 framework computes these exact distances), by Dijkstra's
+ *                 algorithm with a binary heap and lazy deletion; int64
+ *                 distances, -1 for unreached vertices.
  *
  * CSR input: offsets[n+1], targets[m], int32, targets in [0,n). Self-loops and
  * duplicate arcs are allowed and change nothing.
@@ -156,5 +161,66 @@ int oracle_transpose(int32_t n, const int32_t *offsets, const int32_t *targets, 
   for (int32_t u = 0; u < n; u++)
     for (int32_t e = offsets[u]; e < offsets[u + 1]; e++) t_targets[cursor[targets[e]]++] = u;
   free(cursor);
+  return 0;
+}
+
+/* Binary min-heap of (distance, vertex) pairs for Dijkstra. */
+typedef struct {
+  int64_t key;
+  int32_t v;
+} heap_item;
+
+static void heap_push(heap_item *h, int64_t *size, int64_t key, int32_t v) {
+  int64_t i = (*size)++;
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (h[p].key <= key) break;
+    h[i] = h[p];
+    i = p;
+  }
+  h[i].key = key;
+  h[i].v = v;
+}
+
+static heap_item heap_pop(heap_item *h, int64_t *size) {
+  heap_item top = h[0];
+  heap_item last = h[--(*size)];
+  int64_t i = 0;
+  for (;;) {
+    int64_t c = 2 * i + 1;
+    if (c >= *size) break;
+    if (c + 1 < *size && h[c + 1].key < h[c].key) c++;
+    if (last.key <= h[c].key) break;
+    h[i] = h[c];
+    i = c;
+  }
+  if (*size > 0) h[i] = last;
+  return top;
+}
+
+int oracle_sssp(int32_t n, const int32_t *offsets, const int32_t *targets, const uint32_t *weights, int32_t src,
+                int64_t *dist) {
+  if (n <= 0 || src < 0 || src >= n) return -2;
+  const int64_t m = offsets[n];
+  heap_item *heap = (heap_item *)malloc(sizeof(heap_item) * (size_t)(m + 1));
+  if (!heap) return -1;
+  for (int32_t v = 0; v < n; v++) dist[v] = -1;
+  int64_t size = 0;
+  dist[src] = 0;
+  heap_push(heap, &size, 0, src);
+  while (size > 0) {
+    heap_item it = heap_pop(heap, &size);
+    int32_t u = it.v;
+    if (it.key != dist[u]) continue; /* a shorter distance was found after this push */
+    for (int32_t e = offsets[u]; e < offsets[u + 1]; e++) {
+      int32_t w = targets[e];
+      int64_t nd = it.key + (int64_t)weights[e];
+      if (dist[w] < 0 || nd < dist[w]) {
+        dist[w] = nd;
+        heap_push(heap, &size, nd, w);
+      }
+    }
+  }
+  free(heap);
   return 0;
 }

@@ -294,3 +294,76 @@ ALL_BFS_PINS = [pin_bfs_grid, pin_bfs_torus, pin_bfs_families, pin_bfs_bruteforc
 
 def all_pairs_iter(n):
     return itertools.product(range(n), range(n))
+
+
+# ------------------------------------------------------------------ SSSP ---
+
+def sssp_certificate_ok(g, w, s, d) -> bool:
+    """Exact characterisation of shortest-path distances for POSITIVE integer
+    weights, checked arc by arc: (I1) d(s) = 0; (I2) every arc (u, v) with u
+    reached has v reached and d(v) <= d(u) + w(u, v) (so d <= the true
+    distance, by induction along a shortest path); (I3) every reached v != s
+    has an in-arc (u, v) from a reached u with d(u) + w(u, v) = d(v) (so,
+    following such arcs back, d(v) is the length of a real path, reaching s
+    because d strictly decreases)."""
+    d = np.asarray(d, dtype=np.int64)
+    w = np.asarray(w, dtype=np.int64)
+    if d[s] != 0:
+        return False
+    u = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    v = g.targets.astype(np.int64)
+    ru = d[u] >= 0
+    if np.any(ru & (d[v] < 0)):
+        return False
+    if np.any(ru & (d[v] > d[u] + w)):
+        return False
+    tight = ru & (d[u] + w == d[v])
+    has = np.zeros(g.n, dtype=bool)
+    has[v[tight]] = True
+    need = (d >= 0)
+    need[s] = False
+    return bool(np.all(has[need]))
+
+
+def weighted_floyd_warshall(g, w) -> np.ndarray:
+    n = g.n
+    inf = np.iinfo(np.int64).max // 4
+    dm = np.full((n, n), inf, dtype=np.int64)
+    np.fill_diagonal(dm, 0)
+    u = np.repeat(np.arange(n), np.diff(g.offsets))
+    for a, b, c in zip(u, g.targets, np.asarray(w, dtype=np.int64)):
+        dm[a, b] = min(dm[a, b], c)
+    for k in range(n):
+        dm = np.minimum(dm, dm[:, k:k + 1] + dm[k:k + 1, :])
+    dm[dm >= inf] = -1
+    return dm
+
+
+def pin_sssp(sssp, bfs):
+    # unit weights: hop distances (an independent algorithm, FIFO BFS)
+    for g in [gg.grid(30, 40), gg.knn(3000, 5, 4, layout="draw"), gg.road(40, 2), gg.rmat(10, 8, 3)]:
+        ones = np.ones(g.m, dtype=np.uint32)
+        for s in [0, g.n // 2]:
+            assert np.array_equal(sssp(g, ones, s), bfs(g, s).astype(np.int64)), (g.name, s)
+    # weighted directed chain: prefix sums from the source, -1 before it
+    n = 50
+    g = gg.simple("dchain", n)
+    w = gg.weights(g, 5, 0, 99)
+    pre = np.concatenate([[0], np.cumsum(w.astype(np.int64))])
+    for s in [0, 17, n - 1]:
+        exp = np.full(n, -1, dtype=np.int64)
+        exp[s:] = pre[s:] - pre[s]
+        assert np.array_equal(sssp(g, w, s), exp), s
+    # brute force (Floyd-Warshall), zero weights included
+    for t in range(20):
+        nn = 4 + 2 * t
+        g = gg.random_graph(nn, 3 * nn, seed=800 + t)
+        w = gg.weights(g, 900 + t, 0, 20)
+        dm = weighted_floyd_warshall(g, w)
+        for s in range(0, nn, 3):
+            assert np.array_equal(sssp(g, w, s), dm[s]), (t, s)
+    # certificate with positive weights on larger graphs
+    for g in [gg.knn(2000, 5, 3, layout="draw"), gg.road(48, 9), gg.rmat(9, 8, 2)]:
+        w = gg.weights(g, 7, 1, 1000)
+        for s in [int(x) for x in gg.sources(g, 3, 13)]:
+            assert sssp_certificate_ok(g, w, s, sssp(g, w, s)), (g.name, s)

@@ -53,6 +53,22 @@ def test_scc_min_label_pins():
     pins.pin_scc_min_label(oracle.scc_min_label)
 
 
+def test_sssp_pins():
+    pins.pin_sssp(oracle.sssp, oracle.bfs)
+
+
+def test_sssp_certificate_rejects_wrong_distances():
+    g = gg.road(30, 4)
+    w = gg.weights(g, 3, 1, 50)
+    d = oracle.sssp(g, w, 0)
+    assert pins.sssp_certificate_ok(g, w, 0, d)
+    for v in [int(np.argmax(d)), int(np.flatnonzero(d > 0)[0])]:
+        for delta in (-1, 1):
+            bad = d.copy()
+            bad[v] += delta
+            assert not pins.sssp_certificate_ok(g, w, 0, bad), (v, delta)
+
+
 def test_transpose_pins():
     pins.pin_transpose(oracle.transpose)
 
@@ -106,6 +122,10 @@ MUTATIONS = {
     "reach_no_source": ("mask[(size_t)s * words + word] |= bit;\n    stack[top++] = s;", "stack[top++] = s;", "reach"),
     # Tarjan without the on-stack test (cross arcs merge components)
     "tarjan_no_onstack": ("} else if (onstack[w] && index[w] < low[u]) {", "} else if (index[w] < low[u]) {", "scc"),
+    # Dijkstra relaxes with weight 1 instead of the arc's weight
+    "sssp_unit_weight": ("int64_t nd = it.key + (int64_t)weights[e];", "int64_t nd = it.key + 1;", "sssp"),
+    # Dijkstra sets a distance only on first discovery (never lowers it)
+    "sssp_first_visit_only": ("if (dist[w] < 0 || nd < dist[w]) {", "if (dist[w] < 0) {", "sssp"),
     # transpose keeps the original direction
     "transpose_same_dir": ("t_targets[cursor[targets[e]]++] = u;", "t_targets[cursor[targets[e]]++] = targets[e];", "transpose"),
 }
@@ -141,6 +161,8 @@ def test_pins_catch_planted_mistake(name, monkeypatch):
                 pins.pin_reach(oracle.reach, oracle.bfs)
             elif which == "scc":
                 pins.pin_scc(oracle.scc)
+            elif which == "sssp":
+                pins.pin_sssp(oracle.sssp, oracle.bfs)
             else:
                 pins.pin_transpose(oracle.transpose)
         except (AssertionError, ValueError, IndexError):
