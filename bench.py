@@ -160,7 +160,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (counter calibration for rocprofv3 runs)")
-    ap.add_argument("--suite", choices=["c1", "c3", "c4", "c5", "scc"], default=None,
+    ap.add_argument("--suite", choices=["c1", "c3", "c4", "c5", "scc", "sssp", "bfs_do"], default=None,
                     help="run one of the other configurations instead of the headline job (one JSON line)")
     ap.add_argument("--rates", default="5,10,20,40,100,300,1000,3000,10000", help="c5: Poisson arrival rates (q/s)")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,

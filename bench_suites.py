@@ -16,6 +16,12 @@ all traversal work runs in libpasgal.so through its C ABI.
       VGC against tau = 1 (one BFS level per round), and with the trimming and
       weak-connectivity additions switched off; Tarjan's sequential algorithm
       (the CPU oracle, one core) is timed beside it as the CPU baseline.
+  sssp single-source shortest paths (VGC local searches in delta-stepping
+      rounds) with integer weights uniform in [1, 1000] on the 10M-point
+      5-NN graph, the c3 road graph and an RMAT-22 graph: VGC against tau = 1,
+      Dijkstra (the CPU oracle, one core) timed beside it.
+  bfs_do direction-optimizing BFS against the VGC and plain BFS on the served
+      RMAT-24 graph and on the 10M-point 5-NN graph.
   c5  resident 8192x8192 grid + RMAT scale 24 (edge factor 16, symmetrised):
       Poisson arrivals of BFS / reach requests from random sources, served by
       the continuous-batching server; p50/p99 latency and achieved q/s per
@@ -151,6 +157,97 @@ def suite_scc(args, pg, gg, torch):
         torch.cuda.empty_cache()
     return {"suite": "scc", "workload": "SCC of road4096 (seed 3), knn 10M/5 (seed 2), RMAT-20 (ef 16, seed 5)",
             "results": res}
+
+
+def _cpu_baseline_sssp(g, w, s):
+    """Dijkstra from the CPU oracle, one core: the baseline column."""
+    import oracle
+
+    a = time.perf_counter()
+    d = oracle.sssp(g, w, s)
+    return time.perf_counter() - a, d
+
+
+def _median_ms(fn, reps=3):
+    ts = []
+    out = None
+    for _ in range(reps):
+        torch_sync()
+        a = time.perf_counter()
+        out = fn()
+        torch_sync()
+        ts.append(time.perf_counter() - a)
+    return float(np.median(ts)) * 1e3, out
+
+
+def torch_sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def suite_sssp(args, pg, gg, torch):
+    graphs = [("knn10m", lambda: gg.knn(10_000_000, 5, 2, layout="morton")), ("road4096", lambda: gg.road(4096, 3)),
+              ("rmat22", lambda: gg.rmat(22, 16, 5))]
+    res = []
+    for name, make in graphs:
+        g = make()
+        w = gg.weights(g, 2002, 1, 1000)
+        d = pg.DeviceGraph.from_graph(g)
+        wd = torch.from_numpy(w.view(np.int32)).cuda()
+        s = int(gg.sources(g, 1, 1002, min_degree=1)[0])
+        cpu_s, exp = _cpu_baseline_sssp(g, w, s)
+        reached = exp >= 0
+        arcs = int(np.diff(g.offsets)[reached].sum())
+        entry = {"graph": name, "n": g.n, "m": g.m, "source": s, "weights": "uniform [1, 1000], seed 2002",
+                 "reached_arcs": arcs,
+                 "cpu_baseline": {"dijkstra_ms": round(cpu_s * 1e3, 1), "cores": 1, "kind": "oracle"}, "gpu": {}}
+        for label, kw in [("vgc", dict()), ("tau1", dict(mode="plain"))]:
+            ms, (out, st) = _median_ms(lambda: pg.sssp(d, wd, s, stats=True, **kw))
+            got = out.cpu().numpy().view(np.uint32).astype(np.int64)
+            got[got == 0xFFFFFFFF] = -1
+            entry["gpu"][label] = {"ms": round(ms, 2), "kernel_ms": round(st["kernel_ms"], 2),
+                                   "matches_oracle": bool(np.array_equal(got, exp)),
+                                   "speedup_vs_dijkstra": round(cpu_s * 1e3 / ms, 1), "rounds": st["rounds"],
+                                   "expansions_per_reached": round(st["expansions"] / max(1, int(reached.sum())), 3),
+                                   "gteps": round(arcs / (ms * 1e-3) / 1e9, 3)}
+            _log(f"sssp {name} {label}: {entry['gpu'][label]}")
+        res.append(entry)
+        del d, wd
+        torch.cuda.empty_cache()
+    return {"suite": "sssp", "workload": "SSSP, weights uniform in [1, 1000]: knn 10M/5 (seed 2), road4096 (seed 3), "
+                                         "RMAT-22 (ef 16, seed 5)", "results": res}
+
+
+def suite_bfs_do(args, pg, gg, torch):
+    res = []
+    for name, make, symmetric in [("rmat24", lambda: gg.rmat(24, 16, 5), True),
+                                  ("knn10m", lambda: gg.knn(10_000_000, 5, 2, layout="morton"), False)]:
+        g = make()
+        d = pg.DeviceGraph.from_graph(g)
+        t = None if symmetric else pg.transpose(d)
+        srcs = [int(x) for x in gg.sources(g, 4, 1005, min_degree=1)]
+        import oracle
+
+        exp = oracle.bfs(g, srcs[0])
+        arcs = int(np.diff(g.offsets)[exp >= 0].sum())
+        entry = {"graph": name, "n": g.n, "m": g.m, "reached_arcs_src0": arcs, "gpu": {}}
+        for label, fn in [("vgc", lambda s: pg.bfs(d, s)), ("plain", lambda s: pg.bfs(d, s, mode="plain")),
+                          ("direction_optimizing", lambda s: pg.bfs_do(d, s, transpose=t)),
+                          ("direction_optimizing_alpha50", lambda s: pg.bfs_do(d, s, transpose=t, alpha=50))]:
+            ok = bool(np.array_equal(fn(srcs[0]).cpu().numpy(), exp))
+            ts = []
+            for s in srcs:
+                ms, _ = _median_ms(lambda: fn(s), reps=1)
+                ts.append(ms)
+            entry["gpu"][label] = {"ms_median_of_4_sources": round(float(np.median(ts)), 2), "matches_oracle": ok,
+                                   "gteps_src0_arcs": round(arcs / (float(np.median(ts)) * 1e-3) / 1e9, 3)}
+            _log(f"bfs_do {name} {label}: {entry['gpu'][label]}")
+        res.append(entry)
+        del d, t
+        torch.cuda.empty_cache()
+    return {"suite": "bfs_do", "workload": "single-source BFS on RMAT-24 (ef 16, seed 5) and knn 10M/5 (seed 2), "
+                                           "4 sources (seed 1005)", "results": res}
 
 
 def suite_c4(args, pg, gg, torch):
@@ -327,6 +424,7 @@ def run(name, args):
 
     pg.load()
     torch.cuda.set_device(0)
-    fn = {"c1": suite_c1, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "scc": suite_scc}[name]
+    fn = {"c1": suite_c1, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "scc": suite_scc, "sssp": suite_sssp,
+          "bfs_do": suite_bfs_do}[name]
     out = fn(args, pg, gg, torch)
     print(json.dumps(out), flush=True)

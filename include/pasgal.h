@@ -128,6 +128,24 @@ int pasgal_bfs(const pasgal_csr *g, int32_t src, int32_t *dist_out);
 int pasgal_bfs_ex(const pasgal_csr *g, int32_t src, int32_t *dist_out, const pasgal_opts *opts,
                   pasgal_stats *stats);
 
+/* Single-source shortest paths with non-negative integer arc weights
+ * (Parallel SSSP paragraph: the stepping framework with VGC local searches).
+ * Round r of the persistent kernel expands only tentative distances below
+ * (r + 1) * delta (delta-stepping's buckets over rounds); inside a round each
+ * frontier vertex runs a local search of up to tau expansions, relaxing
+ * dist[w] = min(dist[w], dist[u] + weight) with atomicMin and re-queueing a
+ * vertex whenever its distance drops, so the fixpoint is the exact distance.
+ * weights: device, m uint32, weights[e] belongs to arc e (parallel to
+ * targets). dist_out: device, n uint32, written entirely; 0xFFFFFFFF marks an
+ * unreachable vertex. The caller must keep every shortest distance below
+ * 0xFFFFFFFF (larger sums saturate at 0xFFFFFFFE). opts->window is delta:
+ * > 0 as given, 0 selects 8 times the mean arc weight (computed on the
+ * device), < 0 no buckets (every tentative distance may be expanded at once).
+ * PASGAL_MODE_PLAIN runs tau = 1 (one expansion per local search, VGC off) in
+ * the same kernel; PASGAL_FLAG_PREFETCH is ignored. */
+int pasgal_sssp(const pasgal_csr *g, const uint32_t *weights, int32_t src, uint32_t *dist_out,
+                const pasgal_opts *opts, pasgal_stats *stats);
+
 /* Direction-optimizing BFS (Parallel BFS paragraph: the paper's BFS also uses
  * the direction optimization of Beamer et al.). Level-synchronous: a level is
  * expanded top-down (frontier vertices relax their out-arcs) while the

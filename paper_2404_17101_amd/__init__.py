@@ -21,8 +21,8 @@ import numpy as np
 
 from . import _lib as L
 
-__all__ = ["DeviceGraph", "PasgalError", "bfs", "bfs_do", "reach", "transpose", "validate", "scc", "Batch",
-           "Server", "load"]
+__all__ = ["DeviceGraph", "PasgalError", "bfs", "bfs_do", "sssp", "reach", "transpose", "validate", "scc",
+           "Batch", "Server", "load"]
 
 load = L.load
 
@@ -142,6 +142,27 @@ def bfs_do(g: DeviceGraph, src: int, transpose: DeviceGraph | None = None, dist_
     _check(L.load().pasgal_bfs_do(ctypes.byref(csr), ctypes.byref(tcsr) if tcsr is not None else None, int(src),
                                   dist_out.data_ptr(), int(alpha), int(beta), ctypes.byref(o), ctypes.byref(st)),
            "pasgal_bfs_do")
+    return (dist_out, st.as_dict()) if stats else dist_out
+
+
+def sssp(g: DeviceGraph, weights, src: int, dist_out=None, stats: bool = False, **opts):
+    """Shortest-path distances with non-negative integer arc weights (a device
+    tensor of m int32/uint32, parallel to g.targets). Returns an int32 tensor
+    holding uint32 distances (0xFFFFFFFF, i.e. -1, = unreachable). window is
+    the bucket width delta (0 = 8 x mean weight, negative = none)."""
+    torch = _torch()
+    if dist_out is None:
+        dist_out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    if weights.numel() != g.m:
+        raise ValueError("one weight per arc")
+    csr = g.csr()
+    delta = int(opts.pop("window", 0))
+    o = _opts(**opts)
+    o.window = delta if delta >= 0 else -1
+    st = L.Stats()
+    wp = weights.data_ptr() if g.m > 0 else None
+    _check(L.load().pasgal_sssp(ctypes.byref(csr), wp, int(src), dist_out.data_ptr(), ctypes.byref(o),
+                                ctypes.byref(st)), "pasgal_sssp")
     return (dist_out, st.as_dict()) if stats else dist_out
 
 

@@ -273,7 +273,7 @@ void fill_stats_from_ctl(const Ctl &c, pasgal_stats *st, bool add) {
 // One query (or one mask word) on one CSR, persistent VGC launch.
 static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *state, const uint32_t *sv,
                           const unsigned long long *sval, int nseed, const Opts &o, pasgal_stats *st,
-                          bool add_stats) {
+                          bool add_stats, const uint32_t *wgt = nullptr) {
   hipStream_t s = o.stream;
   const uint64_t n = (uint64_t)g->n;
   const uint64_t cap = default_cap(o.cap, n);
@@ -322,6 +322,7 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   VgcArgs a{};
   a.off = g->offsets;
   a.tgt = g->targets;
+  a.wgt = wgt;
   a.state = state;
   a.dirty = (uint32_t *)w.dirty.p;
   a.qi = (const QInfo *)w.qi.p;
@@ -349,7 +350,7 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   w.slices.apply(a, o.heavy, hcap, false);
 
   if ((e = hipEventRecord(w.ev0, s)) != hipSuccess) return hip_fail(e);
-  if (kind == KIND_BFS)
+  if (kind != KIND_REACH)
     e = launch_fill_u32((uint32_t *)state, n, 0xFFFFFFFFu, s);
   else
     e = launch_fill_u64((unsigned long long *)state, n, 0ull, s);
@@ -538,6 +539,40 @@ int pasgal_bfs_ex(const pasgal_csr *g, int32_t src, int32_t *dist_out, const pas
   if (o.mode == PASGAL_MODE_PLAIN)
     return run_plain(*w, KIND_BFS, g, dist_out, &sv, &val, 1, o, stats, false);
   return run_vgc_single(*w, KIND_BFS, g, dist_out, &sv, &val, 1, o, stats, false);
+}
+
+int pasgal_sssp(const pasgal_csr *g, const uint32_t *weights, int32_t src, uint32_t *dist_out,
+                const pasgal_opts *opts, pasgal_stats *stats) {
+  if (!csr_valid(g) || !dist_out || (g->m > 0 && !weights) || src < 0 || src >= g->n || !opts_valid(opts))
+    return PASGAL_EINVAL;
+  Opts o = resolve_opts(opts);
+  o.prefetch = false;
+  if (o.mode == PASGAL_MODE_PLAIN) o.tau = 1;
+  Workspace *w = workspace_for(o.stream);
+  if (!w) return PASGAL_ENOMEM;
+  std::lock_guard<std::mutex> lk(w->mu);
+  int rc;
+  hipError_t e;
+  if (o.flags & PASGAL_FLAG_VALIDATE) {
+    if ((rc = validate_csr_device(*w, g, o.stream))) return rc;
+  }
+  if (!opts || opts->window == 0) {
+    // default bucket width: 8 mean arc weights. Local searches run in FIFO,
+    // not distance, order, so a wider bucket costs re-expansions
+    if ((rc = grow(w->aux, 64)) || (rc = grow_host(w->h_aux, 64))) return rc;
+    if ((e = launch_fill_u32((uint32_t *)w->aux.p, 2, 0u, o.stream)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_sum_u32(weights, (uint64_t)g->m, (unsigned long long *)w->aux.p, o.stream)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = hipMemcpyAsync(w->h_aux.p, w->aux.p, 8, hipMemcpyDeviceToHost, o.stream)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = hipStreamSynchronize(o.stream)) != hipSuccess) return hip_fail(e);
+    const unsigned long long sum = *(const unsigned long long *)w->h_aux.p;
+    const double mean = g->m > 0 ? (double)sum / (double)g->m : 1.0;
+    o.window = (uint32_t)std::min(std::max(8.0 * mean, 1.0), 2147483647.0);
+  }
+  const uint32_t sv = (uint32_t)src;
+  const unsigned long long val = 0ull;
+  return run_vgc_single(*w, KIND_SSSP, g, dist_out, &sv, &val, 1, o, stats, false, weights);
 }
 
 int pasgal_bfs(const pasgal_csr *g, int32_t src, int32_t *dist_out) {

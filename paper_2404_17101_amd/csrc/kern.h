@@ -3,6 +3,7 @@
 // Device data layout (all in HBM):
 //   CSR        offsets int32[n+1], targets int32[m] (caller's, read-only)
 //   state      BFS: uint32 dist[v] (0xFFFFFFFF = unreached = -1 as int32)
+//              SSSP: uint32 dist[v], weighted (0xFFFFFFFF = unreached)
 //              REACH: uint64 mask[v] (bit i = source i of the request)
 //              A launch serves several queries: query q's value of global
 //              vertex v lives at state[qi[q].sbase + v].
@@ -21,7 +22,7 @@
 
 namespace pg {
 
-enum Kind : int { KIND_BFS = 0, KIND_REACH = 1 };
+enum Kind : int { KIND_BFS = 0, KIND_REACH = 1, KIND_SSSP = 2 };
 
 struct QInfo {
   int64_t sbase;  // state index of global vertex v is sbase + v
@@ -68,6 +69,7 @@ struct Frontier {
 struct VgcArgs {
   const int32_t *off;
   const int32_t *tgt;
+  const uint32_t *wgt;    // SSSP: weight of each arc (parallel to tgt); unused otherwise
   void *state;
   uint32_t *dirty;
   const QInfo *qi;
@@ -81,7 +83,7 @@ struct VgcArgs {
   uint32_t ring_cap;      // LDS ring entries per wave (power of two)
   uint32_t stage_cap;     // LDS staging entries per wave
   uint32_t min_chunk;     // frontier entries a wavefront takes at least per local search
-  uint32_t window;        // BFS: round r of query q expands only distances below
+  uint32_t window;        // BFS / SSSP: round r of query q expands only distances below
                           // (round_base + r + 1 - qi[q].r0) * window; 0 = no limit
   uint32_t round_base;    // absolute number of the launch's first round
   uint32_t test_first;    // plain load before each atomic to skip relaxations that cannot succeed
@@ -113,7 +115,7 @@ struct SeedEnt {
 // plus 64 words of scan scratch, 16-byte aligned.
 __host__ __device__ inline size_t vgc_lds_bytes(int kind, bool multi, bool pf, int waves, uint32_t ring_cap,
                                                 uint32_t stage_cap) {
-  const size_t vsz = (kind == KIND_BFS) ? 4 : 8;
+  const size_t vsz = (kind == KIND_REACH) ? 8 : 4;
   size_t per = (size_t)(ring_cap + stage_cap) * (vsz + 4 + (multi ? 4 : 0)) + (pf ? 8 * (size_t)ring_cap : 0) +
                64 * 4;
   per = (per + 15) & ~(size_t)15;
@@ -121,6 +123,8 @@ __host__ __device__ inline size_t vgc_lds_bytes(int kind, bool multi, bool pf, i
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t val, hipStream_t s);
+// *out += sum of p[0..n) (64-bit; *out is not cleared).
+hipError_t launch_sum_u32(const uint32_t *p, uint64_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long val, hipStream_t s);
 // Zero the control block, set cnt[0] = start_cnt + nseed and ovf[0]; write the
 // seed entries into frontier buffer start_buf after start_cnt and apply them

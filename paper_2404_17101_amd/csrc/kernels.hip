@@ -80,11 +80,14 @@ template <>
 struct ValT<KIND_BFS> { using T = uint32_t; };
 template <>
 struct ValT<KIND_REACH> { using T = unsigned long long; };
+template <>
+struct ValT<KIND_SSSP> { using T = uint32_t; };
 
 template <int KIND, bool MULTI, bool PF>
 struct Wave {
   using Val = typename ValT<KIND>::T;
-  static constexpr bool FIFO = (KIND == KIND_BFS);  // BFS: local BFS order; reach: LIFO (deep first)
+  static constexpr bool FIFO = (KIND != KIND_REACH);  // distances: local BFS order; reach: LIFO (deep first)
+  static constexpr bool DIST = (KIND != KIND_REACH);  // BFS and SSSP: uint32 distances lowered by atomicMin
   // PF: local-queue entries carry their vertex's arc range, loaded while the
   // relaxing atomic is in flight, so expanding them starts at the targets.
 
@@ -139,7 +142,7 @@ struct Wave {
   // BFS window: distances below the limit may be expanded in this round;
   // the rest wait in the frontier (bucket width a.window per round).
   __device__ __forceinline__ uint32_t limit_of(uint32_t q) const {
-    if (KIND != KIND_BFS || a.window == 0) return 0xFFFFFFFFu;
+    if (!DIST || a.window == 0) return 0xFFFFFFFFu;
     const uint32_t r0 = MULTI ? a.qi[q].r0 : 0u;
     const uint64_t lim = (uint64_t)(rabs + 1u - r0) * a.window;
     return lim > 0xFFFFFFFEull ? 0xFFFFFFFFu : (uint32_t)lim;
@@ -236,7 +239,7 @@ struct Wave {
   __device__ __forceinline__ void push(bool p, uint32_t w, uint32_t q, Val nv, bool ring_ok, int32_t nb = 0,
                                       int32_t ne = 0) {
     // BFS window: values at or beyond the round's limit wait for a later round
-    if (KIND == KIND_BFS && a.window) {
+    if (DIST && a.window) {
       const bool late = p && (uint32_t)nv >= limit_of(q);
       push_stage(late, w, q, nv);
       p = p && !late;
@@ -278,13 +281,17 @@ struct Wave {
   // the current value. Cached loads cost far less than the agent-scope
   // atomic, which is performed past the L2. With PF the arc range of w is
   // loaded alongside.
-  __device__ __forceinline__ bool relax(int64_t sb, uint32_t w, Val val, Val &nv, int32_t &nb, int32_t &ne) {
+  __device__ __forceinline__ bool relax(int64_t sb, uint32_t w, int32_t arc, Val val, Val &nv, int32_t &nb,
+                                       int32_t &ne) {
     if (PF) {
       nb = a.off[w];
       ne = a.off[w + 1];
     }
-    if (KIND == KIND_BFS) {
-      const uint32_t nd = (uint32_t)val + 1u;
+    if (DIST) {
+      // SSSP distances saturate below the "unreached" value
+      const uint32_t nd = (KIND == KIND_SSSP)
+                              ? (uint32_t)min((unsigned long long)val + a.wgt[arc], 0xFFFFFFFEull)
+                              : (uint32_t)val + 1u;
       nv = (Val)nd;
       uint32_t *p = (uint32_t *)&state[sb + w];
       if (a.test_first && *(const uint32_t *)p <= nd) return false;
@@ -368,7 +375,7 @@ struct Wave {
       b = a.off[v];
       e = a.off[v + 1];
     }
-    if (KIND == KIND_BFS && act && check_stale) {
+    if (DIST && act && check_stale) {
       // a smaller distance is already known: another entry carries it
       const uint32_t cur = ld_ag((uint32_t *)&state[sb + v]);
       if (cur < (uint32_t)val) act = false;
@@ -392,7 +399,7 @@ struct Wave {
         ok[u] = false;
         nv[u] = 0;
         nb[u] = ne[u] = 0;
-        if ((uint32_t)u < deg) ok[u] = relax(sb, (uint32_t)w[u], val, nv[u], nb[u], ne[u]);
+        if ((uint32_t)u < deg) ok[u] = relax(sb, (uint32_t)w[u], b + u, val, nv[u], nb[u], ne[u]);
       }
       uint32_t nsucc = 0, arcs = 0;
 #pragma clang loop unroll(full)
@@ -429,7 +436,7 @@ struct Wave {
       const uint32_t qo = MULTI ? (uint32_t)__shfl(q, owner) : 0u;
       const int64_t sbo = MULTI ? (int64_t)shfl64((unsigned long long)sb, owner) : 0;
       Val vo;
-      if (KIND == KIND_BFS)
+      if (DIST)
         vo = (Val)__shfl((uint32_t)val, owner);
       else
         vo = (Val)shfl64((unsigned long long)val, owner);
@@ -438,8 +445,9 @@ struct Wave {
       Val nv = 0;
       int32_t nb = 0, ne = 0;
       if (okl) {
-        w = (uint32_t)a.tgt[bo + (int32_t)(ai - eo)];
-        ok = relax(sbo, w, vo, nv, nb, ne);
+        const int32_t arc = bo + (int32_t)(ai - eo);
+        w = (uint32_t)a.tgt[arc];
+        ok = relax(sbo, w, arc, vo, nv, nb, ne);
       }
       nsucc += __popcll(__ballot(ok));
       push(ok, w, qo, nv, ring_ok, nb, ne);
@@ -573,7 +581,7 @@ struct Wave {
           if (MULTI) q = ld_ag(&a.fr.q[cbuf][base + j + ln]);
           val = (Val)ld_ag(&a.fr.val[cbuf][base + j + ln]);
         }
-        if (KIND == KIND_BFS && a.window) {  // roots beyond the window wait for a later round
+        if (DIST && a.window) {  // roots beyond the window wait for a later round
           const bool defer = has && (uint32_t)val >= limit_of(q);
           push_stage(defer, v, q, val);
           has = has && !defer;
@@ -627,7 +635,7 @@ struct Wave {
           val = ld_ag(&state[sb + v]);
         }
         bool go = has;
-        if (KIND == KIND_BFS && a.window) {
+        if (DIST && a.window) {
           const bool defer = has && (uint32_t)val >= limit_of(q);
           push_stage(defer, v, q, val);
           go = has && !defer;
@@ -731,7 +739,7 @@ __global__ void seed_kernel(VgcArgs a, const SeedEnt *seeds, uint32_t nseed, uin
     const SeedEnt s = seeds[i];
     const QInfo qi = a.qi[s.q];
     Val *state = (Val *)a.state;
-    if (KIND == KIND_BFS)
+    if (KIND != KIND_REACH)
       min_ag((uint32_t *)&state[qi.sbase + s.v], (uint32_t)s.val);
     else
       or_ag((unsigned long long *)&state[qi.sbase + s.v], (unsigned long long)s.val);
@@ -788,18 +796,38 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
   return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256) sum_u32_kernel(const uint32_t *p, uint64_t n, unsigned long long *out) {
+  unsigned long long s = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) s += p[i];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += shfl64(s, (int)(lane_id() ^ (uint32_t)d));
+  if (lane_id() == 0 && s) add_ag(out, s);
+}
+
+hipError_t launch_sum_u32(const uint32_t *p, uint64_t n, unsigned long long *out, hipStream_t s) {
+  (void)hipGetLastError();  // report only this launch's error
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_t nseed, uint32_t start_cnt,
                        uint32_t start_ovf, hipStream_t s) {
   (void)hipGetLastError();  // report only this launch's error
   const int grid = (int)((nseed + 255) / 256) > 0 ? (int)((nseed + 255) / 256) : 1;
   if (kind == KIND_BFS)
     hipLaunchKernelGGL(seed_kernel<KIND_BFS>, dim3(grid), dim3(256), 0, s, a, seeds, nseed, start_cnt, start_ovf);
+  else if (kind == KIND_SSSP)
+    hipLaunchKernelGGL(seed_kernel<KIND_SSSP>, dim3(grid), dim3(256), 0, s, a, seeds, nseed, start_cnt, start_ovf);
   else
     hipLaunchKernelGGL(seed_kernel<KIND_REACH>, dim3(grid), dim3(256), 0, s, a, seeds, nseed, start_cnt, start_ovf);
   return hipGetLastError();
 }
 
 const void *vgc_kernel_ptr(int kind, bool multi, bool pf) {
+  if (kind == KIND_SSSP)  // one query per launch, arc ranges loaded when expanded
+    return (multi || pf) ? nullptr : (const void *)vgc_kernel<KIND_SSSP, false, false>;
   if (kind == KIND_BFS) {
     if (multi) return pf ? (const void *)vgc_kernel<KIND_BFS, true, true> : (const void *)vgc_kernel<KIND_BFS, true, false>;
     return pf ? (const void *)vgc_kernel<KIND_BFS, false, true> : (const void *)vgc_kernel<KIND_BFS, false, false>;
@@ -813,6 +841,7 @@ hipError_t launch_vgc(int kind, bool multi, bool pf, const VgcArgs &a, int grid,
                       bool cooperative, hipStream_t s) {
   (void)hipGetLastError();  // report only this launch's error
   const void *fn = vgc_kernel_ptr(kind, multi, pf);
+  if (!fn) return hipErrorInvalidDeviceFunction;
   VgcArgs copy = a;
   void *args[] = {&copy};
   if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, s);

@@ -73,6 +73,23 @@ def test_c2_knn10m_single_source_calls(pg, knn10m):
     assert np.array_equal(pg.reach(d, [s]).cpu().numpy().view(np.uint64)[:, 0] == 1, exp >= 0)
 
 
+def test_c2_knn10m_sssp_against_dijkstra(pg, knn10m):
+    """Weighted shortest paths on the 10M-point 5-NN graph (weights uniform in
+    [1, 1000], seed 2002) from one source, element by element."""
+    g = knn10m
+    w = gg.weights(g, 2002, 1, 1000)
+    d = pg.DeviceGraph.from_graph(g)
+    wd = torch.from_numpy(w.view(np.int32)).cuda()
+    s = int(gg.sources(g, 16, 1002)[0])
+    _say("c2 sssp dijkstra")
+    exp = oracle.sssp(g, w, s)
+    for kw in [dict(), dict(mode="plain")]:
+        _say(f"c2 sssp {kw}")
+        got = pg.sssp(d, wd, s, **kw).cpu().numpy().view(np.uint32).astype(np.int64)
+        got[got == 0xFFFFFFFF] = -1
+        assert np.array_equal(got, exp), kw
+
+
 def test_c3_road4096_forward_backward_scc(pg):
     g = gg.road(4096, 3)
     d = pg.DeviceGraph.from_graph(g)
