@@ -72,6 +72,47 @@ def _counter_means(path):
     return {k: sum(v) / len(v) for k, v in agg.items()}
 
 
+SUITE_TRACES = {
+    "scc": ("Kernel trace: SCC suite (road4096, knn 10M/5, RMAT-20; VGC, tau 1, no trim, no split; 3 runs each)",
+            "vgc_kernel<1, false, false> is the reach kernel running the forward and backward searches of a "
+            "batch together on the packed 2n-vertex graph; pack_kernel<false/true> count and scatter the arcs that "
+            "stay inside one subproblem; union_kernel / piece_label_kernel are the weak-connectivity split; "
+            "trim_kernel, select_kernel, refine_kernel and min_member_kernel are the per-batch steps."),
+    "sssp": ("Kernel trace: SSSP suite (knn 10M/5, road4096, RMAT-22; weights uniform in [1, 1000]; VGC and tau 1)",
+             "vgc_kernel<2, false, false> is the SSSP kernel (kind 2 = weighted distances); sum_u32_kernel is the "
+             "mean-weight reduction behind the default bucket width."),
+    "bfs_do": ("Kernel trace: direction-optimizing BFS suite (RMAT-24 and knn 10M/5, 4 sources each)",
+               "bottom_up_kernel, collect_kernel and degsum_kernel belong to the direction-optimizing BFS; "
+               "plain_level_kernel<0> runs its top-down levels and the plain BFS; vgc_kernel<0, false, false> is the "
+               "VGC BFS."),
+}
+
+
+def summarize_suite_trace(suite, d):
+    """profiles/<suite>_trace.md from the kernel-stats CSV of a traced suite run."""
+    import csv
+
+    title, note = SUITE_TRACES[suite]
+    rows = list(csv.DictReader(open(os.path.join(d, f"prof_{suite}", "run_kernel_stats.csv"))))
+    lines = [f"# {title}", "", "Command (GPU host, `TMPDIR=/tmp`, run from `/tmp`):", "", "```",
+             f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_{suite} -o run -- \\",
+             f"    python3 <repo>/bench.py --suite {suite}", "```", "",
+             f"Summarised by `python bench.py --summarize-suite-trace {suite} <out>`. Times include every "
+             f"configuration the suite runs; rocprofv3 may end with a segmentation fault in its own exit handler "
+             f"after the program's last line, the CSV files were complete.", "",
+             "| kernel | calls | avg (ms) | min (ms) | max (ms) | total (ms) | share |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:14]:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 80:
+            name = name[:77] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                     f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.1f}% |")
+    lines += ["", note]
+    with open(os.path.join(ROOT, "profiles", f"{suite}_trace.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def summarize_profiles(d, args):
     """Turn the rocprofv3 CSVs of the trace, counter and copy-calibration runs
     into the committed summaries under profiles/."""
@@ -163,6 +204,8 @@ def main():
     ap.add_argument("--suite", choices=["c1", "c3", "c4", "c5", "scc", "sssp", "bfs_do"], default=None,
                     help="run one of the other configurations instead of the headline job (one JSON line)")
     ap.add_argument("--rates", default="5,10,20,40,100,300,1000,3000,10000", help="c5: Poisson arrival rates (q/s)")
+    ap.add_argument("--summarize-suite-trace", nargs=2, metavar=("SUITE", "DIR"), default=None,
+                    help="write profiles/SUITE_trace.md from DIR/prof_SUITE/run_kernel_stats.csv")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSV output under DIR (prof_trace, prof_fetch, "
                          "prof_write, prof_cfetch, prof_cwrite)")
@@ -170,6 +213,9 @@ def main():
 
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args)
+        return
+    if args.summarize_suite_trace:
+        summarize_suite_trace(*args.summarize_suite_trace)
         return
 
     if args.suite:

@@ -84,3 +84,32 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
+    """Argument checks happen before any HIP call, so they run without a GPU."""
+    from paper_2404_17101_amd import _lib as L
+    L._lib = None
+    lib = L.load()
+    P = ctypes.POINTER
+    csr = L.Csr(0, 0, None, None)  # n = 0 is invalid
+    out = ctypes.c_void_p(1)
+    assert lib.pasgal_scc(ctypes.byref(csr), None, out, None, None, None) == -1
+    assert lib.pasgal_sssp(ctypes.byref(csr), None, 0, out, None, None) == -1
+    assert lib.pasgal_bfs_do(ctypes.byref(csr), None, 0, out, 0, 0, None, None) == -1
+    good = L.Csr(4, 0, ctypes.c_void_p(1), None)
+    # SCC: unknown flag bits and a transpose of another size are rejected
+    so = L.SccOpts(-1, 0x80, 0, 0)
+    assert lib.pasgal_scc(ctypes.byref(good), None, out, ctypes.byref(so), None, None) == -1
+    other = L.Csr(5, 0, ctypes.c_void_p(1), None)
+    assert lib.pasgal_scc(ctypes.byref(good), ctypes.byref(other), out, None, None, None) == -1
+    # sources out of range, missing output
+    assert lib.pasgal_sssp(ctypes.byref(good), None, 4, out, None, None) == -1
+    assert lib.pasgal_bfs_do(ctypes.byref(good), None, -1, out, 0, 0, None, None) == -1
+    assert lib.pasgal_bfs_do(ctypes.byref(good), None, 0, None, 0, 0, None, None) == -1
+    # a nonzero reserved field in the options is rejected
+    o = L.Opts()
+    lib.pasgal_opts_default(ctypes.byref(o))
+    assert o.heavy_arcs == 512
+    o.reserved = 1
+    assert lib.pasgal_bfs_ex(ctypes.byref(good), 0, out, ctypes.byref(o), None) == -1
