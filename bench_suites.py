@@ -234,7 +234,7 @@ def suite_bfs_do(args, pg, gg, torch):
         entry = {"graph": name, "n": g.n, "m": g.m, "reached_arcs_src0": arcs, "gpu": {}}
         for label, fn in [("vgc", lambda s: pg.bfs(d, s)), ("plain", lambda s: pg.bfs(d, s, mode="plain")),
                           ("direction_optimizing", lambda s: pg.bfs_do(d, s, transpose=t)),
-                          ("direction_optimizing_alpha50", lambda s: pg.bfs_do(d, s, transpose=t, alpha=50))]:
+                          ("direction_optimizing_alpha14", lambda s: pg.bfs_do(d, s, transpose=t, alpha=14))]:
             ok = bool(np.array_equal(fn(srcs[0]).cpu().numpy(), exp))
             ts = []
             for s in srcs:

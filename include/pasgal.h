@@ -156,7 +156,7 @@ int pasgal_sssp(const pasgal_csr *g, const uint32_t *weights, int32_t src, uint3
  * when g is symmetric (every arc u->v has its reverse v->u), in which case g
  * serves as its own transpose; a NULL gt with a directed g gives wrong
  * distances. alpha: go bottom-up when the arcs out of the frontier exceed
- * 1/alpha of the arcs out of unreached vertices (0 selects 14, < 0 never);
+ * 1/alpha of the arcs out of unreached vertices (0 selects 100, < 0 never);
  * beta: go back top-down when the frontier holds fewer than n/beta vertices
  * (0 selects 24, < 0 never). Output exactly as pasgal_bfs. Synchronous on
  * opts->stream (PASGAL_FLAG_ASYNC is rejected); opts->mode, tau and window are

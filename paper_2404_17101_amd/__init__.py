@@ -131,7 +131,7 @@ def bfs_do(g: DeviceGraph, src: int, transpose: DeviceGraph | None = None, dist_
            beta: int = 0, stats: bool = False, **opts):
     """Direction-optimizing BFS (top-down / bottom-up levels). transpose: G^T;
     None only when g is symmetric. alpha / beta: switching thresholds (0 =
-    defaults 14 / 24, negative = never switch that way). Same output as bfs."""
+    defaults 100 / 24, negative = never switch that way). Same output as bfs."""
     torch = _torch()
     if dist_out is None:
         dist_out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)

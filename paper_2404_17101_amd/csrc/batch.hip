@@ -95,6 +95,28 @@ struct pasgal_batch {
     return PASGAL_OK;
   }
 
+  // Reallocate the frontier buffers (and the slice buffers sized from them)
+  // at a smaller capacity; the launch arguments follow.
+  int shrink_frontier(uint64_t c) {
+    int rc = PASGAL_OK;
+    for (int i = 0; i < 2 && !rc; i++) {
+      for (DBuf *d : {&fv[i], &fq[i], &fval[i]}) free_buf(*d);
+      rc = grow(fv[i], 4 * c);
+      if (!rc) rc = grow(fq[i], 4 * c);
+      if (!rc) rc = grow(fval[i], 8 * c);
+    }
+    if (rc) return rc;
+    cap = c;
+    for (int i = 0; i < 2; i++) {
+      args.fr.v[i] = (uint32_t *)fv[i].p;
+      args.fr.q[i] = (uint32_t *)fq[i].p;
+      args.fr.val[i] = (unsigned long long *)fval[i].p;
+    }
+    args.fr.cap = (uint32_t)c;
+    hcap = std::min<uint32_t>(hcap, (uint32_t)std::max<uint64_t>(c, 64));
+    return PASGAL_OK;
+  }
+
   // Direct (uncaptured) run; returns the device time in ms through *ms.
   int run_direct(float *ms) {
     hipError_t e;
@@ -309,6 +331,33 @@ int pasgal_batch_create(const pasgal_batch_desc *d, const pasgal_opts *opts, uin
       return PASGAL_ETIMEOUT;
     }
     o = best_o;
+    // Frontier capacity: the smallest of cap, cap/4, cap/16 (at least 64 Ki
+    // entries) whose time stays within 5% of the best. A smaller frontier
+    // sends overflow through the dirty bitmaps, exact but usually slower, so
+    // this only trades footprint for time where it costs nothing.
+    if ((rc = b->configure(o))) {
+      delete b;
+      return rc;
+    }
+    const uint64_t full = b->cap;
+    uint64_t chosen = full;
+    for (uint64_t c = full / 4; c >= (1u << 16) && c >= full / 16; c /= 4) {
+      b->args.fr.cap = (uint32_t)c;
+      float ms = 0;
+      rc = b->run_direct(&ms);
+      if (rc == PASGAL_OK) rc = b->run_direct(&ms);
+      if (rc == PASGAL_ETIMEOUT) break;
+      if (rc != PASGAL_OK) {
+        delete b;
+        return rc;
+      }
+      if (ms <= 1.05f * best) chosen = c;
+    }
+    b->args.fr.cap = (uint32_t)full;
+    if (chosen < full && (rc = b->shrink_frontier(chosen))) {
+      delete b;
+      return rc;
+    }
   }
   if ((rc = b->configure(o))) {
     delete b;

@@ -56,8 +56,9 @@ namespace {
 enum : int { C_NPIV = 0, C_DEFER, C_POOL, C_TRIM, C_COMPS, C_UNSETTLED, C_COUNT = 8 };
 
 // Source rows of a pack: rows [0, n) from (offA, tgtA), rows [n, 2n) from
-// (offB, tgtB) read at row index v - n. Targets may be local ([0, n)) or
-// already packed (backward rows in [n, 2n)).
+// (offB, tgtB) read at row index v - n. Targets are either local vertex ids
+// in [0, n) (the caller's G and G^T) or packed ids (backward rows pointing
+// into [n, 2n)).
 struct PackIn {
   const int32_t *offA, *tgtA;
   const int32_t *offB, *tgtB;
@@ -489,7 +490,6 @@ SccBufs *scc_bufs(Workspace *w) {
 }
 
 struct SccRun {
-  Workspace &w;
   SccBufs &b;
   hipStream_t s;
   uint32_t n;
@@ -629,7 +629,7 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
   uint32_t *slot_base = (uint32_t *)B.slot_base.p;
   uint32_t *piv_v = (uint32_t *)B.piv_v.p, *piv_bit = (uint32_t *)B.piv_bit.p;
   int32_t *pivtab = (int32_t *)B.pivtab.p;
-  SccRun R{*w, B, s, n};
+  SccRun R{B, s, n};
   uint32_t *ctr = R.counters();
   uint32_t *h_ctr = (uint32_t *)B.h_read.p;
   Ctl *h_ctl = (Ctl *)((uint8_t *)B.h_read.p + 4 * C_COUNT);
