@@ -213,8 +213,9 @@ typedef struct pasgal_scc_stats {
                                   64 pivots per batch) */
 
 typedef struct pasgal_scc_opts {
-  int32_t trim_rounds; /* trimming passes before the first batch (the loop stops at a pass that settles
-                          nothing), plus one pass after every batch; < 0 selects 8, 0 disables trimming */
+  int32_t trim_rounds; /* trimming passes before the first batch (the loop stops after a pass that
+                          settles fewer than n/1024 vertices), plus one pass after every batch; < 0
+                          selects 8, 0 disables trimming */
   uint32_t flags;      /* PASGAL_SCC_* */
   uint32_t seed;       /* key of the random pivot order; 0 selects a fixed default. The result does not
                           depend on it. */

@@ -692,9 +692,12 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
     if (got == 0) break;
     if ((e = R.pack(R.packed_in(), R.cur ^ 1, comp, label)) != hipSuccess) return fail(e);
     R.cur ^= 1;
+    // a pass that settles few vertices is not worth another full repack: the
+    // pass after every batch picks up what is left
+    if (got < std::max<int64_t>(1, (int64_t)n / 1024)) break;
   }
-
-  if (split && (e = R.split_pieces(comp, label)) != hipSuccess) return fail(e);
+  // no weak-connectivity split yet: most inputs are one piece until the
+  // first batch removes their giant component
 
   int64_t batches = 0, pivots = 0, rounds = 0, arcs = 0;
   double reach_ms = 0;

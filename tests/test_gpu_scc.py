@@ -110,7 +110,7 @@ def test_scc_many_pivots_per_subproblem_repeat_batches(pg):
     """600 disjoint 2-cycles, no trimming and no weak-connectivity split: a
     batch of 512 positions holds far more than 64 unsettled vertices of the
     one initial subproblem, so batches must repeat until every draw got a
-    bit. With the split every pair is its own subproblem from the start."""
+    bit. With the split every pair is its own subproblem after the first batch."""
     g = _disjoint_two_cycles(600)
     exp = oracle.scc_min_label(g)
     assert np.array_equal(exp, (np.arange(g.n) // 2 * 2).astype(np.int32))
