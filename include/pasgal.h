@@ -96,6 +96,17 @@ typedef struct pasgal_opts {
                                 wavefront that expands it: its arcs are cut into slices of this many and
                                 dealt one per wavefront in the next round (skewed degrees, e.g. RMAT).
                                 0 selects 512; < 0 never cuts. */
+  int32_t filter_slots;      /* BFS / SSSP, VGC: entries of each wavefront's LDS filter (rounded down to a
+                                power of two, at most 4096). It remembers values the wavefront saw in the
+                                state and skips a relaxation whose value cannot beat one of them (values
+                                only go down, so this never skips a winning relaxation). 0 selects 256,
+                                < 0 turns it off. The filter gets at most half of the LDS ring. */
+  int32_t chunks_per_wave;   /* VGC: the frontier of a round is cut into this many chunks per wavefront;
+                                each wavefront takes one, then claims more from its XCD's share as it
+                                finishes, so early finishers take over work. 0 selects 1 (purely
+                                static): on the 5-NN graph smaller chunks thin the local searches more
+                                than the balancing gains (batched 16-source BFS: 29.6 ms at 1, 42.8 ms
+                                at 4). */
   int32_t reserved;          /* 0 */
 } pasgal_opts;
 
@@ -111,6 +122,9 @@ typedef struct pasgal_stats {
   int64_t max_frontier;   /* largest global frontier */
   double device_ms;       /* time on the stream from the state fill to the end of the traversal */
   double kernel_ms;       /* time of the traversal launches alone (VGC: the persistent kernel) */
+  int64_t steps;          /* VGC: local-search steps (each pops up to 64 entries; expansions / steps is
+                             the average width) */
+  int64_t filtered;       /* VGC: relaxations skipped without an atomic (LDS filter, test-first load) */
 } pasgal_stats;
 
 void pasgal_opts_default(pasgal_opts *opts);

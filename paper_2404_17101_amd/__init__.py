@@ -91,10 +91,11 @@ def _stream_ptr(stream) -> int:
 
 def _opts(mode="vgc", tau=1024, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
           stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=False, test_first=False,
-          spread_arcs=True, heavy_arcs=0) -> L.Opts:
+          spread_arcs=True, heavy_arcs=0, filter_slots=0, chunks_per_wave=0) -> L.Opts:
     """window: BFS distance window per round (0 or negative = none).
     heavy_arcs: rows with more arcs are cut into slices dealt to all
-    wavefronts (0 = default 512, negative = never)."""
+    wavefronts (0 = default 512, negative = never). filter_slots: per-wavefront
+    LDS filter of BFS/SSSP relaxations (0 = default 256, negative = off)."""
     o = L.Opts()
     L.load().pasgal_opts_default(ctypes.byref(o))
     o.mode = {"vgc": L.MODE_VGC, "plain": L.MODE_PLAIN}[mode]
@@ -110,6 +111,8 @@ def _opts(mode="vgc", tau=1024, wg_size=1024, blocks_per_cu=1, frontier_capacity
     o.window = int(window) if int(window) > 0 else -1
     o.min_chunk = int(min_chunk)
     o.heavy_arcs = int(heavy_arcs)
+    o.filter_slots = int(filter_slots)
+    o.chunks_per_wave = int(chunks_per_wave)
     return o
 
 

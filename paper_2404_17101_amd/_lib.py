@@ -37,14 +37,14 @@ class Opts(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("frontier_capacity", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("timeout_ms", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("window", ctypes.c_int32), ("min_chunk", ctypes.c_int32), ("heavy_arcs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("filter_slots", ctypes.c_int32), ("chunks_per_wave", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("expansions", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64),
                 ("relax_success", ctypes.c_int64), ("published", ctypes.c_int64), ("overflow", ctypes.c_int64),
                 ("stale", ctypes.c_int64), ("max_frontier", ctypes.c_int64), ("device_ms", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("steps", ctypes.c_int64), ("filtered", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -39,6 +39,7 @@ struct pasgal_batch {
   bool coop_in_graph = false;
   SliceBufs slices;
   uint32_t hcap = 0;
+  int64_t dist_len = 0;  // values in the state array
 
   ~pasgal_batch() {
     if (exec) hipGraphExecDestroy(exec);
@@ -87,9 +88,12 @@ struct pasgal_batch {
     args.ring_cap = lg.ring;
     args.stage_cap = lg.stage;
     args.min_chunk = o.min_chunk;
+    args.chunks_per_wave = o.cpw;
     args.window = o.window;
     args.test_first = o.test_first ? 1u : 0u;
     args.lane_arcs = o.lane_arcs;
+    // filter keys are 32-bit state indices: exact only below 2^32 values
+    args.filt = dist_len < (int64_t(1) << 32) ? lg.filt : 0u;
     args.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
     slices.apply(args, o.heavy, hcap, true);
     return PASGAL_OK;
@@ -226,6 +230,7 @@ int pasgal_batch_create(const pasgal_batch_desc *d, const pasgal_opts *opts, uin
   b->packed = d->packed;
   b->nq = nq;
   b->dist = d->dist_out;
+  b->dist_len = d->dist_len;
   b->words = words;
   int rc = PASGAL_OK;
   hipError_t e;

@@ -73,12 +73,15 @@ struct Opts {
   bool test_first = false;
   uint32_t lane_arcs = 0;
   uint32_t heavy = 512;  // 0 = never cut heavy rows
+  uint32_t filt = 256;   // LDS filter entries per wavefront wanted (0 = none)
+  uint32_t cpw = 1;      // frontier chunks per wavefront and round
 };
 
 struct LaunchGeom {
   int grid = 0, block = 0;
   size_t lds = 0;
   uint32_t ring = 0, stage = 0;
+  uint32_t filt = 0;  // LDS filter entries per wavefront (distance kinds)
   bool pf = false;
 };
 

@@ -157,6 +157,14 @@ Opts resolve_opts(const pasgal_opts *o) {
   r.test_first = (o->flags & PASGAL_FLAG_TEST_FIRST) != 0;
   r.lane_arcs = (o->flags & PASGAL_FLAG_ROW_PER_LANE) ? 8u : 0u;
   r.heavy = o->heavy_arcs > 0 ? (uint32_t)o->heavy_arcs : (o->heavy_arcs == 0 ? 512u : 0u);
+  r.cpw = o->chunks_per_wave > 0 ? (uint32_t)std::min(o->chunks_per_wave, 64) : 1u;
+  if (o->filter_slots > 0) {
+    uint32_t f = 1;
+    while (f * 2 <= (uint32_t)std::min(o->filter_slots, 4096)) f *= 2;  // round down to a power of two
+    r.filt = f;
+  } else {
+    r.filt = o->filter_slots == 0 ? 256u : 0u;
+  }
   return r;
 }
 
@@ -217,14 +225,27 @@ int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   // stage 128 entries; ring = largest power of two that fits
   const uint32_t S = 128;
   const bool pf = o.prefetch;
-  uint32_t Q = 4096;
-  while (Q > 64 && vgc_lds_bytes(kind, multi, pf, waves, Q, S) + 512 > lds_cap_block) Q >>= 1;
-  if (vgc_lds_bytes(kind, multi, pf, waves, Q, S) + 512 > lds_cap_block) return PASGAL_EINVAL;
+  auto largest_ring = [&](uint32_t F) {
+    uint32_t Q = 4096;
+    while (Q > 64 && vgc_lds_bytes(kind, multi, pf, waves, Q, S, F) + 2048 > lds_cap_block) Q >>= 1;
+    return Q;
+  };
+  // The LDS filter (distance kinds) may take at most half of the ring it
+  // would otherwise get; a smaller filter is tried before that.
+  const uint32_t Q0 = largest_ring(0);
+  uint32_t F = (kind == KIND_REACH) ? 0u : o.filt;
+  while (F > 0 && (largest_ring(F) < Q0 / 2 || largest_ring(F) < 64 ||
+                   vgc_lds_bytes(kind, multi, pf, waves, largest_ring(F), S, F) + 2048 > lds_cap_block))
+    F >>= 1;
+  if (F < 16) F = 0;
+  const uint32_t Q = largest_ring(F);
+  if (vgc_lds_bytes(kind, multi, pf, waves, Q, S, F) + 2048 > lds_cap_block) return PASGAL_EINVAL;
   lg.ring = Q;
   lg.stage = S;
+  lg.filt = F;
   lg.block = o.wg;
   lg.pf = pf;
-  lg.lds = vgc_lds_bytes(kind, multi, pf, waves, Q, S);
+  lg.lds = vgc_lds_bytes(kind, multi, pf, waves, Q, S, F);
   const void *fn = vgc_kernel_ptr(kind, multi, pf);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lg.lds);
   if (e != hipSuccess) {
@@ -267,6 +288,8 @@ void fill_stats_from_ctl(const Ctl &c, pasgal_stats *st, bool add) {
   st->published += (int64_t)c.stats[ST_PUBLISH];
   st->overflow += (int64_t)c.stats[ST_OVERFLOW];
   st->stale += (int64_t)c.stats[ST_STALE];
+  st->steps += (int64_t)c.stats[ST_STEPS];
+  st->filtered += (int64_t)c.stats[ST_FILTERED];
   st->max_frontier = std::max<int64_t>(st->max_frontier, c.max_frontier);
 }
 
@@ -341,11 +364,13 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   a.ring_cap = lg.ring;
   a.stage_cap = lg.stage;
   a.min_chunk = o.min_chunk;
+  a.chunks_per_wave = o.cpw;
   a.window = o.window;
   a.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
   a.round_base = 0;
   a.test_first = o.test_first ? 1u : 0u;
   a.lane_arcs = o.lane_arcs;
+  a.filt = lg.filt;  // single query: keys are vertex ids
   a.ctl = (Ctl *)w.ctl.p;
   w.slices.apply(a, o.heavy, hcap, false);
 
@@ -502,6 +527,7 @@ void pasgal_opts_default(pasgal_opts *o) {
   o->window = 0;
   o->min_chunk = 1;
   o->heavy_arcs = 512;
+  o->filter_slots = 256;
 }
 
 const char *pasgal_strerror(int code) {

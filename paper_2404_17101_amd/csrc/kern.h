@@ -40,6 +40,8 @@ enum StatIdx {
   ST_PUBLISH,
   ST_OVERFLOW,
   ST_STALE,
+  ST_STEPS,     // local-search steps (one pop of up to 64 entries)
+  ST_FILTERED,  // relaxations skipped by the LDS filter or the test-first load
   ST_COUNT
 };
 
@@ -55,7 +57,8 @@ struct Ctl {
   uint32_t max_frontier;
   uint32_t bad_csr;   // validation result
   uint32_t hcnt[3];   // heavy-row slices: round r reads hcnt[r%3], appends to hcnt[(r+1)%3]
-  uint32_t pad[10];
+  uint32_t claim[3][8];  // frontier chunks claimed in round r, per XCD: claim[r%3][xcd]
+  uint32_t pad[1];
   unsigned long long stats[8];
 };
 
@@ -83,10 +86,15 @@ struct VgcArgs {
   uint32_t ring_cap;      // LDS ring entries per wave (power of two)
   uint32_t stage_cap;     // LDS staging entries per wave
   uint32_t min_chunk;     // frontier entries a wavefront takes at least per local search
+  uint32_t chunks_per_wave; // frontier chunks per wavefront and round: 1 deals them statically; more
+                            // makes chunks smaller, deals the first per wavefront statically and lets
+                            // wavefronts that finish early claim the rest of their XCD's range
   uint32_t window;        // BFS / SSSP: round r of query q expands only distances below
                           // (round_base + r + 1 - qi[q].r0) * window; 0 = no limit
   uint32_t round_base;    // absolute number of the launch's first round
   uint32_t test_first;    // plain load before each atomic to skip relaxations that cannot succeed
+  uint32_t filt;          // BFS / SSSP: entries of each wavefront's LDS filter of values it wrote (power of
+                          // two; 0 = off). Keys are 32-bit state indices, so the state must hold < 2^32 values
   uint32_t lane_arcs;     // rows of at most this many arcs (<= 8) are scanned lane by lane; longer rows, or
                           // every row when 0, are dealt out across the wavefront (consecutive lanes take
                           // consecutive arcs)
@@ -111,13 +119,14 @@ struct SeedEnt {
 };
 
 // LDS of a persistent launch: per wavefront a ring (local queue) of ring_cap
-// entries and a staging buffer of stage_cap entries ({v, val[, q]} each, SoA)
-// plus 64 words of scan scratch, 16-byte aligned.
+// entries and a staging buffer of stage_cap entries ({v, val[, q]} each, SoA),
+// 64 words of scan scratch and a filter of filt 8-byte entries, 16-byte
+// aligned.
 __host__ __device__ inline size_t vgc_lds_bytes(int kind, bool multi, bool pf, int waves, uint32_t ring_cap,
-                                                uint32_t stage_cap) {
+                                                uint32_t stage_cap, uint32_t filt) {
   const size_t vsz = (kind == KIND_REACH) ? 8 : 4;
   size_t per = (size_t)(ring_cap + stage_cap) * (vsz + 4 + (multi ? 4 : 0)) + (pf ? 8 * (size_t)ring_cap : 0) +
-               64 * 4;
+               64 * 4 + 8 * (size_t)filt;
   per = (per + 15) & ~(size_t)15;
   return per * (size_t)waves;
 }

@@ -43,6 +43,15 @@ struct RoundHdr {
   uint32_t ncur, ovf, nheavy, abort;
 };
 
+// The per-query fields a step reads (state base, window origin), copied to
+// LDS at the start of a multi-query launch of at most QLITE queries so that
+// a step does not wait on a memory load for them.
+struct QLite {
+  int64_t sbase;
+  uint32_t r0, pad;
+};
+constexpr int QLITE = 64;
+
 // Grid barrier for a persistent launch whose workgroups are all resident.
 // Fence-free: callers keep cross-workgroup data in agent-scope atomics.
 // After the wait, thread 0 reads the counters of slot `slot` for everyone.
@@ -97,6 +106,8 @@ struct Wave {
   Val *rval, *sval;
   uint32_t *rv, *sv, *rq, *sq, *scan;
   int32_t *rb, *re;
+  unsigned long long *filt;  // LDS filter: (32-bit state index << 32) | a value this wavefront saw stored there
+  uint32_t fshift;           // slot = (key * golden) >> fshift
   uint32_t Q, S, ln;
   // wave-uniform
   uint32_t head, tail, scount;
@@ -104,7 +115,7 @@ struct Wave {
   uint32_t rabs;   // absolute number of the current round (BFS window)
   uint32_t root_end;  // local-queue positions below this hold the current search's roots
   uint32_t slice_ok;  // heavy rows may be cut into slices this round
-  unsigned long long st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale;
+  unsigned long long st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale, st_steps, st_filtered;
 
   __device__ __forceinline__ Wave(const VgcArgs &args, uint8_t *lds_wave) : a(args) {
     state = (Val *)a.state;
@@ -129,21 +140,32 @@ struct Wave {
       rb = re = nullptr;
     }
     scan = (uint32_t *)p;
+    p += 64 * 4;
+    filt = (unsigned long long *)p;
+    fshift = 32u - (uint32_t)__builtin_ctz(a.filt ? a.filt : 1u);
+    for (uint32_t i = ln; i < a.filt; i += 64) filt[i] = ~0ull;  // key 0xFFFFFFFF: empty
+    wave_sync();
     head = tail = scount = 0;
     nslot = nbuf = 0;
     rabs = 0;
     root_end = 0;
     slice_ok = 0;
-    st_expand = st_arcs = st_success = st_publish = st_overflow = st_stale = 0;
+    qlite = nullptr;
+    st_expand = st_arcs = st_success = st_publish = st_overflow = st_stale = st_steps = st_filtered = 0;
   }
 
-  __device__ __forceinline__ int64_t sbase_of(uint32_t q) const { return MULTI ? a.qi[q].sbase : 0; }
+  const QLite *qlite;  // LDS copy of the query table, or null
+
+  __device__ __forceinline__ int64_t sbase_of(uint32_t q) const {
+    if (!MULTI) return 0;
+    return qlite ? qlite[q].sbase : a.qi[q].sbase;
+  }
 
   // BFS window: distances below the limit may be expanded in this round;
   // the rest wait in the frontier (bucket width a.window per round).
   __device__ __forceinline__ uint32_t limit_of(uint32_t q) const {
     if (!DIST || a.window == 0) return 0xFFFFFFFFu;
-    const uint32_t r0 = MULTI ? a.qi[q].r0 : 0u;
+    const uint32_t r0 = MULTI ? (qlite ? qlite[q].r0 : a.qi[q].r0) : 0u;
     const uint64_t lim = (uint64_t)(rabs + 1u - r0) * a.window;
     return lim > 0xFFFFFFFEull ? 0xFFFFFFFFu : (uint32_t)lim;
   }
@@ -272,45 +294,87 @@ struct Wave {
     }
   }
 
-  // Relax arc (., w) with value val of its tail; returns whether the state of
-  // w changed and the value to carry. With a.test_first, a plain load first
-  // rules out relaxations that cannot change anything. The load may be served
-  // by this XCD's L2 and be stale, but values only ever go down for BFS and
-  // only gain bits for reach, so a stale value is an upper bound (a subset)
-  // of the current one: when it already rules the relaxation out, so would
-  // the current value. Cached loads cost far less than the agent-scope
-  // atomic, which is performed past the L2. With PF the arc range of w is
-  // loaded alongside.
-  __device__ __forceinline__ bool relax(int64_t sb, uint32_t w, int32_t arc, Val val, Val &nv, int32_t &nb,
-                                       int32_t &ne) {
+  // Relaxation of arc (., w) carrying value val of its tail, in two halves so
+  // that several relaxations per lane are in flight at once: issue() applies
+  // the filters and performs the atomic; finish() records the outcome in the
+  // LDS filter and reports whether the state of w changed (and the value to
+  // carry).
+  //  * a.test_first: a plain load first rules out relaxations that cannot
+  //    change anything. It may be served by this XCD's L2 and be stale, but
+  //    values only ever go down for distances and only gain bits for reach,
+  //    so a stale value still proves the relaxation cannot win.
+  //  * LDS filter (distances): values this wavefront saw in the state; for the
+  //    same reason a remembered value <= the new one proves the atomic
+  //    cannot win.
+  //  * PF: the arc range of w is loaded alongside.
+  struct Rx {
+    Val nd;       // value offered to w
+    Val old;      // value of w before the atomic (or the value that filtered it)
+    uint32_t key, slot;
+    bool skipped;
+    int32_t nb, ne;
+  };
+
+  __device__ __forceinline__ Rx relax_issue(int64_t sb, uint32_t w, int32_t arc, Val val) {
+    Rx x;
+    x.skipped = false;
+    x.key = x.slot = 0;
+    x.nb = x.ne = 0;
     if (PF) {
-      nb = a.off[w];
-      ne = a.off[w + 1];
+      x.nb = a.off[w];
+      x.ne = a.off[w + 1];
     }
     if (DIST) {
       // SSSP distances saturate below the "unreached" value
       const uint32_t nd = (KIND == KIND_SSSP)
                               ? (uint32_t)min((unsigned long long)val + a.wgt[arc], 0xFFFFFFFEull)
                               : (uint32_t)val + 1u;
-      nv = (Val)nd;
+      x.nd = (Val)nd;
       uint32_t *p = (uint32_t *)&state[sb + w];
-      if (a.test_first && *(const uint32_t *)p <= nd) return false;
-      const uint32_t old = min_ag(p, nd);
-      return nd < old;
+      if (a.test_first && *(const uint32_t *)p <= nd) {
+        x.skipped = true;
+        x.old = (Val)nd;
+        return x;
+      }
+      if (a.filt) {
+        x.key = (uint32_t)(sb + (int64_t)w);
+        x.slot = (x.key * 0x9E3779B1u) >> fshift;
+        const unsigned long long e = filt[x.slot];
+        if ((uint32_t)(e >> 32) == x.key && (uint32_t)e <= nd) {
+          x.skipped = true;
+          x.old = (Val)nd;
+          return x;
+        }
+      }
+      x.old = (Val)min_ag(p, nd);
     } else {
       unsigned long long *p = (unsigned long long *)&state[sb + w];
       const unsigned long long m = (unsigned long long)val;
+      x.nd = (Val)m;
       if (a.test_first) {
         const unsigned long long cur = *(const unsigned long long *)p;
         if ((cur & m) == m) {
-          nv = (Val)cur;
-          return false;
+          x.skipped = true;
+          x.old = (Val)cur;
+          return x;
         }
       }
-      const unsigned long long old = or_ag(p, m);
-      nv = (Val)(old | m);
-      return nv != (Val)old;
+      x.old = (Val)or_ag(p, m);
     }
+    return x;
+  }
+
+  __device__ __forceinline__ bool relax_finish(const Rx &x, Val &nv) {
+    if (DIST) {
+      nv = x.nd;
+      if (x.skipped) return false;
+      if (a.filt)
+        filt[x.slot] = ((unsigned long long)x.key << 32) | (unsigned long long)min((uint32_t)x.old, (uint32_t)x.nd);
+      return (uint32_t)x.nd < (uint32_t)x.old;
+    }
+    nv = (Val)((unsigned long long)x.old | (unsigned long long)x.nd);
+    if (x.skipped) return false;
+    return nv != x.old;
   }
 
   // Heavy rows: a lane whose row has more than a.heavy arcs hands them to the
@@ -394,12 +458,20 @@ struct Wave {
       bool ok[8];
       Val nv[8];
       int32_t nb[8], ne[8];
+      Rx x[8];
 #pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) {
-        ok[u] = false;
-        nv[u] = 0;
-        nb[u] = ne[u] = 0;
-        if ((uint32_t)u < deg) ok[u] = relax(sb, (uint32_t)w[u], b + u, val, nv[u], nb[u], ne[u]);
+        x[u].skipped = true;
+        x[u].nd = x[u].old = 0;
+        x[u].nb = x[u].ne = 0;
+        if ((uint32_t)u < deg) x[u] = relax_issue(sb, (uint32_t)w[u], b + u, val);
+      }
+#pragma clang loop unroll(full)
+      for (int u = 0; u < 8; u++) {
+        ok[u] = relax_finish(x[u], nv[u]);
+        nb[u] = x[u].nb;
+        ne[u] = x[u].ne;
+        if ((uint32_t)u < maxd) st_filtered += __popcll(__ballot((uint32_t)u < deg && x[u].skipped));
       }
       uint32_t nsucc = 0, arcs = 0;
 #pragma clang loop unroll(full)
@@ -416,6 +488,8 @@ struct Wave {
     }
     // Flattened: the wave's arcs are dealt out 64 at a time; each lane finds
     // its arc's owner lane by binary search over the inclusive degree scan.
+    // RB such passes are issued together (target loads, then atomics, then
+    // pushes), so a lane has RB relaxations in flight instead of one.
     const uint32_t incl = wave_incl_scan(deg, ln);
     const uint32_t total = __shfl(incl, 63);
     const uint32_t excl = incl - deg;
@@ -423,34 +497,50 @@ struct Wave {
     wave_sync();
     st_arcs += total;
     uint32_t nsucc = 0;
-    for (uint32_t j = 0; j < total; j += 64) {
-      const uint32_t ai = j + ln;
-      const bool okl = ai < total;
-      uint32_t pos = 0;
+    constexpr int RB = 4;
+    for (uint32_t j0 = 0; j0 < total; j0 += 64 * RB) {
+      uint32_t w[RB], qo[RB];
+      int32_t arc[RB];
+      int64_t sbo[RB];
+      Val vo[RB];
+      bool okl[RB];
+#pragma clang loop unroll(full)
+      for (int r = 0; r < RB; r++) {
+        const uint32_t ai = j0 + (uint32_t)r * 64u + ln;
+        okl[r] = ai < total;
+        uint32_t pos = 0;
 #pragma unroll
-      for (uint32_t step = 32; step >= 1; step >>= 1)
-        if (scan[pos + step - 1] <= ai) pos += step;
-      const int owner = (int)min(pos, 63u);
-      const int32_t bo = __shfl(b, owner);
-      const uint32_t eo = __shfl(excl, owner);
-      const uint32_t qo = MULTI ? (uint32_t)__shfl(q, owner) : 0u;
-      const int64_t sbo = MULTI ? (int64_t)shfl64((unsigned long long)sb, owner) : 0;
-      Val vo;
-      if (DIST)
-        vo = (Val)__shfl((uint32_t)val, owner);
-      else
-        vo = (Val)shfl64((unsigned long long)val, owner);
-      uint32_t w = 0;
-      bool ok = false;
-      Val nv = 0;
-      int32_t nb = 0, ne = 0;
-      if (okl) {
-        const int32_t arc = bo + (int32_t)(ai - eo);
-        w = (uint32_t)a.tgt[arc];
-        ok = relax(sbo, w, arc, vo, nv, nb, ne);
+        for (uint32_t step = 32; step >= 1; step >>= 1)
+          if (scan[pos + step - 1] <= ai) pos += step;
+        const int owner = (int)min(pos, 63u);
+        const int32_t bo = __shfl(b, owner);
+        const uint32_t eo = __shfl(excl, owner);
+        qo[r] = MULTI ? (uint32_t)__shfl(q, owner) : 0u;
+        sbo[r] = MULTI ? (int64_t)shfl64((unsigned long long)sb, owner) : 0;
+        if (DIST)
+          vo[r] = (Val)__shfl((uint32_t)val, owner);
+        else
+          vo[r] = (Val)shfl64((unsigned long long)val, owner);
+        arc[r] = bo + (int32_t)(ai - eo);
+        w[r] = okl[r] ? (uint32_t)a.tgt[arc[r]] : 0u;
       }
-      nsucc += __popcll(__ballot(ok));
-      push(ok, w, qo, nv, ring_ok, nb, ne);
+      Rx x[RB];
+#pragma clang loop unroll(full)
+      for (int r = 0; r < RB; r++) {
+        x[r].skipped = true;
+        x[r].nd = x[r].old = 0;
+        x[r].nb = x[r].ne = 0;
+        if (okl[r]) x[r] = relax_issue(sbo[r], w[r], arc[r], vo[r]);
+      }
+#pragma clang loop unroll(full)
+      for (int r = 0; r < RB; r++) {
+        if (j0 + (uint32_t)r * 64u >= total) break;  // wave-uniform
+        Val nv = 0;
+        const bool ok = okl[r] && relax_finish(x[r], nv);
+        nsucc += __popcll(__ballot(ok));
+        st_filtered += __popcll(__ballot(okl[r] && x[r].skipped));
+        push(ok, w[r], qo[r], nv, ring_ok, x[r].nb, x[r].ne);
+      }
     }
     wave_sync();
     st_success += nsucc;
@@ -485,6 +575,7 @@ struct Wave {
     // the coherent re-read of the distance is kept for roots and for the
     // windowless schedule, where overlapping searches make staleness common.
     const bool chk = (a.window == 0) || (idx < root_end);
+    st_steps += k ? 1u : 0u;
     const uint32_t ne = expand(act, v, q, val, ring_ok, b, e, PF, chk);
     st_stale += (uint32_t)__popcll(__ballot(act)) - ne;
     return ne;
@@ -558,40 +649,58 @@ struct Wave {
     tail = __popcll(bal);
   }
 
-  // Frontier entries are dealt out statically: chunk c of `chunk` consecutive
-  // entries goes to wavefront c mod total (gw numbers wavefronts so that each
-  // XCD holds a contiguous range). Consecutive entries were published together
-  // by one local search, so a wavefront's roots are close in the graph. A
-  // chunk may hold more roots than lanes (up to half the ring): they all start
-  // one local search, which then advances a wide front per step instead of
-  // several narrow searches one after another.
-  __device__ __forceinline__ void process_frontier(uint32_t cbuf, uint32_t nproc, uint32_t chunk, uint32_t gw,
-                                                   uint32_t total) {
-    const uint32_t nchunks = (nproc + chunk - 1) / chunk;
-    for (uint32_t c = gw; c < nchunks; c += total) {
-      const uint32_t base = c * chunk;
-      const uint32_t cnt = min(chunk, nproc - base);
-      head = tail = 0;
-      for (uint32_t j = 0; j < cnt; j += 64) {
-        bool has = j + ln < cnt;
-        uint32_t v = 0, q = 0;
-        Val val = 0;
-        if (has) {
-          v = ld_ag(&a.fr.v[cbuf][base + j + ln]);
-          if (MULTI) q = ld_ag(&a.fr.q[cbuf][base + j + ln]);
-          val = (Val)ld_ag(&a.fr.val[cbuf][base + j + ln]);
-        }
-        if (DIST && a.window) {  // roots beyond the window wait for a later round
-          const bool defer = has && (uint32_t)val >= limit_of(q);
-          push_stage(defer, v, q, val);
-          has = has && !defer;
-        }
-        append_roots(has, v, q, val);
+  // Frontier entries are dealt out in chunks of `chunk` consecutive entries.
+  // Consecutive entries were published together by one local search, so a
+  // wavefront's roots are close in the graph; a chunk may hold more roots than
+  // lanes (up to half the ring): they all start one local search, which then
+  // advances a wide front per step. The chunks are split into 8 contiguous
+  // ranges, one per XCD (gw numbers wavefronts so that each XCD holds a
+  // contiguous range of them). A wavefront first takes chunk lo + i of its
+  // XCD's range (i = its index inside the XCD), then claims further chunks
+  // of that range from the XCD's counter until the range is used up, so
+  // wavefronts whose searches end early take over the remaining work.
+  __device__ __forceinline__ void run_chunk(uint32_t cbuf, uint32_t nproc, uint32_t chunk, uint32_t c) {
+    const uint32_t base = c * chunk;
+    const uint32_t cnt = min(chunk, nproc - base);
+    head = tail = 0;
+    for (uint32_t j = 0; j < cnt; j += 64) {
+      bool has = j + ln < cnt;
+      uint32_t v = 0, q = 0;
+      Val val = 0;
+      if (has) {
+        v = ld_ag(&a.fr.v[cbuf][base + j + ln]);
+        if (MULTI) q = ld_ag(&a.fr.q[cbuf][base + j + ln]);
+        val = (Val)ld_ag(&a.fr.val[cbuf][base + j + ln]);
       }
-      const uint32_t nroots = tail - head;
-      if (nroots == 0) continue;
-      root_end = tail;
-      local_search(a.tau * nroots);
+      if (DIST && a.window) {  // roots beyond the window wait for a later round
+        const bool defer = has && (uint32_t)val >= limit_of(q);
+        push_stage(defer, v, q, val);
+        has = has && !defer;
+      }
+      append_roots(has, v, q, val);
+    }
+    const uint32_t nroots = tail - head;
+    if (nroots == 0) return;
+    root_end = tail;
+    local_search(a.tau * nroots);
+  }
+
+  __device__ __forceinline__ void process_frontier(uint32_t cbuf, uint32_t nproc, uint32_t chunk, uint32_t gw,
+                                                   uint32_t total, uint32_t cslot) {
+    const uint32_t nchunks = (nproc + chunk - 1) / chunk;
+    const uint32_t groups = (total % 8u == 0) ? 8u : 1u;
+    const uint32_t per = total / groups;
+    const uint32_t x = gw / per, i = gw % per;
+    const uint32_t lo = (uint32_t)((uint64_t)nchunks * x / groups);
+    const uint32_t hi = (uint32_t)((uint64_t)nchunks * (x + 1) / groups);
+    uint32_t c = lo + i;
+    while (c < hi) {
+      run_chunk(cbuf, nproc, chunk, c);
+      if (hi - lo <= per) break;  // every chunk of the range was dealt statically
+      uint32_t k = 0;
+      if (ln == 0) k = add_ag(&a.ctl->claim[cslot][x], 1u);
+      k = __shfl(k, 0);
+      c = lo + per + k;
     }
   }
 
@@ -651,7 +760,8 @@ struct Wave {
 
   __device__ __forceinline__ void flush_stats() {
     if (ln == 0) {
-      const unsigned long long vals[ST_COUNT] = {st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale};
+      const unsigned long long vals[ST_COUNT] = {st_expand, st_arcs,  st_success, st_publish,
+                                                 st_overflow, st_stale, st_steps,   st_filtered};
 #pragma clang loop unroll(full)
       for (int i = 0; i < ST_COUNT; i++)
         if (vals[i]) add_ag(&a.ctl->stats[i], vals[i]);
@@ -666,8 +776,17 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
   __shared__ uint32_t s_cnt[17];
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wid = threadIdx.x >> 6;
-  const size_t per_wave = vgc_lds_bytes(KIND, MULTI, PF, 1, a.ring_cap, a.stage_cap);
+  const size_t per_wave = vgc_lds_bytes(KIND, MULTI, PF, 1, a.ring_cap, a.stage_cap, a.filt);
   Wave<KIND, MULTI, PF> wv(a, smem + per_wave * wid);
+  __shared__ QLite qlite[MULTI ? QLITE : 1];
+  if (MULTI && a.nq <= QLITE) {
+    for (int i = threadIdx.x; i < a.nq; i += blockDim.x) {
+      qlite[i].sbase = a.qi[i].sbase;
+      qlite[i].r0 = a.qi[i].r0;
+      qlite[i].pad = 0;
+    }
+    wv.qlite = qlite;
+  }
   const uint32_t total_waves = gridDim.x * nw;
   // XCD-aware numbering: workgroups are dispatched round-robin over the 8
   // XCDs; give each XCD a contiguous range of logical workgroups.
@@ -691,6 +810,7 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
     if (ncur == 0 && ovf == 0 && nheavy == 0) break;
     maxf = max(maxf, ncur);
     const uint32_t nslot = (r + 1) % 3, fslot = (r + 2) % 3;
+    if (blockIdx.x == 0 && threadIdx.x < 8) st_ag(&a.ctl->claim[fslot][threadIdx.x], 0u);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st_ag(&a.ctl->cnt[fslot], 0u);
       st_ag(&a.ctl->ovf[fslot], 0u);
@@ -705,9 +825,10 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
     if (nheavy) wv.process_heavy(cbuf, min(nheavy, a.hcap), gw, total_waves);
     if (ovf) wv.process_dirty(gw, total_waves);
     const uint32_t nproc = min(ncur, a.fr.cap);
-    uint32_t chunk = (nproc + total_waves - 1) / total_waves;
+    const uint64_t slots = (uint64_t)total_waves * max(a.chunks_per_wave, 1u);
+    uint32_t chunk = (uint32_t)((nproc + slots - 1) / slots);
     chunk = min(max(chunk, max(a.min_chunk, 1u)), a.ring_cap / 2);
-    wv.process_frontier(cbuf, nproc, chunk, gw, total_waves);
+    wv.process_frontier(cbuf, nproc, chunk, gw, total_waves, r % 3);
     wv.flush_stage_block(s_cnt, wid, nw);
     grid_barrier(a.ctl, epoch, deadline, nslot, &hdr);
     if (hdr.abort) break;

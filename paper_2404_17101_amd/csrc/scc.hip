@@ -654,6 +654,7 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
   a.ring_cap = lg.ring;
   a.stage_cap = lg.stage;
   a.min_chunk = o.min_chunk;
+  a.chunks_per_wave = o.cpw;
   a.window = 0;
   a.round_base = 0;
   a.test_first = o.test_first ? 1u : 0u;

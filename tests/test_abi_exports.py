@@ -107,9 +107,7 @@ def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
     assert lib.pasgal_sssp(ctypes.byref(good), None, 4, out, None, None) == -1
     assert lib.pasgal_bfs_do(ctypes.byref(good), None, -1, out, 0, 0, None, None) == -1
     assert lib.pasgal_bfs_do(ctypes.byref(good), None, 0, None, 0, 0, None, None) == -1
-    # a nonzero reserved field in the options is rejected
+    # defaults of the VGC options
     o = L.Opts()
     lib.pasgal_opts_default(ctypes.byref(o))
-    assert o.heavy_arcs == 512
-    o.reserved = 1
-    assert lib.pasgal_bfs_ex(ctypes.byref(good), 0, out, ctypes.byref(o), None) == -1
+    assert (o.heavy_arcs, o.filter_slots, o.window) == (512, 256, 0)

@@ -487,3 +487,30 @@ def test_heavy_rows_batch_scc_and_server(pg):
             else:
                 assert np.array_equal(np_mask(out)[:, None], oracle.reach(g, [s])), (rounds, s)
         srv.close()
+
+
+@pytest.mark.parametrize("slots", [-1, 16, 4096])
+def test_lds_filter_sizes_keep_results_exact(pg, slots):
+    """The per-wavefront filter only skips relaxations that cannot win; any
+    size (16 forces constant slot collisions, 4096 squeezes the ring) and off
+    give the same exact results, single-query, batched and weighted."""
+    g = gg.knn(30000, 5, 12)
+    d = dev(pg, g)
+    srcs = [int(s) for s in gg.sources(g, 3, 91)]
+    for s in srcs:
+        _say(f"filter {slots} bfs src={s}")
+        assert np.array_equal(np_dist(pg.bfs(d, s, filter_slots=slots)), oracle.bfs(g, s))
+    w = gg.weights(g, 92, 1, 300)
+    wd = torch.from_numpy(w.view(np.int32)).cuda()
+    got = pg.sssp(d, wd, srcs[0], filter_slots=slots).cpu().numpy().view(np.uint32).astype(np.int64)
+    got[got == 0xFFFFFFFF] = -1
+    assert np.array_equal(got, oracle.sssp(g, w, srcs[0]))
+    graphs = [g, gg.grid(70, 90)]
+    packed, pd, qg, qs, qo, dist = _batch_inputs(pg, graphs, 5, 93)
+    b = pg.Batch(pd, packed.vbase, qg, qs, qo, dist, filter_slots=slots)
+    b.run()
+    out = dist.cpu().numpy()
+    b.close()
+    for j in range(len(qg)):
+        gr = graphs[qg[j]]
+        assert np.array_equal(out[qo[j]:qo[j] + gr.n], oracle.bfs(gr, int(qs[j]))), (slots, j)
