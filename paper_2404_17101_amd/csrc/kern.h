@@ -46,8 +46,13 @@ enum StatIdx {
 };
 
 struct Ctl {
+  // Words that many waiters poll sit on 128-byte lines of their own (the
+  // buffer is 256-byte aligned), away from the frontier tails that every
+  // flush updates atomically.
   uint32_t bar;       // grid-barrier arrivals within one launch
+  uint32_t pad_bar[31];
   uint32_t abort;     // set when a bounded wait expired
+  uint32_t pad_abort[31];
   uint32_t cnt[3];    // frontier tails: round r reads cnt[r%3], appends to cnt[(r+1)%3]
   uint32_t ovf[3];    // ovf[(r+1)%3] != 0: round r+1 must rescan the dirty bitmaps
   uint32_t rounds;    // rounds run by the launch (exit record)

@@ -62,9 +62,9 @@ __device__ void grid_barrier(Ctl *ctl, uint32_t &epoch, long long deadline, uint
     epoch += 1;
     const uint32_t target = epoch * gridDim.x;
     add_ag(&ctl->bar, 1u);
-    uint32_t ab = 0;
+    uint32_t ab = 0, polls = 0;
     while (ld_ag(&ctl->bar) < target) {
-      if (ld_ag(&ctl->abort)) { ab = 1; break; }
+      if ((++polls & 15u) == 0 && ld_ag(&ctl->abort)) { ab = 1; break; }
       if (wall_clock64() > deadline) {
         st_ag(&ctl->abort, 1u);
         ab = 1;
