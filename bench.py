@@ -9,6 +9,11 @@ batch of sources, inputs resident in HBM:
     (pasgal_batch_run, hipGraph-captured), and
   * reachability from the 16 sources in one VGC launch with 16-bit masks
     (pasgal_reach_ex, k = 16).
+By default (--schedule concurrent) the two launches run at the same time on
+two streams, each sized to half of every compute unit (PASGAL_FLAG_HALF_DEVICE,
+512-thread workgroups): both are latency-bound, and each loses little when
+given half the wavefronts. --schedule sequential runs them one after the
+other on the whole device (1024-thread workgroups).
 value = traversed edges per second (GTEPS): per query, the arcs whose tail the
 source reaches (BFS and reach alike), summed over the 32 queries, over the
 wall time of the timed steps.
@@ -18,9 +23,12 @@ The JSON line also carries
                 achieved = algorithmic bytes of one launch (16 B per reached
                 vertex + 8 B per arc of a reached vertex, per query) / the
                 launch's duration (HIP events recorded around the kernel on
-                its own stream, averaged over the timed steps); peak 8 TB/s;
-                traffic from committed rocprofv3 counter runs when they were
-                taken on the same kernel source and setting, else null.
+                its own stream, averaged over the timed steps; under the
+                concurrent schedule the reach launch runs beside it); peak
+                8 TB/s; traffic from committed rocprofv3 counter runs when
+                they were taken on the same kernel source and setting, else
+                null. detail.job_* gives both launches' algorithmic bytes over
+                the step time.
   cpu_baseline  the CPU oracle (sequential queue BFS / DFS reach, one host
                 thread) on a bounded sample of the same queries.
   extras        single-source calls: plain (one launch per BFS level) vs VGC
@@ -28,7 +36,8 @@ The JSON line also carries
                 own roofline figure.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--tau T] [--window W]
-                [--layout morton|draw] [--no-extras] [--no-cpu]
+                [--schedule concurrent|sequential] [--layout morton|draw]
+                [--no-extras] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -131,8 +140,12 @@ def summarize_profiles(d, args):
     traffic_b = F[kb] * 1024 * f_scale + W[kb] * 1024 * w_scale
     traffic_r = F[kr] * 1024 * f_scale + W[kr] * 1024 * w_scale
     avg = {r["Name"]: float(r["AverageNs"]) / 1e6 for r in rows}
+    wg = args.wg if args.wg > 0 else (512 if args.schedule == "concurrent" else 1024)
+    sched = ("the two launches run concurrently on two streams, each on half of every CU "
+             f"({wg}-thread workgroups)" if args.schedule == "concurrent" else
+             f"the two launches run one after the other ({wg}-thread workgroups)")
     out = {"kernel": kb, "kernel_hash": kernel_source_hash(), "layout": args.layout, "tau": args.tau,
-           "window": args.window, "fetch_kib_per_dispatch": round(F[kb], 1), "write_kib_per_dispatch": round(W[kb], 1),
+           "window": args.window, "wg_size": wg, "schedule": args.schedule, "fetch_kib_per_dispatch": round(F[kb], 1), "write_kib_per_dispatch": round(W[kb], 1),
            "copy_calibration": {"fetch_kib_per_1GiB_copy": round(CF[cp], 1), "write_kib_per_1GiB_copy": round(CW[cp], 1),
                                 "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)},
            "hbm_bytes_per_launch": int(traffic_b), "kernel_avg_ms": round(avg.get(kb, 0.0), 4),
@@ -147,8 +160,8 @@ def summarize_profiles(d, args):
              "    python3 <repo>/bench.py --steps 2 --warmup 1 --no-extras --no-cpu", "```", "",
              f"Summarised by `python bench.py --summarize-profiles <out>`. Workload: directed 5-NN graph of 10^7 "
              f"uniform points ({args.layout} layout), 16 sources; each step is one batched VGC BFS launch (16 "
-             f"queries, tau {args.tau}, window {args.window}) and one 16-source VGC reach launch; 1 warm-up + 2 "
-             f"timed steps. rocprofv3 may end with a segmentation fault in its own exit handler after the "
+             f"queries, tau {args.tau}, window {args.window}) and one 16-source VGC reach launch; {sched}; "
+             f"1 warm-up + 2 timed steps. rocprofv3 may end with a segmentation fault in its own exit handler after the "
              f"program's last line; the CSV files were complete.", "",
              "| kernel | calls | avg (ms) | min (ms) | max (ms) | share |", "|---|---|---|---|---|---|"]
     for r in rows[:8]:
@@ -177,6 +190,8 @@ def summarize_profiles(d, args):
              f"| `{cp}`, 1 GiB copy (calibration) | {CF[cp]:,.1f} | {CW[cp]:,.1f} | 2.15 GB |", "",
              f"Calibration: a plain 1 GiB copy reads and writes 1 GiB; the counters report {CF[cp] / 1048576:.3f} GiB and "
              f"{CW[cp] / 1048576:.3f} GiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.",
+             "", "Under counter collection the profiler runs dispatches one at a time, so these bytes are each "
+                 "kernel's own even where the bench overlaps the two launches.",
              "", "`vgc_bfs_batched16_knn10m_counters.txt` holds these figures with the hash of the kernel source they "
                  "were taken on; bench.py reports `traffic` only while that hash matches the current source."]
     with open(os.path.join(prof, "vgc_bfs_batched16_knn10m_counters.md"), "w") as f:
@@ -191,7 +206,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tau", type=int, default=1024)
     ap.add_argument("--window", type=int, default=32)
-    ap.add_argument("--wg", type=int, default=1024)
+    ap.add_argument("--wg", type=int, default=0, help="workgroup size (default 512 concurrent, 1024 sequential)")
+    ap.add_argument("--schedule", choices=["concurrent", "sequential"], default="concurrent")
     ap.add_argument("--bpc", type=int, default=1)
     ap.add_argument("--points", type=int, default=10_000_000)
     ap.add_argument("--sources", type=int, default=16)
@@ -260,7 +276,13 @@ def main():
     d = pg.DeviceGraph.from_graph(g)
     n, nq = g.n, len(srcs)
     stream = torch.cuda.current_stream()
-    vgc = dict(tau=args.tau, window=args.window, wg_size=args.wg, blocks_per_cu=args.bpc, stream=stream)
+    conc = args.schedule == "concurrent"
+    if args.wg <= 0:
+        args.wg = 512 if conc else 1024
+    vgc = dict(tau=args.tau, window=args.window, wg_size=args.wg, blocks_per_cu=args.bpc, stream=stream,
+               half_device=conc)
+    rstream = torch.cuda.Stream() if conc else stream  # the reach launch's stream
+    rvgc = dict(vgc, stream=rstream, asynchronous=conc)
 
     # outputs: 16 distance arrays (one batched launch) and one 16-bit mask word per vertex
     dist16 = torch.empty(n * nq, dtype=torch.int32, device="cuda")
@@ -271,8 +293,19 @@ def main():
     torch.cuda.synchronize()
 
     def step(rec=None):
-        bst = batch.run()
-        _, rst = pg.reach(d, srcs, label_out=mask, stats=True, **vgc)
+        if conc:
+            # reach enqueued on its own stream first, then the batch on the
+            # caller's stream; pasgal_batch_run returns when the batch is done
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(rstream)
+            pg.reach(d, srcs, label_out=mask, **rvgc)
+            e1.record(rstream)
+            bst = batch.run()
+            rst = {"events": (e0, e1)}
+        else:
+            bst = batch.run()
+            _, rst = pg.reach(d, srcs, label_out=mask, stats=True, **rvgc)
         if rec is not None:
             rec.append((bst, rst))
 
@@ -301,9 +334,20 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - ta
     gteps = edges_per_step * args.steps / wall / 1e9
+    # the timed steps must reproduce the warm-up results (distances and masks
+    # are unique), which also shows that every asynchronous launch completed
+    if not (np.array_equal(dist16.view(nq, n).cpu().numpy(), dd) and
+            np.array_equal(mask.cpu().numpy().view(np.uint64)[:, 0], mk)):
+        raise RuntimeError("timed steps did not reproduce the warm-up results")
+    for _, r in rec:
+        if "events" in r:
+            r["kernel_ms"] = r["events"][0].elapsed_time(r["events"][1])
+            r["rounds"] = float("nan")
 
     # roofline of the batched BFS kernel
     alg_bytes = float(sum(16 * a + 8 * b for a, b in zip(bfs_nr, bfs_mr)))
+    rch_alg = float(sum(20 * int(((mk >> np.uint64(i)) & np.uint64(1)).astype(bool).sum()) + 12 * rch_mr[i]
+                        for i in range(nq)))
     kms = float(np.mean([b["kernel_ms"] for b, _ in rec]))
     achieved = alg_bytes / (kms * 1e-3) / 1e9
     traffic, note = None, None
@@ -311,7 +355,8 @@ def main():
         with open(PROFILE_COUNTERS) as f:
             pc = json.load(f)
         if (pc.get("kernel_hash") == kernel_source_hash() and pc.get("layout") == args.layout
-                and pc.get("tau") == args.tau and pc.get("window") == args.window):
+                and pc.get("tau") == args.tau and pc.get("window") == args.window
+                and pc.get("wg_size", 1024) == args.wg and pc.get("schedule", "sequential") == args.schedule):
             traffic = pc.get("hbm_bytes_per_launch")
         else:
             note = "committed counter profile was taken on a different kernel source or setting"
@@ -319,18 +364,26 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "vgc_kernel<BFS, multi-query>", "kernel_ms_avg": round(kms, 4),
                 "alg_bytes_per_launch": int(alg_bytes)}
+    if conc:
+        # the reach launch runs beside this one: both launches' algorithmic
+        # bytes over the step time
+        roofline["concurrent_with"] = "16-source reach launch on a second stream"
+        roofline["pair_achieved"] = round((alg_bytes + rch_alg) / (wall / args.steps) / 1e9, 2)
+        roofline["pair_frac"] = round(roofline["pair_achieved"] / HBM_PEAK_GBS, 5)
     if note:
         roofline["note"] = note
-    rch_alg = float(sum(20 * int(((mk >> np.uint64(i)) & np.uint64(1)).astype(bool).sum()) + 12 * rch_mr[i]
-                        for i in range(nq)))
     rkms = float(np.mean([r["kernel_ms"] for _, r in rec]))
     detail = {
+        "schedule": args.schedule,
+        "job_alg_bytes_per_step": int(alg_bytes + rch_alg),
+        "job_achieved_gbs": round((alg_bytes + rch_alg) / (wall / args.steps) / 1e9, 2),
+        "job_frac": round((alg_bytes + rch_alg) / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 5),
         "bfs_batched_ms": float(np.mean([b["device_ms"] for b, _ in rec])),
         "bfs_kernel_ms": kms,
         "bfs_rounds": float(np.mean([b["rounds"] for b, _ in rec])),
         "bfs_expansions_per_reached": float(np.mean([b["expansions"] for b, _ in rec]) / sum(bfs_nr)),
-        "reach16_kernel_ms": rkms,
-        "reach16_rounds": float(np.mean([r["rounds"] for _, r in rec])),
+        "reach16_kernel_ms" if not conc else "reach16_stream_ms": rkms,
+        "reach16_rounds": float(np.mean([r["rounds"] for _, r in rec])) if not conc else None,
         "reach16_roofline_frac": round(rch_alg / (rkms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
         "reached_vertices_avg": float(np.mean(bfs_nr)),
         "reached_arcs_avg": float(np.mean(bfs_mr)),
@@ -388,6 +441,22 @@ def main():
             el = time.perf_counter() - a
             extras[f"reach_single_{label}"] = {"gteps": round(sum(rch_mr[:4]) / el / 1e9, 3),
                                                "ms_per_query": round(el / len(sub) * 1e3, 3)}
+        if conc:
+            # the same job with the two launches one after the other, each on the whole device
+            full = dict(tau=args.tau, window=args.window, wg_size=1024, blocks_per_cu=1, stream=stream)
+            sb = pg.Batch(d, vb, np.zeros(nq, np.int32), np.array(srcs, np.int32),
+                          np.arange(nq, dtype=np.int64) * n, dist16, **full)
+            for rep_ in range(2):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                for _ in range(3):
+                    sb.run()
+                    pg.reach(d, srcs, label_out=mask, **full)
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - a) / 3
+            sb.close()
+            extras["job_sequential_full_device"] = {"gteps": round(edges_per_step / el / 1e9, 3),
+                                                    "ms_per_step": round(el * 1e3, 3)}
         plain_ms = extras["bfs_single_plain"]["ms_per_query"] + extras["reach_single_plain"]["ms_per_query"]
         extras["job_plain_sequential_estimate"] = {
             "gteps": round(edges_per_step / (plain_ms * nq * 1e-3) / 1e9, 3),
@@ -408,7 +477,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"knn5 n={n} m={g.m} points uniform in [0,1)^2 (seed 2, {args.layout} layout), "
                                f"{nq} sources (seed 1002); step = 16 BFS in one batched launch + "
-                               f"16-source reach in one launch",
+                               f"16-source reach in one launch"
+                               + (", run concurrently on two streams, each on half of every CU" if conc else
+                                  ", one after the other"),
+                   "schedule": args.schedule,
                    "tau": args.tau, "window": args.window, "wg_size": args.wg, "blocks_per_cu": args.bpc},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -107,6 +107,25 @@ def suite_c3(args, pg, gg, torch):
             ts.append(time.perf_counter() - a)
         el = float(np.median(ts))
         out[label] = {"ms_forward_plus_backward": round(el * 1e3, 3), "gteps": round(credit / el / 1e9, 3)}
+    # forward and backward at the same time on two streams, each launch on
+    # half of every compute unit; both results are checked against the above
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    half = dict(tau=1024, wg_size=512, half_device=True, asynchronous=True)
+    mf = torch.empty((g.n, 1), dtype=torch.int64, device="cuda")
+    mb = torch.empty((g.n, 1), dtype=torch.int64, device="cuda")
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        pg.reach(d, pivots, label_out=mf, stream=sa, **half)
+        pg.reach(t, pivots, label_out=mb, stream=sb, **half)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - a)
+    ok = (np.array_equal(mf.cpu().numpy().view(np.uint64)[:, 0], fw) and
+          np.array_equal(mb.cpu().numpy().view(np.uint64)[:, 0], bw))
+    el = float(np.median(ts))
+    out["tau1024_concurrent_half_device"] = {"ms_forward_plus_backward": round(el * 1e3, 3),
+                                             "gteps": round(credit / el / 1e9, 3), "matches_full_device": ok}
     return {"suite": "c3", "workload": "road grid 4096x4096 (seed 3), 64 pivots, forward + backward reach",
             "n": g.n, "m": g.m, "transpose_ms": round(t_ms, 3), "teps_credit_arcs": credit, "results": out}
 

@@ -73,6 +73,12 @@ typedef struct pasgal_csr {
 #define PASGAL_FLAG_ROW_PER_LANE 16u /* VGC: scan rows of <= 8 arcs lane by lane instead of dealing every
                                         vertex's arcs out across the wavefront (default: consecutive lanes take
                                         consecutive arcs, so one memory instruction touches few cache lines) */
+#define PASGAL_FLAG_HALF_DEVICE 32u /* VGC: size the persistent launch to half of every compute unit (LDS and
+                                       wave slots for 2 x blocks_per_cu workgroups per CU; PASGAL_EINVAL if
+                                       that many do not fit) and launch it as an ordinary kernel, so that a
+                                       second such call on another stream runs beside it: the two grids always
+                                       fit the device together. A grid that cannot become resident (a third
+                                       launch holding the CUs) ends in PASGAL_ETIMEOUT, never a hang. */
 
 typedef struct pasgal_opts {
   int32_t mode;              /* PASGAL_MODE_VGC or PASGAL_MODE_PLAIN */

@@ -91,11 +91,13 @@ def _stream_ptr(stream) -> int:
 
 def _opts(mode="vgc", tau=1024, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
           stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=False, test_first=False,
-          spread_arcs=True, heavy_arcs=0, filter_slots=0, chunks_per_wave=0) -> L.Opts:
+          spread_arcs=True, heavy_arcs=0, filter_slots=0, chunks_per_wave=0, half_device=False) -> L.Opts:
     """window: BFS distance window per round (0 or negative = none).
     heavy_arcs: rows with more arcs are cut into slices dealt to all
     wavefronts (0 = default 512, negative = never). filter_slots: per-wavefront
-    LDS filter of BFS/SSSP relaxations (0 = default 256, negative = off)."""
+    LDS filter of BFS/SSSP relaxations (0 = default 256, negative = off).
+    half_device: the persistent launch takes half of every compute unit, so
+    that a second such call on another stream runs beside it."""
     o = L.Opts()
     L.load().pasgal_opts_default(ctypes.byref(o))
     o.mode = {"vgc": L.MODE_VGC, "plain": L.MODE_PLAIN}[mode]
@@ -105,7 +107,7 @@ def _opts(mode="vgc", tau=1024, wg_size=1024, blocks_per_cu=1, frontier_capacity
     o.frontier_capacity = int(frontier_capacity)
     o.flags = ((L.FLAG_VALIDATE if validate else 0) | (L.FLAG_ASYNC if asynchronous else 0) |
                (L.FLAG_PREFETCH if prefetch else 0) | (L.FLAG_TEST_FIRST if test_first else 0) |
-               (0 if spread_arcs else L.FLAG_ROW_PER_LANE))
+               (0 if spread_arcs else L.FLAG_ROW_PER_LANE) | (L.FLAG_HALF_DEVICE if half_device else 0))
     o.timeout_ms = int(timeout_ms)
     o.stream = _stream_ptr(stream)
     o.window = int(window) if int(window) > 0 else -1

@@ -126,7 +126,7 @@ struct pasgal_batch {
     hipError_t e;
     if ((e = follow_caller()) != hipSuccess) return hip_fail(e);
     if ((e = hipEventRecord(ev0, stream)) != hipSuccess) return hip_fail(e);
-    if ((e = enqueue(dev_info().coop != 0)) != hipSuccess) return hip_fail(e);
+    if ((e = enqueue(coop_launch(o))) != hipSuccess) return hip_fail(e);
     if ((e = hipEventRecord(ev1, stream)) != hipSuccess) return hip_fail(e);
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e);
     if (((const Ctl *)h_ctl.p)->abort) return PASGAL_ETIMEOUT;
@@ -148,7 +148,7 @@ struct pasgal_batch {
     // occupancy-sized grid (the device-side barrier deadline still bounds it).
     hipError_t last = hipSuccess;
     for (int attempt = 0; attempt < 2; attempt++) {
-      const bool coop = (attempt == 0) && dev_info().coop;
+      const bool coop = (attempt == 0) && coop_launch(o);
       hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e);
       hipError_t ee = enqueue(coop);

@@ -75,7 +75,12 @@ struct Opts {
   uint32_t heavy = 512;  // 0 = never cut heavy rows
   uint32_t filt = 256;   // LDS filter entries per wavefront wanted (0 = none)
   uint32_t cpw = 1;      // frontier chunks per wavefront and round
+  bool half = false;     // PASGAL_FLAG_HALF_DEVICE
 };
+
+// Persistent launches are cooperative where the device supports it, except
+// half-device launches, which must be able to run beside another one.
+bool coop_launch(const Opts &o);
 
 struct LaunchGeom {
   int grid = 0, block = 0;

@@ -158,6 +158,7 @@ Opts resolve_opts(const pasgal_opts *o) {
   r.lane_arcs = (o->flags & PASGAL_FLAG_ROW_PER_LANE) ? 8u : 0u;
   r.heavy = o->heavy_arcs > 0 ? (uint32_t)o->heavy_arcs : (o->heavy_arcs == 0 ? 512u : 0u);
   r.cpw = o->chunks_per_wave > 0 ? (uint32_t)std::min(o->chunks_per_wave, 64) : 1u;
+  r.half = (o->flags & PASGAL_FLAG_HALF_DEVICE) != 0;
   if (o->filter_slots > 0) {
     uint32_t f = 1;
     while (f * 2 <= (uint32_t)std::min(o->filter_slots, 4096)) f *= 2;  // round down to a power of two
@@ -218,10 +219,14 @@ bool csr_valid(const pasgal_csr *g) {
 }
 
 // Persistent-launch geometry for a kernel and LDS budget.
+bool coop_launch(const Opts &o) { return dev_info().coop != 0 && !o.half; }
+
 int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   const DevInfo &di = dev_info();
   const int waves = o.wg / 64;
-  const size_t lds_cap_block = std::min<size_t>(di.lds_per_cu / (size_t)o.bpc, di.lds_per_block);
+  // a half-device launch sizes its workgroups for twice as many per CU
+  const int per_cu = o.half ? 2 * o.bpc : o.bpc;
+  const size_t lds_cap_block = std::min<size_t>(di.lds_per_cu / (size_t)per_cu, di.lds_per_block);
   // stage 128 entries; ring = largest power of two that fits
   const uint32_t S = 128;
   const bool pf = o.prefetch;
@@ -255,6 +260,7 @@ int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, lg.block, lg.lds);
   if (e != hipSuccess) return hip_fail(e);
   if (nb < 1) return PASGAL_EINVAL;
+  if (o.half && nb < per_cu) return PASGAL_EINVAL;  // the other half would not fit beside it
   const int bpc = std::min(nb, o.bpc);
   lg.grid = bpc * di.cus;
   return PASGAL_OK;
@@ -385,7 +391,7 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   if ((e = launch_seed(kind, a, (const SeedEnt *)w.seeds.p, (uint32_t)nseed, 0, 0, s)) != hipSuccess)
     return hip_fail(e);
   if ((e = hipEventRecord(w.evk, s)) != hipSuccess) return hip_fail(e);
-  if ((e = launch_vgc(kind, false, lg.pf, a, lg.grid, lg.block, lg.lds, dev_info().coop != 0, s)) != hipSuccess)
+  if ((e = launch_vgc(kind, false, lg.pf, a, lg.grid, lg.block, lg.lds, coop_launch(o), s)) != hipSuccess)
     return hip_fail(e);
   if ((e = hipEventRecord(w.ev1, s)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpyAsync(w.h_ctl.p, w.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s)) != hipSuccess)

@@ -743,7 +743,7 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
                          (const uint32_t *)piv_bit, (const uint32_t *)label, (const uint32_t *)slot_base, pivtab);
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       if ((e = hipEventRecord(w->evk, s)) != hipSuccess) return fail(e);
-      if ((e = launch_vgc(KIND_REACH, false, lg.pf, a, lg.grid, lg.block, lg.lds, dev_info().coop != 0, s)) !=
+      if ((e = launch_vgc(KIND_REACH, false, lg.pf, a, lg.grid, lg.block, lg.lds, coop_launch(o), s)) !=
           hipSuccess)
         return fail(e);
       if ((e = hipEventRecord(w->ev1, s)) != hipSuccess) return fail(e);

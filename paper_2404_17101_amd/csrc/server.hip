@@ -359,7 +359,7 @@ struct pasgal_server {
     if ((e = launch_seed(kind, a, (const SeedEnt *)L.seeds.p, (uint32_t)nseed, L.cur_cnt, L.cur_ovf, s)) !=
         hipSuccess)
       return hip_fail(e);
-    if ((e = launch_vgc(kind, true, L.lg.pf, a, L.lg.grid, L.lg.block, L.lg.lds, dev_info().coop != 0, s)) !=
+    if ((e = launch_vgc(kind, true, L.lg.pf, a, L.lg.grid, L.lg.block, L.lg.lds, coop_launch(vopts), s)) !=
         hipSuccess)
       return hip_fail(e);
     if ((e = hipMemcpyAsync(L.h_ctl.p, L.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s)) != hipSuccess)
