@@ -523,7 +523,7 @@ void pasgal_opts_default(pasgal_opts *o) {
   if (!o) return;
   memset(o, 0, sizeof(*o));
   o->mode = PASGAL_MODE_VGC;
-  o->tau = 1024;
+  o->tau = 0;  // each entry point's default (1024; pasgal_sssp: by mean degree)
   o->wg_size = 1024;
   o->blocks_per_cu = 1;
   o->frontier_capacity = 0;
@@ -579,6 +579,8 @@ int pasgal_sssp(const pasgal_csr *g, const uint32_t *weights, int32_t src, uint3
     return PASGAL_EINVAL;
   Opts o = resolve_opts(opts);
   o.prefetch = false;
+  // default tau by mean out-degree: no local search beyond the roots on dense graphs
+  if (!opts || opts->tau <= 0) o.tau = (int64_t)g->m > 8 * (int64_t)g->n ? 1u : 1024u;
   if (o.mode == PASGAL_MODE_PLAIN) o.tau = 1;
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;

@@ -115,7 +115,8 @@ struct Wave {
   uint32_t rabs;   // absolute number of the current round (BFS window)
   uint32_t root_end;  // local-queue positions below this hold the current search's roots
   uint32_t slice_ok;  // heavy rows may be cut into slices this round
-  unsigned long long st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale, st_steps, st_filtered;
+  unsigned long long st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale, st_steps;
+  uint32_t st_filt_lane;  // per lane: relaxations ruled out by a filter (summed over the wave at the end)
 
   __device__ __forceinline__ Wave(const VgcArgs &args, uint8_t *lds_wave) : a(args) {
     state = (Val *)a.state;
@@ -151,7 +152,8 @@ struct Wave {
     root_end = 0;
     slice_ok = 0;
     qlite = nullptr;
-    st_expand = st_arcs = st_success = st_publish = st_overflow = st_stale = st_steps = st_filtered = 0;
+    st_expand = st_arcs = st_success = st_publish = st_overflow = st_stale = st_steps = 0;
+    st_filt_lane = 0;
   }
 
   const QLite *qlite;  // LDS copy of the query table, or null
@@ -307,18 +309,21 @@ struct Wave {
   //    same reason a remembered value <= the new one proves the atomic
   //    cannot win.
   //  * PF: the arc range of w is loaded alongside.
+  // A relaxation that a filter rules out keeps, as its "old" value, the value
+  // that proved it (<= the offered one for distances, a superset mask for
+  // reach), so finish() sees no change and the LDS filter entry it rewrites
+  // is still a value the state held. Few fields, so that several can be live
+  // at once without spilling.
   struct Rx {
-    Val nd;       // value offered to w
-    Val old;      // value of w before the atomic (or the value that filtered it)
-    uint32_t key, slot;
-    bool skipped;
+    Val nd;   // value offered to w
+    Val old;  // value of w before the atomic, or the value that filtered it
     int32_t nb, ne;
   };
 
+  __device__ __forceinline__ uint32_t filt_slot(uint32_t key) const { return (key * 0x9E3779B1u) >> fshift; }
+
   __device__ __forceinline__ Rx relax_issue(int64_t sb, uint32_t w, int32_t arc, Val val) {
     Rx x;
-    x.skipped = false;
-    x.key = x.slot = 0;
     x.nb = x.ne = 0;
     if (PF) {
       x.nb = a.off[w];
@@ -331,18 +336,20 @@ struct Wave {
                               : (uint32_t)val + 1u;
       x.nd = (Val)nd;
       uint32_t *p = (uint32_t *)&state[sb + w];
-      if (a.test_first && *(const uint32_t *)p <= nd) {
-        x.skipped = true;
-        x.old = (Val)nd;
-        return x;
+      if (a.test_first) {
+        const uint32_t cur = *(const uint32_t *)p;
+        if (cur <= nd) {
+          st_filt_lane++;
+          x.old = (Val)cur;
+          return x;
+        }
       }
       if (a.filt) {
-        x.key = (uint32_t)(sb + (int64_t)w);
-        x.slot = (x.key * 0x9E3779B1u) >> fshift;
-        const unsigned long long e = filt[x.slot];
-        if ((uint32_t)(e >> 32) == x.key && (uint32_t)e <= nd) {
-          x.skipped = true;
-          x.old = (Val)nd;
+        const uint32_t key = (uint32_t)(sb + (int64_t)w);
+        const unsigned long long e = filt[filt_slot(key)];
+        if ((uint32_t)(e >> 32) == key && (uint32_t)e <= nd) {
+          st_filt_lane++;
+          x.old = (Val)(uint32_t)e;
           return x;
         }
       }
@@ -354,7 +361,7 @@ struct Wave {
       if (a.test_first) {
         const unsigned long long cur = *(const unsigned long long *)p;
         if ((cur & m) == m) {
-          x.skipped = true;
+          st_filt_lane++;
           x.old = (Val)cur;
           return x;
         }
@@ -364,16 +371,18 @@ struct Wave {
     return x;
   }
 
-  __device__ __forceinline__ bool relax_finish(const Rx &x, Val &nv) {
+  // Only for a lane whose relax_issue ran (a valid arc).
+  __device__ __forceinline__ bool relax_finish(const Rx &x, int64_t sb, uint32_t w, Val &nv) {
     if (DIST) {
       nv = x.nd;
-      if (x.skipped) return false;
-      if (a.filt)
-        filt[x.slot] = ((unsigned long long)x.key << 32) | (unsigned long long)min((uint32_t)x.old, (uint32_t)x.nd);
+      if (a.filt) {
+        const uint32_t key = (uint32_t)(sb + (int64_t)w);
+        filt[filt_slot(key)] =
+            ((unsigned long long)key << 32) | (unsigned long long)min((uint32_t)x.old, (uint32_t)x.nd);
+      }
       return (uint32_t)x.nd < (uint32_t)x.old;
     }
     nv = (Val)((unsigned long long)x.old | (unsigned long long)x.nd);
-    if (x.skipped) return false;
     return nv != x.old;
   }
 
@@ -455,31 +464,22 @@ struct Wave {
       int32_t w[8];
 #pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) w[u] = ((uint32_t)u < deg) ? a.tgt[b + u] : 0;
-      bool ok[8];
-      Val nv[8];
-      int32_t nb[8], ne[8];
       Rx x[8];
 #pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) {
-        x[u].skipped = true;
         x[u].nd = x[u].old = 0;
         x[u].nb = x[u].ne = 0;
         if ((uint32_t)u < deg) x[u] = relax_issue(sb, (uint32_t)w[u], b + u, val);
       }
-#pragma clang loop unroll(full)
-      for (int u = 0; u < 8; u++) {
-        ok[u] = relax_finish(x[u], nv[u]);
-        nb[u] = x[u].nb;
-        ne[u] = x[u].ne;
-        if ((uint32_t)u < maxd) st_filtered += __popcll(__ballot((uint32_t)u < deg && x[u].skipped));
-      }
       uint32_t nsucc = 0, arcs = 0;
 #pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) {
-        if ((uint32_t)u < maxd) {
+        if ((uint32_t)u < maxd) {  // wave-uniform
+          Val nv = x[u].nd;
+          const bool ok = (uint32_t)u < deg && relax_finish(x[u], sb, (uint32_t)w[u], nv);
           arcs += __popcll(__ballot((uint32_t)u < deg));
-          nsucc += __popcll(__ballot(ok[u]));
-          push(ok[u], (uint32_t)w[u], q, nv[u], ring_ok, nb[u], ne[u]);
+          nsucc += __popcll(__ballot(ok));
+          push(ok, (uint32_t)w[u], q, nv, ring_ok, x[u].nb, x[u].ne);
         }
       }
       st_success += nsucc;
@@ -488,8 +488,10 @@ struct Wave {
     }
     // Flattened: the wave's arcs are dealt out 64 at a time; each lane finds
     // its arc's owner lane by binary search over the inclusive degree scan.
-    // RB such passes are issued together (target loads, then atomics, then
-    // pushes), so a lane has RB relaxations in flight instead of one.
+    // Up to RB such passes are issued together (target loads, then atomics,
+    // then pushes), so a lane has RB relaxations in flight instead of one;
+    // passes past the last arc are skipped whole (wave-uniform), so a thin
+    // step costs one pass.
     const uint32_t incl = wave_incl_scan(deg, ln);
     const uint32_t total = __shfl(incl, 63);
     const uint32_t excl = incl - deg;
@@ -497,7 +499,7 @@ struct Wave {
     wave_sync();
     st_arcs += total;
     uint32_t nsucc = 0;
-    constexpr int RB = 4;
+    constexpr int RB = MULTI ? 4 : 1;  // single-query steps are thin: one pass, fewer registers
     for (uint32_t j0 = 0; j0 < total; j0 += 64 * RB) {
       uint32_t w[RB], qo[RB];
       int32_t arc[RB];
@@ -508,6 +510,12 @@ struct Wave {
       for (int r = 0; r < RB; r++) {
         const uint32_t ai = j0 + (uint32_t)r * 64u + ln;
         okl[r] = ai < total;
+        w[r] = 0;
+        arc[r] = 0;
+        qo[r] = 0;
+        sbo[r] = 0;
+        vo[r] = 0;
+        if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform: no arcs left for this pass
         uint32_t pos = 0;
 #pragma unroll
         for (uint32_t step = 32; step >= 1; step >>= 1)
@@ -527,18 +535,17 @@ struct Wave {
       Rx x[RB];
 #pragma clang loop unroll(full)
       for (int r = 0; r < RB; r++) {
-        x[r].skipped = true;
         x[r].nd = x[r].old = 0;
         x[r].nb = x[r].ne = 0;
+        if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform
         if (okl[r]) x[r] = relax_issue(sbo[r], w[r], arc[r], vo[r]);
       }
 #pragma clang loop unroll(full)
       for (int r = 0; r < RB; r++) {
         if (j0 + (uint32_t)r * 64u >= total) break;  // wave-uniform
         Val nv = 0;
-        const bool ok = okl[r] && relax_finish(x[r], nv);
+        const bool ok = okl[r] && relax_finish(x[r], sbo[r], w[r], nv);
         nsucc += __popcll(__ballot(ok));
-        st_filtered += __popcll(__ballot(okl[r] && x[r].skipped));
         push(ok, w[r], qo[r], nv, ring_ok, x[r].nb, x[r].ne);
       }
     }
@@ -759,6 +766,9 @@ struct Wave {
   }
 
   __device__ __forceinline__ void flush_stats() {
+    unsigned long long st_filtered = st_filt_lane;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) st_filtered += shfl64(st_filtered, ln ^ (uint32_t)d);
     if (ln == 0) {
       const unsigned long long vals[ST_COUNT] = {st_expand, st_arcs,  st_success, st_publish,
                                                  st_overflow, st_stale, st_steps,   st_filtered};

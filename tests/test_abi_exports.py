@@ -55,7 +55,7 @@ def test_host_only_calls(lib):
     from paper_2404_17101_amd import _lib as L
     o = L.Opts()
     lib.pasgal_opts_default(ctypes.byref(o))
-    assert (o.mode, o.tau, o.wg_size, o.blocks_per_cu, o.timeout_ms) == (0, 1024, 1024, 1, 20000)
+    assert (o.mode, o.tau, o.wg_size, o.blocks_per_cu, o.timeout_ms) == (0, 0, 1024, 1, 20000)
 
 
 def test_struct_layouts_match_header(tmp_path):

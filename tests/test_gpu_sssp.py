@@ -51,6 +51,7 @@ CASES = [
     ("knn20k", lambda: gg.knn(20000, 5, 7), (1, 1000)),
     ("road128", lambda: gg.road(128, 3), (1, 1000)),
     ("rmat12", lambda: gg.rmat(12, 8, 1), (1, 1000)),
+    ("rmat12_dense", lambda: gg.rmat(12, 24, 4), (1, 1000)),  # m > 8n: default tau 1
     ("rand_zero_w", lambda: gg.random_graph(3000, 9000, 52), (0, 20)),
     ("dchain_w", lambda: gg.simple("dchain", 300), (0, 99)),
     ("empty", lambda: gg.simple("empty", 9), (1, 1)),
@@ -69,10 +70,10 @@ def test_sssp_families(pg, name, make, wr):
         assert np.array_equal(got, exp), s
 
 
-@pytest.mark.parametrize("kw", [dict(mode="plain"), dict(tau=16), dict(window=-1), dict(window=50),
+@pytest.mark.parametrize("kw", [dict(mode="plain"), dict(tau=16), dict(tau=1024), dict(window=-1), dict(window=50),
                                 dict(frontier_capacity=64), dict(heavy_arcs=16), dict(wg_size=256, blocks_per_cu=2),
                                 dict(tau=1, window=-1, frontier_capacity=64)],
-                         ids=["plain", "tau16", "nowindow", "delta50", "cap64", "heavy16", "wg256x2", "bellman"])
+                         ids=["plain", "tau16", "tau1024", "nowindow", "delta50", "cap64", "heavy16", "wg256x2", "bellman"])
 def test_sssp_schedules(pg, kw):
     for g, wr in [(gg.road(96, 5), (1, 1000)), (gg.rmat(11, 16, 3), (1, 100)), (gg.knn(8000, 5, 9), (0, 50))]:
         w = gg.weights(g, 83, *wr)
