@@ -115,7 +115,9 @@ struct Wave {
   uint32_t rabs;   // absolute number of the current round (BFS window)
   uint32_t root_end;  // local-queue positions below this hold the current search's roots
   uint32_t slice_ok;  // heavy rows may be cut into slices this round
-  unsigned long long st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale, st_steps;
+  // statistics, per wavefront and launch (32-bit: a wavefront would have to
+  // scan 2^32 arcs in one launch to wrap them; widened when flushed)
+  uint32_t st_expand, st_arcs, st_success, st_publish, st_overflow, st_stale, st_steps;
   uint32_t st_filt_lane;  // per lane: relaxations ruled out by a filter (summed over the wave at the end)
 
   __device__ __forceinline__ Wave(const VgcArgs &args, uint8_t *lds_wave) : a(args) {
@@ -460,6 +462,10 @@ struct Wave {
     const uint32_t deg = act ? (uint32_t)(e - b) : 0u;
     const uint32_t maxd = wave_max(deg);
     if (maxd == 0) return nexp;
+    // both paths count into these, and one epilogue adds them to the stats
+    // (an update per path let the compiler merge the two into one store
+    // through a selected address, which kept the counters in scratch memory)
+    uint32_t nsucc = 0, arcs = 0;
     if (maxd <= a.lane_arcs) {
       int32_t w[8];
 #pragma clang loop unroll(full)
@@ -471,7 +477,6 @@ struct Wave {
         x[u].nb = x[u].ne = 0;
         if ((uint32_t)u < deg) x[u] = relax_issue(sb, (uint32_t)w[u], b + u, val);
       }
-      uint32_t nsucc = 0, arcs = 0;
 #pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) {
         if ((uint32_t)u < maxd) {  // wave-uniform
@@ -482,75 +487,75 @@ struct Wave {
           push(ok, (uint32_t)w[u], q, nv, ring_ok, x[u].nb, x[u].ne);
         }
       }
-      st_success += nsucc;
-      st_arcs += arcs;
-      return nexp;
+    } else {
+      // Flattened: the wave's arcs are dealt out 64 at a time; each lane finds
+      // its arc's owner lane by binary search over the inclusive degree scan.
+      // Up to RB such passes are issued together (target loads, then atomics,
+      // then pushes), so a lane has RB relaxations in flight instead of one;
+      // passes past the last arc are skipped whole (wave-uniform), so a thin
+      // step costs one pass.
+      const uint32_t incl = wave_incl_scan(deg, ln);
+      const uint32_t total = __shfl(incl, 63);
+      const uint32_t excl = incl - deg;
+      scan[ln] = incl;
+      wave_sync();
+      arcs = total;
+      constexpr int RB = MULTI ? 4 : 1;  // single-query steps are thin: one pass, fewer registers
+      for (uint32_t j0 = 0; j0 < total; j0 += 64 * RB) {
+        uint32_t w[RB], qo[RB];
+        int32_t arc[RB];
+        int64_t sbo[RB];
+        Val vo[RB];
+        bool okl[RB];
+  #pragma clang loop unroll(full)
+        for (int r = 0; r < RB; r++) {
+          const uint32_t ai = j0 + (uint32_t)r * 64u + ln;
+          okl[r] = ai < total;
+          w[r] = 0;
+          arc[r] = 0;
+          qo[r] = 0;
+          sbo[r] = 0;
+          vo[r] = 0;
+          if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform: no arcs left for this pass
+          uint32_t pos = 0;
+  #pragma unroll
+          for (uint32_t step = 32; step >= 1; step >>= 1)
+            if (scan[pos + step - 1] <= ai) pos += step;
+          const int owner = (int)min(pos, 63u);
+          const int32_t bo = __shfl(b, owner);
+          const uint32_t eo = __shfl(excl, owner);
+          qo[r] = MULTI ? (uint32_t)__shfl(q, owner) : 0u;
+          sbo[r] = MULTI ? (int64_t)shfl64((unsigned long long)sb, owner) : 0;
+          if (DIST)
+            vo[r] = (Val)__shfl((uint32_t)val, owner);
+          else
+            vo[r] = (Val)shfl64((unsigned long long)val, owner);
+          arc[r] = bo + (int32_t)(ai - eo);
+          w[r] = okl[r] ? (uint32_t)a.tgt[arc[r]] : 0u;
+        }
+        Rx x[RB];
+  #pragma clang loop unroll(full)
+        for (int r = 0; r < RB; r++) {
+          x[r].nd = x[r].old = 0;
+          x[r].nb = x[r].ne = 0;
+          if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform
+          if (okl[r]) x[r] = relax_issue(sbo[r], w[r], arc[r], vo[r]);
+        }
+  #pragma clang loop unroll(full)
+        for (int r = 0; r < RB; r++) {
+          if (j0 + (uint32_t)r * 64u >= total) break;  // wave-uniform
+          Val nv = 0;
+          // the query's state base is looked up again (LDS query table) rather
+          // than kept live across the passes in flight
+          const bool ok = okl[r] && relax_finish(x[r], MULTI ? sbase_of(qo[r]) : 0, w[r], nv);
+          nsucc += __popcll(__ballot(ok));
+          push(ok, w[r], qo[r], nv, ring_ok, x[r].nb, x[r].ne);
+        }
+      }
+      wave_sync();
     }
-    // Flattened: the wave's arcs are dealt out 64 at a time; each lane finds
-    // its arc's owner lane by binary search over the inclusive degree scan.
-    // Up to RB such passes are issued together (target loads, then atomics,
-    // then pushes), so a lane has RB relaxations in flight instead of one;
-    // passes past the last arc are skipped whole (wave-uniform), so a thin
-    // step costs one pass.
-    const uint32_t incl = wave_incl_scan(deg, ln);
-    const uint32_t total = __shfl(incl, 63);
-    const uint32_t excl = incl - deg;
-    scan[ln] = incl;
-    wave_sync();
-    st_arcs += total;
-    uint32_t nsucc = 0;
-    constexpr int RB = MULTI ? 4 : 1;  // single-query steps are thin: one pass, fewer registers
-    for (uint32_t j0 = 0; j0 < total; j0 += 64 * RB) {
-      uint32_t w[RB], qo[RB];
-      int32_t arc[RB];
-      int64_t sbo[RB];
-      Val vo[RB];
-      bool okl[RB];
-#pragma clang loop unroll(full)
-      for (int r = 0; r < RB; r++) {
-        const uint32_t ai = j0 + (uint32_t)r * 64u + ln;
-        okl[r] = ai < total;
-        w[r] = 0;
-        arc[r] = 0;
-        qo[r] = 0;
-        sbo[r] = 0;
-        vo[r] = 0;
-        if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform: no arcs left for this pass
-        uint32_t pos = 0;
-#pragma unroll
-        for (uint32_t step = 32; step >= 1; step >>= 1)
-          if (scan[pos + step - 1] <= ai) pos += step;
-        const int owner = (int)min(pos, 63u);
-        const int32_t bo = __shfl(b, owner);
-        const uint32_t eo = __shfl(excl, owner);
-        qo[r] = MULTI ? (uint32_t)__shfl(q, owner) : 0u;
-        sbo[r] = MULTI ? (int64_t)shfl64((unsigned long long)sb, owner) : 0;
-        if (DIST)
-          vo[r] = (Val)__shfl((uint32_t)val, owner);
-        else
-          vo[r] = (Val)shfl64((unsigned long long)val, owner);
-        arc[r] = bo + (int32_t)(ai - eo);
-        w[r] = okl[r] ? (uint32_t)a.tgt[arc[r]] : 0u;
-      }
-      Rx x[RB];
-#pragma clang loop unroll(full)
-      for (int r = 0; r < RB; r++) {
-        x[r].nd = x[r].old = 0;
-        x[r].nb = x[r].ne = 0;
-        if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform
-        if (okl[r]) x[r] = relax_issue(sbo[r], w[r], arc[r], vo[r]);
-      }
-#pragma clang loop unroll(full)
-      for (int r = 0; r < RB; r++) {
-        if (j0 + (uint32_t)r * 64u >= total) break;  // wave-uniform
-        Val nv = 0;
-        const bool ok = okl[r] && relax_finish(x[r], sbo[r], w[r], nv);
-        nsucc += __popcll(__ballot(ok));
-        push(ok, w[r], qo[r], nv, ring_ok, x[r].nb, x[r].ne);
-      }
-    }
-    wave_sync();
     st_success += nsucc;
+    st_arcs += arcs;
     return nexp;
   }
 
@@ -770,7 +775,7 @@ struct Wave {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) st_filtered += shfl64(st_filtered, ln ^ (uint32_t)d);
     if (ln == 0) {
-      const unsigned long long vals[ST_COUNT] = {st_expand, st_arcs,  st_success, st_publish,
+      const unsigned long long vals[ST_COUNT] = {st_expand,   st_arcs,  st_success, st_publish,
                                                  st_overflow, st_stale, st_steps,   st_filtered};
 #pragma clang loop unroll(full)
       for (int i = 0; i < ST_COUNT; i++)
