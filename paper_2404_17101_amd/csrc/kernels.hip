@@ -317,7 +317,7 @@ struct Wave {
   // is still a value the state held. Few fields, so that several can be live
   // at once without spilling.
   struct Rx {
-    Val nd;   // value offered to w
+    Val nd;   // value offered to w (distances; reach passes its mask to finish)
     Val old;  // value of w before the atomic, or the value that filtered it
     int32_t nb, ne;
   };
@@ -359,7 +359,6 @@ struct Wave {
     } else {
       unsigned long long *p = (unsigned long long *)&state[sb + w];
       const unsigned long long m = (unsigned long long)val;
-      x.nd = (Val)m;
       if (a.test_first) {
         const unsigned long long cur = *(const unsigned long long *)p;
         if ((cur & m) == m) {
@@ -373,8 +372,9 @@ struct Wave {
     return x;
   }
 
-  // Only for a lane whose relax_issue ran (a valid arc).
-  __device__ __forceinline__ bool relax_finish(const Rx &x, int64_t sb, uint32_t w, Val &nv) {
+  // Only for a lane whose relax_issue ran (a valid arc); offered is the value
+  // that relax_issue got (read for reach, whose records do not keep it).
+  __device__ __forceinline__ bool relax_finish(const Rx &x, int64_t sb, uint32_t w, Val offered, Val &nv) {
     if (DIST) {
       nv = x.nd;
       if (a.filt) {
@@ -384,7 +384,7 @@ struct Wave {
       }
       return (uint32_t)x.nd < (uint32_t)x.old;
     }
-    nv = (Val)((unsigned long long)x.old | (unsigned long long)x.nd);
+    nv = (Val)((unsigned long long)x.old | (unsigned long long)offered);
     return nv != x.old;
   }
 
@@ -480,8 +480,8 @@ struct Wave {
 #pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) {
         if ((uint32_t)u < maxd) {  // wave-uniform
-          Val nv = x[u].nd;
-          const bool ok = (uint32_t)u < deg && relax_finish(x[u], sb, (uint32_t)w[u], nv);
+          Val nv = DIST ? x[u].nd : val;
+          const bool ok = (uint32_t)u < deg && relax_finish(x[u], sb, (uint32_t)w[u], val, nv);
           arcs += __popcll(__ballot((uint32_t)u < deg));
           nsucc += __popcll(__ballot(ok));
           push(ok, (uint32_t)w[u], q, nv, ring_ok, x[u].nb, x[u].ne);
@@ -500,7 +500,7 @@ struct Wave {
       scan[ln] = incl;
       wave_sync();
       arcs = total;
-      constexpr int RB = MULTI ? 4 : 1;  // single-query steps are thin: one pass, fewer registers
+      constexpr int RB = MULTI ? 4 : 1;  // single-query steps are thin: one pass
       for (uint32_t j0 = 0; j0 < total; j0 += 64 * RB) {
         uint32_t w[RB], qo[RB];
         int32_t arc[RB];
@@ -547,7 +547,7 @@ struct Wave {
           Val nv = 0;
           // the query's state base is looked up again (LDS query table) rather
           // than kept live across the passes in flight
-          const bool ok = okl[r] && relax_finish(x[r], MULTI ? sbase_of(qo[r]) : 0, w[r], nv);
+          const bool ok = okl[r] && relax_finish(x[r], MULTI ? sbase_of(qo[r]) : 0, w[r], vo[r], nv);
           nsucc += __popcll(__ballot(ok));
           push(ok, w[r], qo[r], nv, ring_ok, x[r].nb, x[r].ne);
         }
