@@ -251,7 +251,7 @@ int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   lg.block = o.wg;
   lg.pf = pf;
   lg.lds = vgc_lds_bytes(kind, multi, pf, waves, Q, S, F);
-  const void *fn = vgc_kernel_ptr(kind, multi, pf);
+  const void *fn = vgc_kernel_ptr(kind, multi, pf, o.lane_arcs != 0);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lg.lds);
   if (e != hipSuccess) {
     hipGetLastError();

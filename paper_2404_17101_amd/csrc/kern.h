@@ -147,7 +147,8 @@ hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_
                        uint32_t start_ovf, hipStream_t s);
 hipError_t launch_vgc(int kind, bool multi, bool pf, const VgcArgs &a, int grid, int block, size_t lds,
                       bool cooperative, hipStream_t s);
-const void *vgc_kernel_ptr(int kind, bool multi, bool pf);
+// lane: the row-per-lane variant (VgcArgs::lane_arcs != 0)
+const void *vgc_kernel_ptr(int kind, bool multi, bool pf, bool lane);
 
 // Plain level-synchronous rounds (one launch per BFS level).
 hipError_t launch_plain_bfs_level(const int32_t *off, const int32_t *tgt, uint32_t *dist, const uint32_t *cur,

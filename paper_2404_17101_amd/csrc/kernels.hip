@@ -92,7 +92,7 @@ struct ValT<KIND_REACH> { using T = unsigned long long; };
 template <>
 struct ValT<KIND_SSSP> { using T = uint32_t; };
 
-template <int KIND, bool MULTI, bool PF>
+template <int KIND, bool MULTI, bool PF, bool LANE>
 struct Wave {
   using Val = typename ValT<KIND>::T;
   static constexpr bool FIFO = (KIND != KIND_REACH);  // distances: local BFS order; reach: LIFO (deep first)
@@ -466,7 +466,10 @@ struct Wave {
     // (an update per path let the compiler merge the two into one store
     // through a selected address, which kept the counters in scratch memory)
     uint32_t nsucc = 0, arcs = 0;
-    if (maxd <= a.lane_arcs) {
+    // the row-per-lane path exists only in LANE instantiations: its eight
+    // relaxation records in flight would otherwise set every kernel's
+    // register budget
+    if (LANE && maxd <= a.lane_arcs) {
       int32_t w[8];
 #pragma clang loop unroll(full)
       for (int u = 0; u < 8; u++) w[u] = ((uint32_t)u < deg) ? a.tgt[b + u] : 0;
@@ -784,7 +787,7 @@ struct Wave {
   }
 };
 
-template <int KIND, bool MULTI, bool PF>
+template <int KIND, bool MULTI, bool PF, bool LANE>
 __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ RoundHdr hdr;
@@ -792,7 +795,7 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wid = threadIdx.x >> 6;
   const size_t per_wave = vgc_lds_bytes(KIND, MULTI, PF, 1, a.ring_cap, a.stage_cap, a.filt);
-  Wave<KIND, MULTI, PF> wv(a, smem + per_wave * wid);
+  Wave<KIND, MULTI, PF, LANE> wv(a, smem + per_wave * wid);
   __shared__ QLite qlite[MULTI ? QLITE : 1];
   if (MULTI && a.nq <= QLITE) {
     for (int i = threadIdx.x; i < a.nq; i += blockDim.x) {
@@ -961,22 +964,26 @@ hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_
   return hipGetLastError();
 }
 
-const void *vgc_kernel_ptr(int kind, bool multi, bool pf) {
-  if (kind == KIND_SSSP)  // one query per launch, arc ranges loaded when expanded
-    return (multi || pf) ? nullptr : (const void *)vgc_kernel<KIND_SSSP, false, false>;
-  if (kind == KIND_BFS) {
-    if (multi) return pf ? (const void *)vgc_kernel<KIND_BFS, true, true> : (const void *)vgc_kernel<KIND_BFS, true, false>;
-    return pf ? (const void *)vgc_kernel<KIND_BFS, false, true> : (const void *)vgc_kernel<KIND_BFS, false, false>;
+template <int KIND, bool MULTI>
+static const void *vgc_variant(bool pf, bool lane) {
+  if (pf) return lane ? (const void *)vgc_kernel<KIND, MULTI, true, true> : (const void *)vgc_kernel<KIND, MULTI, true, false>;
+  return lane ? (const void *)vgc_kernel<KIND, MULTI, false, true> : (const void *)vgc_kernel<KIND, MULTI, false, false>;
+}
+
+const void *vgc_kernel_ptr(int kind, bool multi, bool pf, bool lane) {
+  if (kind == KIND_SSSP) {  // one query per launch, arc ranges loaded when expanded
+    if (multi || pf) return nullptr;
+    return lane ? (const void *)vgc_kernel<KIND_SSSP, false, false, true>
+                : (const void *)vgc_kernel<KIND_SSSP, false, false, false>;
   }
-  if (multi)
-    return pf ? (const void *)vgc_kernel<KIND_REACH, true, true> : (const void *)vgc_kernel<KIND_REACH, true, false>;
-  return pf ? (const void *)vgc_kernel<KIND_REACH, false, true> : (const void *)vgc_kernel<KIND_REACH, false, false>;
+  if (kind == KIND_BFS) return multi ? vgc_variant<KIND_BFS, true>(pf, lane) : vgc_variant<KIND_BFS, false>(pf, lane);
+  return multi ? vgc_variant<KIND_REACH, true>(pf, lane) : vgc_variant<KIND_REACH, false>(pf, lane);
 }
 
 hipError_t launch_vgc(int kind, bool multi, bool pf, const VgcArgs &a, int grid, int block, size_t lds,
                       bool cooperative, hipStream_t s) {
   (void)hipGetLastError();  // report only this launch's error
-  const void *fn = vgc_kernel_ptr(kind, multi, pf);
+  const void *fn = vgc_kernel_ptr(kind, multi, pf, a.lane_arcs != 0);
   if (!fn) return hipErrorInvalidDeviceFunction;
   VgcArgs copy = a;
   void *args[] = {&copy};
