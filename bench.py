@@ -83,16 +83,16 @@ def _counter_means(path):
 
 SUITE_TRACES = {
     "scc": ("Kernel trace: SCC suite (road4096, knn 10M/5, RMAT-20; VGC, tau 1, no trim, no split; 3 runs each)",
-            "vgc_kernel<1, false, false> is the reach kernel running the forward and backward searches of a "
+            "vgc_kernel<1, false, false, false> is the reach kernel running the forward and backward searches of a "
             "batch together on the packed 2n-vertex graph; pack_kernel<false/true> count and scatter the arcs that "
             "stay inside one subproblem; union_kernel / piece_label_kernel are the weak-connectivity split; "
             "trim_kernel, select_kernel, refine_kernel and min_member_kernel are the per-batch steps."),
     "sssp": ("Kernel trace: SSSP suite (knn 10M/5, road4096, RMAT-22; weights uniform in [1, 1000]; VGC and tau 1)",
-             "vgc_kernel<2, false, false> is the SSSP kernel (kind 2 = weighted distances); sum_u32_kernel is the "
+             "vgc_kernel<2, false, false, false> is the SSSP kernel (kind 2 = weighted distances); sum_u32_kernel is the "
              "mean-weight reduction behind the default bucket width."),
     "bfs_do": ("Kernel trace: direction-optimizing BFS suite (RMAT-24 and knn 10M/5, 4 sources each)",
                "bottom_up_kernel, collect_kernel and degsum_kernel belong to the direction-optimizing BFS; "
-               "plain_level_kernel<0> runs its top-down levels and the plain BFS; vgc_kernel<0, false, false> is the "
+               "plain_level_kernel<0> runs its top-down levels and the plain BFS; vgc_kernel<0, false, false, false> is the "
                "VGC BFS."),
 }
 
@@ -127,8 +127,8 @@ def summarize_profiles(d, args):
     into the committed summaries under profiles/."""
     import csv
 
-    kb = "void pg::vgc_kernel<0, true, false>(pg::VgcArgs)"
-    kr = "void pg::vgc_kernel<1, false, false>(pg::VgcArgs)"
+    kb = "void pg::vgc_kernel<0, true, false, false>(pg::VgcArgs)"
+    kr = "void pg::vgc_kernel<1, false, false, false>(pg::VgcArgs)"
     cp = "__amd_rocclr_copyBuffer"
     rows = list(csv.DictReader(open(os.path.join(d, "prof_trace", "run_kernel_stats.csv"))))
     F = _counter_means(os.path.join(d, "prof_fetch", "run_counter_collection.csv"))
@@ -170,8 +170,9 @@ def summarize_profiles(d, args):
             name = name[:67] + "..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                      f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |")
-    lines += ["", "`vgc_kernel<0, true, false>` is the multi-query BFS kernel (kind 0 = BFS, multi-query, no arc-range "
-                  "prefetch); `vgc_kernel<1, false, false>` is the single-query reach kernel, run with a 16-bit mask. "
+    lines += ["", "`vgc_kernel<0, true, false, false>` is the multi-query BFS kernel (kind 0 = BFS, multi-query, no "
+                  "arc-range prefetch, no row-per-lane path); `vgc_kernel<1, false, false, false>` is the single-query "
+                  "reach kernel, run with a 16-bit mask. "
                   "`__amd_rocclr_copyBuffer` dispatches are the graph upload before the timed steps."]
     with open(os.path.join(prof, "vgc_bfs_batched16_knn10m_trace.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -185,8 +186,8 @@ def summarize_profiles(d, args):
              "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/prof_cwrite -o run -- python3 <repo>/bench.py --calibrate-copy",
              "```", "", "Per dispatch (KiB as reported), averaged over the dispatches of each kernel:", "",
              "| kernel | FETCH_SIZE | WRITE_SIZE | HBM bytes (calibrated) |", "|---|---|---|---|",
-             f"| `vgc_kernel<0, true, false>` (BFS, 16 queries) | {F[kb]:,.1f} | {W[kb]:,.1f} | {traffic_b / 1e9:.2f} GB |",
-             f"| `vgc_kernel<1, false, false>` (reach, k = 16) | {F[kr]:,.1f} | {W[kr]:,.1f} | {traffic_r / 1e9:.2f} GB |",
+             f"| `vgc_kernel<0, true, false, false>` (BFS, 16 queries) | {F[kb]:,.1f} | {W[kb]:,.1f} | {traffic_b / 1e9:.2f} GB |",
+             f"| `vgc_kernel<1, false, false, false>` (reach, k = 16) | {F[kr]:,.1f} | {W[kr]:,.1f} | {traffic_r / 1e9:.2f} GB |",
              f"| `{cp}`, 1 GiB copy (calibration) | {CF[cp]:,.1f} | {CW[cp]:,.1f} | 2.15 GB |", "",
              f"Calibration: a plain 1 GiB copy reads and writes 1 GiB; the counters report {CF[cp] / 1048576:.3f} GiB and "
              f"{CW[cp] / 1048576:.3f} GiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.",
