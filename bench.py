@@ -32,8 +32,10 @@ The JSON line also carries
   cpu_baseline  the CPU oracle (sequential queue BFS / DFS reach, one host
                 thread) on a bounded sample of the same queries.
   extras        single-source calls: plain (one launch per BFS level) vs VGC
-                per tau, sequential 16-query totals, and the reach kernel's
-                own roofline figure.
+                per tau, the same job run sequentially on the whole device,
+                and the latency floor: eccentricity x the time of one
+                dependent access (pasgal_probe_latency) beside the measured
+                single-source time.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--tau T] [--window W]
                 [--schedule concurrent|sequential] [--layout morton|draw]
@@ -200,6 +202,17 @@ def summarize_profiles(d, args):
     print(json.dumps(out, indent=1))
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,7 +364,7 @@ def main():
                         for i in range(nq)))
     kms = float(np.mean([b["kernel_ms"] for b, _ in rec]))
     achieved = alg_bytes / (kms * 1e-3) / 1e9
-    traffic, note = None, None
+    traffic, note, traffic_frac = None, None, None
     if os.path.exists(PROFILE_COUNTERS):
         with open(PROFILE_COUNTERS) as f:
             pc = json.load(f)
@@ -359,10 +372,12 @@ def main():
                 and pc.get("tau") == args.tau and pc.get("window") == args.window
                 and pc.get("wg_size", 1024) == args.wg and pc.get("schedule", "sequential") == args.schedule):
             traffic = pc.get("hbm_bytes_per_launch")
+            traffic_frac = traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS
         else:
             note = "committed counter profile was taken on a different kernel source or setting"
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "traffic_frac": None if traffic_frac is None else round(traffic_frac, 5),
                 "kernel": "vgc_kernel<BFS, multi-query>", "kernel_ms_avg": round(kms, 4),
                 "alg_bytes_per_launch": int(alg_bytes)}
     if conc:
@@ -386,6 +401,7 @@ def main():
         "reach16_kernel_ms" if not conc else "reach16_stream_ms": rkms,
         "reach16_rounds": float(np.mean([r["rounds"] for _, r in rec])) if not conc else None,
         "reach16_roofline_frac": round(rch_alg / (rkms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+        "arc_passes_per_s": round(float(np.mean([b["arcs_scanned"] for b, _ in rec])) / (kms * 1e-3), 1),
         "reached_vertices_avg": float(np.mean(bfs_nr)),
         "reached_arcs_avg": float(np.mean(bfs_mr)),
         "queries_per_s": round(2 * nq * args.steps / wall, 2),
@@ -407,7 +423,8 @@ def main():
             calls += 2
         cpu = {"value": round(edges / used / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": f"{calls} of the {2 * nq} queries (BFS and reach from the first {calls // 2} sources) "
-                         f"in {used:.1f} s on one host thread"}
+                         f"in {used:.1f} s on one host thread",
+               "host": f"1 of {os.cpu_count()} cores ({_cpu_model()})"}
 
     extras = {}
     if not args.no_extras:
@@ -458,6 +475,29 @@ def main():
             sb.close()
             extras["job_sequential_full_device"] = {"gteps": round(edges_per_step / el / 1e9, 3),
                                                     "ms_per_step": round(el * 1e3, 3)}
+        # latency floor: a BFS from a source of eccentricity e makes e dependent
+        # accesses one after the other; this design's level is three (offsets,
+        # targets, the returning atomic)
+        hop = {k: pg.probe_latency(1 << 30, 20000, k, stream=stream) for k in ("load", "coherent", "atomic")}
+        hop_l2 = pg.probe_latency(1 << 20, 20000, "load", stream=stream)
+        eccs = []
+        for s in sub:
+            _, st = pg.bfs(d, s, dist_out=dist, stats=True, stream=stream, mode="plain")
+            eccs.append(st["rounds"] - 1)
+        ecc = float(np.mean(eccs))
+        floor_ms = ecc * hop["load"] * 1e-6
+        chain_ms = ecc * (2 * hop["load"] + hop["atomic"]) * 1e-6
+        meas = extras["bfs_single_tau1024_window32"]["ms_per_query"]
+        extras["latency_floor"] = {
+            "t_hop_ns_1GiB": {k: round(v, 1) for k, v in hop.items()}, "t_hop_ns_1MiB_load": round(hop_l2, 1),
+            "ecc_mean_of_4_sources": ecc, "ecc_max_of_4_sources": float(max(eccs)),
+            "single_bfs_floor_ms": round(floor_ms, 3), "single_bfs_chain_floor_ms": round(chain_ms, 3),
+            "single_bfs_measured_ms": meas, "measured_over_floor": round(meas / floor_ms, 2),
+            "measured_over_chain_floor": round(meas / chain_ms, 2),
+            "job_floor_ms": round(float(max(eccs)) * hop["load"] * 1e-6, 3),
+            "note": "floor = eccentricity x one dependent load (1 GiB random cycle); chain floor = eccentricity x "
+                    "(2 loads + 1 atomic), the dependent accesses of one level in this design; the job's 16 "
+                    "queries run at once, so its floor is the largest eccentricity (of the 4 sampled) x one load"}
         plain_ms = extras["bfs_single_plain"]["ms_per_query"] + extras["reach_single_plain"]["ms_per_query"]
         extras["job_plain_sequential_estimate"] = {
             "gteps": round(edges_per_step / (plain_ms * nq * 1e-3) / 1e9, 3),

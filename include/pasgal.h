@@ -209,6 +209,26 @@ int pasgal_transpose(const pasgal_csr *g, int32_t *t_offsets, int32_t *t_targets
  * targets in range). Returns PASGAL_OK or PASGAL_ECSR. */
 int pasgal_validate(const pasgal_csr *g, const pasgal_opts *opts);
 
+/* Memory-latency probe (measurement support; Experimental Results: a
+ * traversal's rounds follow the diameter, so its time has a floor of one
+ * dependent memory access per level): the mean time of one dependent access.
+ * One lane follows a random single cycle through a device buffer of
+ * 2^floor(log2(bytes / 4)) uint32 slots (built on the device; each slot holds
+ * the next slot's index), `steps` times, timed by the device wall clock. A
+ * traversal from a source of eccentricity e makes at least e such accesses
+ * one after the other, so it takes at least e * ns_per_hop.
+ * kind: PASGAL_PROBE_LOAD plain load (cached), PASGAL_PROBE_COHERENT
+ * agent-scope relaxed atomic load (how the kernels read data other
+ * workgroups write), PASGAL_PROBE_ATOMIC agent-scope atomic add of 0 (a
+ * relaxation's round trip). bytes in [4096, 2^32], steps in [1, 2^24].
+ * The buffer is allocated and freed inside the call. Synchronous on
+ * opts->stream (opts may be NULL). PASGAL_EINVAL: null ns_per_hop or an
+ * argument out of range (nothing is run). */
+#define PASGAL_PROBE_LOAD 0
+#define PASGAL_PROBE_COHERENT 1
+#define PASGAL_PROBE_ATOMIC 2
+int pasgal_probe_latency(int64_t bytes, int32_t steps, int32_t kind, double *ns_per_hop, const pasgal_opts *opts);
+
 /* --------------------------------------------------------------------- SCC --
  * Strongly connected components (Parallel SCC section): reachability searches
  * from batches of pivots. Pivots are taken in a random vertex order, in

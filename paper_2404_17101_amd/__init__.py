@@ -205,6 +205,21 @@ def transpose(g: DeviceGraph, **opts) -> DeviceGraph:
     return out
 
 
+PROBE_KINDS = {"load": 0, "coherent": 1, "atomic": 2}
+
+
+def probe_latency(nbytes: int, steps: int = 20000, kind: str = "load", **opts) -> float:
+    """Mean ns of one dependent device-memory access over a buffer of about
+    nbytes (a random single cycle walked by one lane): the per-level floor of
+    a traversal. kind: "load" (cached), "coherent" (agent-scope load) or
+    "atomic" (agent-scope atomic add of 0)."""
+    ns = ctypes.c_double()
+    o = _opts(**opts)
+    _check(L.load().pasgal_probe_latency(int(nbytes), int(steps), PROBE_KINDS[kind], ctypes.byref(ns), ctypes.byref(o)),
+           "pasgal_probe_latency")
+    return ns.value
+
+
 def validate(g: DeviceGraph, **opts) -> bool:
     csr = g.csr()
     o = _opts(**opts)

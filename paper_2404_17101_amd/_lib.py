@@ -21,6 +21,7 @@ REQ_BFS, REQ_REACH = 0, 1
 EXPORTS = [
     "pasgal_opts_default", "pasgal_strerror", "pasgal_last_hip_error", "pasgal_version",
     "pasgal_bfs", "pasgal_bfs_ex", "pasgal_bfs_do", "pasgal_sssp", "pasgal_reach", "pasgal_reach_ex", "pasgal_transpose", "pasgal_validate",
+    "pasgal_probe_latency",
     "pasgal_scc", "pasgal_batch_create", "pasgal_batch_run", "pasgal_batch_config", "pasgal_batch_destroy",
     "pasgal_server_create", "pasgal_server_add_graph", "pasgal_server_submit", "pasgal_server_poll",
     "pasgal_server_drain", "pasgal_server_load", "pasgal_server_destroy",
@@ -119,6 +120,7 @@ def load(path: str = LIB_PATH):
     lib.pasgal_reach_ex.argtypes = [P(Csr), P(i32), i32, vp, P(Opts), P(Stats)]
     lib.pasgal_transpose.argtypes = [P(Csr), vp, vp, P(Opts)]
     lib.pasgal_validate.argtypes = [P(Csr), P(Opts)]
+    lib.pasgal_probe_latency.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), P(Opts)]
     lib.pasgal_scc.argtypes = [P(Csr), P(Csr), vp, P(SccOpts), P(Opts), P(SccStats)]
     lib.pasgal_batch_create.argtypes = [P(BatchDesc), P(Opts), ctypes.c_uint32, P(vp)]
     lib.pasgal_batch_run.argtypes = [vp, P(Stats)]
@@ -134,7 +136,8 @@ def load(path: str = LIB_PATH):
     lib.pasgal_server_destroy.argtypes = [vp]
     lib.pasgal_server_destroy.restype = None
     for f in ("pasgal_bfs", "pasgal_bfs_ex", "pasgal_bfs_do", "pasgal_sssp", "pasgal_reach", "pasgal_reach_ex", "pasgal_transpose",
-              "pasgal_validate", "pasgal_scc", "pasgal_batch_create", "pasgal_batch_run", "pasgal_batch_config",
+              "pasgal_validate", "pasgal_probe_latency", "pasgal_scc", "pasgal_batch_create", "pasgal_batch_run",
+              "pasgal_batch_config",
               "pasgal_server_create", "pasgal_server_add_graph", "pasgal_server_submit", "pasgal_server_poll",
               "pasgal_server_drain", "pasgal_server_load"):
         getattr(lib, f).restype = c_int

@@ -107,6 +107,16 @@ def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
     assert lib.pasgal_sssp(ctypes.byref(good), None, 4, out, None, None) == -1
     assert lib.pasgal_bfs_do(ctypes.byref(good), None, -1, out, 0, 0, None, None) == -1
     assert lib.pasgal_bfs_do(ctypes.byref(good), None, 0, None, 0, 0, None, None) == -1
+    # latency probe: null result, sizes, step counts and kinds out of range
+    ns = ctypes.c_double(-1.0)
+    assert lib.pasgal_probe_latency(1 << 20, 100, 0, None, None) == -1
+    assert lib.pasgal_probe_latency(4095, 100, 0, ctypes.byref(ns), None) == -1
+    assert lib.pasgal_probe_latency((1 << 32) + 1, 100, 0, ctypes.byref(ns), None) == -1
+    assert lib.pasgal_probe_latency(1 << 20, 0, 0, ctypes.byref(ns), None) == -1
+    assert lib.pasgal_probe_latency(1 << 20, (1 << 24) + 1, 0, ctypes.byref(ns), None) == -1
+    assert lib.pasgal_probe_latency(1 << 20, 100, 3, ctypes.byref(ns), None) == -1
+    assert lib.pasgal_probe_latency(1 << 20, 100, -1, ctypes.byref(ns), None) == -1
+    assert ns.value == -1.0
     # defaults of the VGC options
     o = L.Opts()
     lib.pasgal_opts_default(ctypes.byref(o))
