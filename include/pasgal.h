@@ -12,6 +12,12 @@
  *     (reachability search, Parallel SCC section). Visit order is free, so
  *     the local search of VGC (Vertical Granularity Control paragraph) may go
  *     deep. Backward reachability is forward reachability on G^T.
+ *   Built on the same kernel: strongly connected components (pasgal_scc),
+ *   direction-optimizing BFS (pasgal_bfs_do), single-source shortest paths
+ *   (pasgal_sssp), a batched form for many BFS queries over many graphs
+ *   (pasgal_batch_*) and a served form with continuous batching
+ *   (pasgal_server_*); pasgal_probe_latency measures the dependent-access
+ *   time behind a traversal's latency floor.
  *
  * Graph: int32 CSR, G = (V, E), n = |V|, m arcs (Preliminaries). offsets[n+1]
  * with offsets[0] = 0 and offsets[n] = m, targets[m] in [0, n). Self-loops and
@@ -28,7 +34,10 @@
  * Threads: calls on different streams may run concurrently from different
  * host threads; each stream has its own workspace. A persistent traversal
  * launch assumes it has the GPU's compute units to itself (its grid barrier
- * needs every workgroup resident); two such launches must not overlap.
+ * needs every workgroup resident), so two such launches must not overlap,
+ * except two launches that both set PASGAL_FLAG_HALF_DEVICE, which are sized
+ * to share every compute unit. A launch that cannot become resident ends in
+ * PASGAL_ETIMEOUT when its barrier deadline passes; it does not hang.
  */
 #ifndef PASGAL_H
 #define PASGAL_H
