@@ -251,7 +251,9 @@ int pasgal_probe_latency(int64_t bytes, int32_t steps, int32_t kind, double *ns_
  * one persistent VGC reach launch (PASGAL_MODE_PLAIN: tau = 1, one BFS level
  * per round, in the same launch). Trimming, an addition to the paper's
  * description: a vertex with no in-arc or no out-arc left inside its
- * subproblem is a component by itself. */
+ * subproblem is a component by itself. After every batch the still
+ * unsettled vertices are renumbered 0..na-1, and every later pass (packing,
+ * searches, refinement, trimming, splitting) covers only them. */
 typedef struct pasgal_scc_stats {
   int64_t components;   /* strongly connected components */
   int64_t trimmed;      /* vertices settled by trimming */
@@ -271,7 +273,9 @@ typedef struct pasgal_scc_stats {
 typedef struct pasgal_scc_opts {
   int32_t trim_rounds; /* trimming passes before the first batch (the loop stops after a pass that
                           settles fewer than n/1024 vertices), plus one pass after every batch; < 0
-                          selects 8, 0 disables trimming */
+                          selects 1 (every pass before the first batch also renumbers and repacks,
+                          and the pass after each batch catches what a second one would), 0
+                          disables trimming */
   uint32_t flags;      /* PASGAL_SCC_* */
   uint32_t seed;       /* key of the random pivot order; 0 selects a fixed default. The result does not
                           depend on it. */

@@ -35,6 +35,14 @@
 //    pivot bits, instead of one subproblem that gets 64 pivots per repeat.
 //  * The output names each component by its smallest vertex, which makes it
 //    unique whatever the pivots were.
+//  * Active-vertex renumbering: the unsettled vertices, in ascending order,
+//    are numbered 0..na-1 (act[j] = global id, loc[v] = local id). After
+//    every refinement and trimming pass a stable compaction drops the
+//    settled ones, and the packed CSR (2*na rows, local ids), the masks, the
+//    labels (per local row) and every per-vertex pass cover only the active
+//    vertices. Pivots still come from the random order of all vertex ids.
+//    Because the order is kept, the smallest local id of a set of active
+//    vertices is also its smallest global id.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,13 +63,15 @@ namespace {
 // counters[] slots (device; read back once per batch)
 enum : int { C_NPIV = 0, C_DEFER, C_POOL, C_TRIM, C_COMPS, C_UNSETTLED, C_COUNT = 8 };
 
-// Source rows of a pack: rows [0, n) from (offA, tgtA), rows [n, 2n) from
-// (offB, tgtB) read at row index v - n. Targets are either local vertex ids
-// in [0, n) (the caller's G and G^T) or packed ids (backward rows pointing
-// into [n, 2n)).
-struct PackIn {
+// Source of a pack: the arcs of the rows to keep, in the numbering of the
+// previous pack (or the caller's G and G^T, numbered by global id, before the
+// first pack). Forward rows are (offA, tgtA), backward rows (offB, tgtB),
+// both indexed by the old local id; a target t names old local id t, or
+// t - na_old for a backward copy.
+struct PackSrc {
   const int32_t *offA, *tgtA;
   const int32_t *offB, *tgtB;
+  uint32_t na_old;
 };
 
 // ------------------------------------------------------------ permutation --
@@ -120,33 +130,37 @@ __device__ __forceinline__ uint64_t wave_first(uint64_t lo) {
 __device__ __forceinline__ uint64_t grid_step() { return (uint64_t)gridDim.x * blockDim.x; }
 
 // ------------------------------------------------------------ pack kernels --
-// One wavefront handles 64 consecutive rows of the packed graph: their arcs
-// are dealt out across the lanes (consecutive lanes take consecutive arcs,
-// owner row by binary search over the degree scan). An arc (u, w) is kept iff
-// u and w are unsettled, different, and carry the same label. The count pass
-// writes the kept arcs of each row; the scatter pass writes them at
-// off_new[first row] + (kept arcs of the 64 rows before it), which is their
-// packed position because the rows are consecutive.
+// One wavefront handles 64 consecutive rows of the new packed graph (row r <
+// na_new: forward copy of new local vertex r; row na_new + r: its backward
+// copy): their source arcs are dealt out across the lanes (consecutive lanes
+// take consecutive arcs, owner row by binary search over the degree scan).
+// An arc is kept iff its target is still active (remap >= 0), is not the row's
+// own vertex and carries the same label. The count pass writes the kept arcs
+// of each row; the scatter pass writes them at off_new[first row] + (kept
+// arcs of the 64 rows before it), which is their packed position because the
+// rows are consecutive.
 template <bool SCATTER>
-__global__ void __launch_bounds__(256) pack_kernel(PackIn in, uint32_t n, const int32_t *__restrict__ comp,
-                                                   const uint32_t *__restrict__ label, int32_t *__restrict__ cnt,
+__global__ void __launch_bounds__(256) pack_kernel(PackSrc in, uint32_t na_new, const uint32_t *__restrict__ old_of,
+                                                   const int32_t *__restrict__ remap,
+                                                   const uint32_t *__restrict__ label_old, int32_t *__restrict__ cnt,
                                                    const int32_t *__restrict__ off_new,
                                                    int32_t *__restrict__ tgt_new) {
   __shared__ uint32_t scan_s[4][64];
   __shared__ uint32_t keep_s[4][64];
   const uint32_t ln = lane_id(), wid = threadIdx.x >> 6;
-  const uint64_t rows = 2ull * n;
+  const uint64_t rows = 2ull * na_new;
+  const uint32_t na_old = in.na_old;
   for (uint64_t base = wave_first(0); base < rows; base += grid_step()) {
     const uint64_t u = base + ln;
-    const bool fwd = u < n;
-    const uint32_t bu = (uint32_t)(fwd ? u : u - n);
+    const bool fwd = u < na_new;
     int32_t b = 0, e = 0;
-    uint32_t lab = 0;
-    if (u < rows && comp[bu] < 0) {
+    uint32_t lab = 0, src = 0;
+    if (u < rows) {
+      src = old_of[fwd ? u : u - na_new];
       const int32_t *o = fwd ? in.offA : in.offB;
-      b = o[bu];
-      e = o[bu + 1];
-      lab = label[bu];
+      b = o[src];
+      e = o[src + 1];
+      lab = label_old[src];
     }
     const uint32_t deg = (uint32_t)(e - b);
     const uint32_t incl = wave_incl_scan(deg, ln);
@@ -167,16 +181,16 @@ __global__ void __launch_bounds__(256) pack_kernel(PackIn in, uint32_t n, const 
       const int32_t bo = __shfl(b, owner);
       const uint32_t eo = __shfl(excl, owner);
       const uint32_t lo = __shfl(lab, owner);
+      const uint32_t so = __shfl(src, owner);
       bool keep = false;
       uint32_t t_out = 0;
       if (ai < total) {
-        const uint64_t uo = base + (uint64_t)owner;
-        const bool f = uo < n;
-        const uint32_t buo = (uint32_t)(f ? uo : uo - n);
+        const bool f = base + (uint64_t)owner < na_new;
         const uint32_t t = (uint32_t)(f ? in.tgtA : in.tgtB)[bo + (int32_t)(ai - eo)];
-        const uint32_t bw = t >= n ? t - n : t;
-        keep = bw != buo && comp[bw] < 0 && label[bw] == lo;
-        t_out = f ? bw : bw + n;
+        const uint32_t bw = t >= na_old ? t - na_old : t;
+        const int32_t nw = remap[bw];
+        keep = bw != so && nw >= 0 && label_old[bw] == lo;
+        t_out = f ? (uint32_t)nw : (uint32_t)nw + na_new;
       }
       const unsigned long long bal = __ballot(keep);
       if (SCATTER) {
@@ -192,19 +206,73 @@ __global__ void __launch_bounds__(256) pack_kernel(PackIn in, uint32_t n, const 
   }
 }
 
+// Active-vertex compaction, step 1: keep[j] = 1 iff act[j] is unsettled.
+__global__ void __launch_bounds__(256) keep_kernel(uint32_t na, const uint32_t *__restrict__ act,
+                                                   const int32_t *__restrict__ comp, int32_t *__restrict__ keep) {
+  const uint64_t stride = grid_step();
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < na; j += stride)
+    keep[j] = comp[act[j]] < 0 ? 1 : 0;
+}
+
+// Step 2 (after the exclusive scan pos of keep): the kept vertices move to
+// their new local ids in order; remap[old] = new id or -1.
+__global__ void __launch_bounds__(256) compact_kernel(uint32_t na, const uint32_t *__restrict__ act_old,
+                                                      const uint32_t *__restrict__ label_old,
+                                                      const int32_t *__restrict__ keep,
+                                                      const int32_t *__restrict__ pos, uint32_t *__restrict__ act_new,
+                                                      uint32_t *__restrict__ label_new, uint32_t *__restrict__ old_of,
+                                                      int32_t *__restrict__ remap, uint32_t *__restrict__ loc) {
+  const uint64_t stride = grid_step();
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < na; j += stride) {
+    if (keep[j]) {
+      const uint32_t jn = (uint32_t)pos[j], v = act_old[j];
+      act_new[jn] = v;
+      label_new[jn] = label_old[j];
+      old_of[jn] = (uint32_t)j;
+      remap[j] = (int32_t)jn;
+      loc[v] = jn;
+    } else {
+      remap[j] = -1;
+    }
+  }
+}
+
+__global__ void iota_kernel(uint32_t n, uint32_t *__restrict__ out) {
+  const uint64_t stride = grid_step();
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) out[v] = (uint32_t)v;
+}
+
+// The reach launch's query record: one query over the 2*na packed vertices.
+__global__ void set_query_kernel(QInfo *qi, int64_t *qword, uint32_t nv) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    qi->sbase = 0;
+    qi->dbase = 0;
+    qi->vbase = 0;
+    qi->nv = (int32_t)nv;
+    qi->r0 = 0;
+    qi->pad = 0;
+    qword[0] = 0;
+    qword[1] = ((int64_t)nv + 31) / 32;
+  }
+}
+
 // A vertex with no out-arc or no in-arc left in the packed CSR is a
 // component by itself.
-__global__ void __launch_bounds__(256) trim_kernel(const int32_t *__restrict__ off2, uint32_t n,
-                                                   int32_t *__restrict__ comp, uint32_t *__restrict__ counters) {
+__global__ void __launch_bounds__(256) trim_kernel(const int32_t *__restrict__ off2, uint32_t na,
+                                                   const uint32_t *__restrict__ act, int32_t *__restrict__ comp,
+                                                   uint32_t *__restrict__ counters) {
   uint32_t mine = 0;
-  for (uint64_t base = wave_first(0); base < n; base += grid_step()) {
-    const uint64_t v = base + lane_id();
-    if (v < n && comp[v] < 0) {
-      const bool no_out = off2[v + 1] == off2[v];
-      const bool no_in = off2[n + v + 1] == off2[n + v];
-      if (no_out || no_in) {
-        comp[v] = (int32_t)v;
-        mine++;
+  for (uint64_t base = wave_first(0); base < na; base += grid_step()) {
+    const uint64_t j = base + lane_id();
+    if (j < na) {
+      const uint32_t v = act[j];
+      if (comp[v] < 0) {
+        const bool no_out = off2[j + 1] == off2[j];
+        const bool no_in = off2[na + j + 1] == off2[na + j];
+        if (no_out || no_in) {
+          comp[v] = (int32_t)v;
+          mine++;
+        }
       }
     }
   }
@@ -217,6 +285,7 @@ __global__ void __launch_bounds__(256) trim_kernel(const int32_t *__restrict__ o
 // repeat of the batch.
 __global__ void __launch_bounds__(256) select_kernel(uint32_t lo, uint32_t hi, uint32_t n, uint32_t h,
                                                      uint32_t seed, const int32_t *__restrict__ comp,
+                                                     const uint32_t *__restrict__ loc,
                                                      const uint32_t *__restrict__ label,
                                                      uint32_t *__restrict__ slot_cnt, uint32_t *__restrict__ piv_v,
                                                      uint32_t *__restrict__ piv_bit,
@@ -230,7 +299,7 @@ __global__ void __launch_bounds__(256) select_kernel(uint32_t lo, uint32_t hi, u
     if (pos < hi) {
       v = perm_at((uint32_t)pos, n, h, seed);
       if (comp[v] < 0) {
-        bit = add_ag(&slot_cnt[label[v]], 1u);
+        bit = add_ag(&slot_cnt[label[loc[v]]], 1u);
         draw = true;
       }
     }
@@ -254,34 +323,36 @@ __global__ void __launch_bounds__(256) select_kernel(uint32_t lo, uint32_t hi, u
 // of the pivot table for it.
 __global__ void __launch_bounds__(256) reserve_kernel(uint32_t npiv, const uint32_t *__restrict__ piv_v,
                                                       const uint32_t *__restrict__ piv_bit,
+                                                      const uint32_t *__restrict__ loc,
                                                       const uint32_t *__restrict__ label,
                                                       const uint32_t *__restrict__ slot_cnt,
                                                       uint32_t *__restrict__ slot_base,
                                                       uint32_t *__restrict__ counters) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npiv || piv_bit[k] != 0) return;
-  const uint32_t lab = label[piv_v[k]];
+  const uint32_t lab = label[loc[piv_v[k]]];
   slot_base[lab] = add_ag(&counters[C_POOL], min(slot_cnt[lab], 64u));
 }
 
-// Record each pivot in the table and seed its forward copy v and backward
-// copy n+v with its bit: mask state and frontier entries 2k, 2k+1 (entries
-// past the frontier capacity go to the dirty bitmap). The masks and the
-// control block were zeroed before.
-__global__ void __launch_bounds__(256) seed_pivots_kernel(VgcArgs a, uint32_t n, uint32_t npiv,
+// Record each pivot (global id) in the table and seed its forward copy j =
+// loc[v] and backward copy na + j with its bit: mask state and frontier
+// entries 2k, 2k+1 (entries past the frontier capacity go to the dirty
+// bitmap). The masks and the control block were zeroed before.
+__global__ void __launch_bounds__(256) seed_pivots_kernel(VgcArgs a, uint32_t na, uint32_t npiv,
                                                           const uint32_t *__restrict__ piv_v,
                                                           const uint32_t *__restrict__ piv_bit,
+                                                          const uint32_t *__restrict__ loc,
                                                           const uint32_t *__restrict__ label,
                                                           const uint32_t *__restrict__ slot_base,
                                                           int32_t *__restrict__ pivtab) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0) st_ag(&a.ctl->cnt[0], 2u * npiv);
   if (k >= npiv) return;
-  const uint32_t v = piv_v[k], bit = piv_bit[k];
-  pivtab[slot_base[label[v]] + bit] = (int32_t)v;
+  const uint32_t v = piv_v[k], bit = piv_bit[k], j = loc[v];
+  pivtab[slot_base[label[j]] + bit] = (int32_t)v;
   const unsigned long long m = 1ull << bit;
   unsigned long long *mask = (unsigned long long *)a.state;
-  const uint32_t vv[2] = {v, n + v};
+  const uint32_t vv[2] = {j, na + j};
   for (int d = 0; d < 2; d++) {
     mask[vv[d]] = m;
     const uint64_t pos = 2ull * k + (uint64_t)d;
@@ -295,33 +366,36 @@ __global__ void __launch_bounds__(256) seed_pivots_kernel(VgcArgs a, uint32_t n,
   }
 }
 
-// Settle or refine every unsettled vertex from its forward mask F = mask[v]
-// and backward mask B = mask[n+v].
-__global__ void __launch_bounds__(256) refine_kernel(uint32_t n, uint32_t hmask,
+// Settle or refine every unsettled active vertex from its forward mask
+// F = mask[j] and backward mask B = mask[na + j].
+__global__ void __launch_bounds__(256) refine_kernel(uint32_t na, uint32_t hmask,
                                                      const unsigned long long *__restrict__ mask,
-                                                     int32_t *__restrict__ comp, uint32_t *__restrict__ label,
+                                                     const uint32_t *__restrict__ act, int32_t *__restrict__ comp,
+                                                     uint32_t *__restrict__ label,
                                                      const uint32_t *__restrict__ slot_base,
                                                      const int32_t *__restrict__ pivtab) {
   const uint64_t stride = grid_step();
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < na; j += stride) {
+    const uint32_t v = act[j];
     if (comp[v] >= 0) continue;
-    const unsigned long long f = mask[v], b = mask[n + v];
+    const unsigned long long f = mask[j], b = mask[na + j];
     const unsigned long long c = f & b;
-    const uint32_t lab = label[v];
+    const uint32_t lab = label[j];
     if (c)
       comp[v] = pivtab[slot_base[lab] + (uint32_t)__builtin_ctzll(c)];
     else if (f | b)
-      label[v] = refine_label(lab, f, b, hmask);
+      label[j] = refine_label(lab, f, b, hmask);
   }
 }
 
 // Pivots are settled and keep their label: their subproblem counters go back
 // to zero for the next batch.
 __global__ void __launch_bounds__(256) clear_slots_kernel(uint32_t npiv, const uint32_t *__restrict__ piv_v,
+                                                          const uint32_t *__restrict__ loc,
                                                           const uint32_t *__restrict__ label,
                                                           uint32_t *__restrict__ slot_cnt) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < npiv) slot_cnt[label[piv_v[k]]] = 0;
+  if (k < npiv) slot_cnt[label[loc[piv_v[k]]]] = 0;
 }
 
 // minv[c] = smallest vertex whose component record is c. A giant component
@@ -402,23 +476,20 @@ __device__ __forceinline__ void uf_unite(uint32_t *parent, uint32_t a, uint32_t 
   }
 }
 
-__global__ void __launch_bounds__(256) iota_kernel(uint32_t n, uint32_t *__restrict__ parent) {
-  const uint64_t stride = grid_step();
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) parent[v] = (uint32_t)v;
-}
-
 // Unite the endpoints of every forward arc of the packed CSR between
-// unsettled vertices (the backward rows hold the same arcs reversed). The
-// arcs of 64 consecutive rows are dealt out across a wavefront as in the pack.
+// unsettled vertices (local ids; the backward rows hold the same arcs
+// reversed). The arcs of 64 consecutive rows are dealt out across a
+// wavefront as in the pack.
 __global__ void __launch_bounds__(256) union_kernel(const int32_t *__restrict__ off2,
-                                                    const int32_t *__restrict__ tgt2, uint32_t n,
+                                                    const int32_t *__restrict__ tgt2, uint32_t na,
+                                                    const uint32_t *__restrict__ act,
                                                     const int32_t *__restrict__ comp, uint32_t *parent) {
   __shared__ uint32_t scan_s[4][64];
   const uint32_t ln = lane_id(), wid = threadIdx.x >> 6;
-  for (uint64_t base = wave_first(0); base < n; base += grid_step()) {
+  for (uint64_t base = wave_first(0); base < na; base += grid_step()) {
     const uint64_t u = base + ln;
     int32_t b = 0, e = 0;
-    if (u < n && comp[u] < 0) {
+    if (u < na && comp[act[u]] < 0) {
       b = off2[u];
       e = off2[u + 1];
     }
@@ -439,19 +510,22 @@ __global__ void __launch_bounds__(256) union_kernel(const int32_t *__restrict__ 
       const uint32_t eo = __shfl(excl, owner);
       if (ai < total) {
         const uint32_t w = (uint32_t)tgt2[bo + (int32_t)(ai - eo)];
-        if (comp[w] < 0) uf_unite(parent, (uint32_t)base + (uint32_t)owner, w);
+        if (comp[act[w]] < 0) uf_unite(parent, (uint32_t)base + (uint32_t)owner, w);
       }
     }
     wave_sync();
   }
 }
 
-// Every unsettled vertex takes its piece's root (smallest vertex) as label.
-__global__ void __launch_bounds__(256) piece_label_kernel(uint32_t n, const int32_t *__restrict__ comp,
-                                                          uint32_t *parent, uint32_t *__restrict__ label) {
+// Every unsettled active vertex takes its piece's root as label, named by
+// the root's global id (the smallest vertex of the piece, since local ids
+// keep the order of global ids).
+__global__ void __launch_bounds__(256) piece_label_kernel(uint32_t na, const uint32_t *__restrict__ act,
+                                                          const int32_t *__restrict__ comp, uint32_t *parent,
+                                                          uint32_t *__restrict__ label) {
   const uint64_t stride = grid_step();
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    if (comp[v] < 0) label[v] = uf_find(parent, (uint32_t)v);
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < na; j += stride)
+    if (comp[act[j]] < 0) label[j] = act[uf_find(parent, (uint32_t)j)];
 }
 
 int grid_for(uint64_t items, int cap = 8192) {
@@ -465,12 +539,13 @@ int grid_for(uint64_t items, int cap = 8192) {
 
 // Grow-only buffers of the SCC driver, one set per stream workspace.
 struct SccBufs {
-  DBuf off2[2], tgt2[2], mask, label, slot_cnt, slot_base, pivtab, piv_v, piv_bit, cnt, sums, counters, minv, t_off,
-      t_tgt, tscratch, parent;
-  HBuf h_read;  // counters + control block read back per batch
+  DBuf off2[2], tgt2[2], mask, lab[2], act[2], loc, remap, old_of, keep, pos, slot_cnt, slot_base, pivtab, piv_v,
+      piv_bit, cnt, sums, counters, minv, t_off, t_tgt, tscratch, parent;
+  HBuf h_read;  // counters, control block and the active count, read back per batch
   ~SccBufs() {
-    for (DBuf *b : {&off2[0], &off2[1], &tgt2[0], &tgt2[1], &mask, &label, &slot_cnt, &slot_base, &pivtab, &piv_v,
-                    &piv_bit, &cnt, &sums, &counters, &minv, &t_off, &t_tgt, &tscratch, &parent})
+    for (DBuf *b : {&off2[0], &off2[1], &tgt2[0], &tgt2[1], &mask, &lab[0], &lab[1], &act[0], &act[1], &loc, &remap,
+                    &old_of, &keep, &pos, &slot_cnt, &slot_base, &pivtab, &piv_v, &piv_bit, &cnt, &sums, &counters,
+                    &minv, &t_off, &t_tgt, &tscratch, &parent})
       free_buf(*b);
     free_hbuf(h_read);
   }
@@ -493,45 +568,75 @@ struct SccRun {
   SccBufs &b;
   hipStream_t s;
   uint32_t n;
-  int cur = 0;  // packed CSR buffer holding the current graph
+  uint32_t *h_na;  // pinned: the active count read back after a compaction
+  int cur = 0;     // packed CSR buffer holding the current graph
+  int ab = 0;      // act / label buffers of the current numbering
+  uint32_t na = 0;  // active vertices in the current numbering
 
   int32_t *off2(int i) { return (int32_t *)b.off2[i].p; }
   int32_t *tgt2(int i) { return (int32_t *)b.tgt2[i].p; }
   uint32_t *counters() { return (uint32_t *)b.counters.p; }
+  uint32_t *act() { return (uint32_t *)b.act[ab].p; }
+  uint32_t *label() { return (uint32_t *)b.lab[ab].p; }
+  uint32_t *loc() { return (uint32_t *)b.loc.p; }
 
-  // Rebuild the packed CSR from `in` into buffer cur ^ 1 (or cur on the first
-  // pack) with the current labels and settled set.
-  hipError_t pack(const PackIn &in, int dst, const int32_t *comp, const uint32_t *label) {
+  // Drop the settled vertices from the numbering (stable compaction) and
+  // rebuild the packed CSR from `src`, numbered by the numbering before this
+  // call, into buffer dst.
+  hipError_t compact_and_pack(const PackSrc &src, int dst, const int32_t *comp) {
     (void)hipGetLastError();
-    const uint64_t rows = 2ull * n;
-    const int grid = grid_for(rows, 16384);  // 256 rows per block and step (4 waves x 64 rows)
-    int32_t *cnt = (int32_t *)b.cnt.p;
-    hipLaunchKernelGGL(pack_kernel<false>, dim3(grid), dim3(256), 0, s, in, n, comp, label, cnt,
-                       (const int32_t *)nullptr, (int32_t *)nullptr);
+    const uint32_t na_old = na;
+    const int old = ab, nw = ab ^ 1;
+    int32_t *keep = (int32_t *)b.keep.p, *pos = (int32_t *)b.pos.p;
+    hipLaunchKernelGGL(keep_kernel, dim3(grid_for(na_old)), dim3(256), 0, s, na_old, (const uint32_t *)b.act[old].p,
+                       comp, keep);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = launch_excl_scan(keep, (int64_t)na_old, (int32_t *)b.sums.p, pos, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h_na, pos + na_old, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    const uint32_t na_new = *h_na;
+    hipLaunchKernelGGL(compact_kernel, dim3(grid_for(na_old)), dim3(256), 0, s, na_old,
+                       (const uint32_t *)b.act[old].p, (const uint32_t *)b.lab[old].p, (const int32_t *)keep,
+                       (const int32_t *)pos, (uint32_t *)b.act[nw].p, (uint32_t *)b.lab[nw].p,
+                       (uint32_t *)b.old_of.p, (int32_t *)b.remap.p, loc());
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint64_t rows = 2ull * na_new;
+    const int grid = grid_for(rows, 16384);  // 256 rows per block and step (4 waves x 64 rows)
+    int32_t *cnt = (int32_t *)b.cnt.p;
+    hipLaunchKernelGGL(pack_kernel<false>, dim3(grid), dim3(256), 0, s, src, na_new, (const uint32_t *)b.old_of.p,
+                       (const int32_t *)b.remap.p, (const uint32_t *)b.lab[old].p, cnt, (const int32_t *)nullptr,
+                       (int32_t *)nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_excl_scan(cnt, (int64_t)rows, (int32_t *)b.sums.p, off2(dst), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(pack_kernel<true>, dim3(grid), dim3(256), 0, s, in, n, comp, label, (int32_t *)nullptr,
+    hipLaunchKernelGGL(pack_kernel<true>, dim3(grid), dim3(256), 0, s, src, na_new, (const uint32_t *)b.old_of.p,
+                       (const int32_t *)b.remap.p, (const uint32_t *)b.lab[old].p, (int32_t *)nullptr,
                        (const int32_t *)off2(dst), tgt2(dst));
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    ab = nw;
+    na = na_new;
+    return hipSuccess;
   }
-  // Relabel every unsettled vertex by its weakly connected piece of the
-  // current packed CSR.
-  hipError_t split_pieces(const int32_t *comp, uint32_t *label) {
+  // Relabel every unsettled active vertex by its weakly connected piece of
+  // the current packed CSR.
+  hipError_t split_pieces(const int32_t *comp) {
     (void)hipGetLastError();
+    if (na == 0) return hipSuccess;
     uint32_t *parent = (uint32_t *)b.parent.p;
-    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, parent);
-    hipLaunchKernelGGL(union_kernel, dim3(grid_for(n, 16384)), dim3(256), 0, s, (const int32_t *)b.off2[cur].p,
-                       (const int32_t *)b.tgt2[cur].p, n, comp, parent);
-    hipLaunchKernelGGL(piece_label_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, comp, parent, label);
+    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(na)), dim3(256), 0, s, na, parent);
+    hipLaunchKernelGGL(union_kernel, dim3(grid_for(na, 16384)), dim3(256), 0, s, (const int32_t *)b.off2[cur].p,
+                       (const int32_t *)b.tgt2[cur].p, na, (const uint32_t *)act(), comp, parent);
+    hipLaunchKernelGGL(piece_label_kernel, dim3(grid_for(na)), dim3(256), 0, s, na, (const uint32_t *)act(), comp,
+                       parent, label());
     return hipGetLastError();
   }
-  PackIn packed_in() const {
-    PackIn p;
+  PackSrc packed_src() const {
+    PackSrc p;
     p.offA = (const int32_t *)b.off2[cur].p;
     p.tgtA = (const int32_t *)b.tgt2[cur].p;
-    p.offB = (const int32_t *)b.off2[cur].p + n;
+    p.offB = (const int32_t *)b.off2[cur].p + na;
     p.tgtB = (const int32_t *)b.tgt2[cur].p;
+    p.na_old = na;
     return p;
   }
 };
@@ -554,7 +659,7 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
   Opts o = resolve_opts(opts);
   if (o.flags & PASGAL_FLAG_ASYNC) return PASGAL_EINVAL;
   if (o.mode == PASGAL_MODE_PLAIN) o.tau = 1;
-  if (trim_rounds < 0) trim_rounds = 8;
+  if (trim_rounds < 0) trim_rounds = 1;  // later passes run after every batch anyway
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;
   std::lock_guard<std::mutex> lk(w->mu);
@@ -586,7 +691,10 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
     DBuf *b;
     size_t bytes;
   } need[] = {{&B.off2[0], 4 * (n2 + 1)}, {&B.off2[1], 4 * (n2 + 1)}, {&B.tgt2[0], 4 * m2 + 4},
-              {&B.tgt2[1], 4 * m2 + 4}, {&B.mask, 8 * n2}, {&B.label, 4 * (size_t)n}, {&B.slot_cnt, 4 * H},
+              {&B.tgt2[1], 4 * m2 + 4}, {&B.mask, 8 * n2}, {&B.lab[0], 4 * (size_t)n}, {&B.lab[1], 4 * (size_t)n},
+              {&B.act[0], 4 * (size_t)n}, {&B.act[1], 4 * (size_t)n}, {&B.loc, 4 * (size_t)n},
+              {&B.remap, 4 * (size_t)n}, {&B.old_of, 4 * (size_t)n}, {&B.keep, 4 * ((size_t)n + 1)},
+              {&B.pos, 4 * ((size_t)n + 1)}, {&B.slot_cnt, 4 * H},
               {&B.slot_base, 4 * H}, {&B.pivtab, 4 * (size_t)n}, {&B.piv_v, 4 * (size_t)n},
               {&B.piv_bit, 4 * (size_t)n}, {&B.cnt, 4 * (n2 + 1)}, {&B.sums, 4 * (size_t)excl_scan_tiles(n2) + 64},
               {&B.counters, 4 * C_COUNT}, {&B.minv, 4 * (size_t)n}, {&B.parent, 4 * (size_t)n},
@@ -594,8 +702,7 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
               {&w->ctl, sizeof(Ctl)}, {&w->qi, sizeof(QInfo)}, {&w->qword, 2 * sizeof(int64_t)}};
   for (auto &x : need)
     if ((rc = grow(*x.b, x.bytes))) return rc;
-  if ((rc = grow_host(B.h_read, 4 * C_COUNT + sizeof(Ctl)))) return rc;
-  if ((rc = grow_host(w->h_stage, sizeof(QInfo) + 2 * sizeof(int64_t)))) return rc;
+  if ((rc = grow_host(B.h_read, 4 * C_COUNT + sizeof(Ctl) + 16))) return rc;
   pasgal_csr t{};
   if (gt) {
     t = *gt;
@@ -611,28 +718,15 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
     t.offsets = (const int32_t *)B.t_off.p;
     t.targets = (const int32_t *)B.t_tgt.p;
   }
-  // query table of the packed graph: one query over 2n vertices
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
-  QInfo *hq = (QInfo *)w->h_stage.p;
-  int64_t *hw = (int64_t *)((uint8_t *)w->h_stage.p + sizeof(QInfo));
-  memset(hq, 0, sizeof(QInfo));
-  hq->nv = (int32_t)n2;  // n < 2^30, so 2n fits
-  hw[0] = 0;
-  hw[1] = (int64_t)dwords;
-  if ((e = hipMemcpyAsync(w->qi.p, hq, sizeof(QInfo), hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e);
-  if ((e = hipMemcpyAsync(w->qword.p, hw, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s)) != hipSuccess)
-    return hip_fail(e);
-
   int32_t *comp = comp_out;
-  uint32_t *label = (uint32_t *)B.label.p;
   uint32_t *slot_cnt = (uint32_t *)B.slot_cnt.p;
   uint32_t *slot_base = (uint32_t *)B.slot_base.p;
   uint32_t *piv_v = (uint32_t *)B.piv_v.p, *piv_bit = (uint32_t *)B.piv_bit.p;
   int32_t *pivtab = (int32_t *)B.pivtab.p;
-  SccRun R{B, s, n};
-  uint32_t *ctr = R.counters();
   uint32_t *h_ctr = (uint32_t *)B.h_read.p;
   Ctl *h_ctl = (Ctl *)((uint8_t *)B.h_read.p + 4 * C_COUNT);
+  SccRun R{B, s, n, (uint32_t *)((uint8_t *)B.h_read.p + 4 * C_COUNT + sizeof(Ctl))};
+  uint32_t *ctr = R.counters();
 
   VgcArgs a{};
   a.tgt = nullptr;
@@ -674,24 +768,28 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
 
   if ((e = hipEventRecord(w->ev0, s)) != hipSuccess) return fail(e);
   if ((e = launch_fill_u32((uint32_t *)comp, n, 0xFFFFFFFFu, s)) != hipSuccess) return fail(e);
-  if ((e = launch_fill_u32(label, n, 0u, s)) != hipSuccess) return fail(e);
+  if ((e = launch_fill_u32(R.label(), n, 0u, s)) != hipSuccess) return fail(e);
+  hipLaunchKernelGGL(iota_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, R.act());  // every vertex active
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   if ((e = launch_fill_u32(slot_cnt, H, 0u, s)) != hipSuccess) return fail(e);
   if ((e = launch_fill_u32(ctr, C_COUNT, 0u, s)) != hipSuccess) return fail(e);
-  PackIn orig{g->offsets, g->targets, t.offsets, t.targets};
+  // first numbering: every vertex (the caller's G and G^T are numbered by global id)
+  R.na = n;
   R.cur = 0;
-  if ((e = R.pack(orig, 0, comp, label)) != hipSuccess) return fail(e);
+  if ((e = R.compact_and_pack(PackSrc{g->offsets, g->targets, t.offsets, t.targets, n}, 0, comp)) != hipSuccess)
+    return fail(e);
 
   int64_t trimmed = 0;
-  for (int tr = 0; tr < trim_rounds; tr++) {
-    hipLaunchKernelGGL(trim_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const int32_t *)R.off2(R.cur), n, comp,
-                       ctr);
+  for (int tr = 0; tr < trim_rounds && R.na > 0; tr++) {
+    hipLaunchKernelGGL(trim_kernel, dim3(grid_for(R.na)), dim3(256), 0, s, (const int32_t *)R.off2(R.cur), R.na,
+                       (const uint32_t *)R.act(), comp, ctr);
     if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     if ((e = read_counters()) != hipSuccess) return fail(e);
     const int64_t now = h_ctr[C_TRIM];
     const int64_t got = now - trimmed;
     trimmed = now;
     if (got == 0) break;
-    if ((e = R.pack(R.packed_in(), R.cur ^ 1, comp, label)) != hipSuccess) return fail(e);
+    if ((e = R.compact_and_pack(R.packed_src(), R.cur ^ 1, comp)) != hipSuccess) return fail(e);
     R.cur ^= 1;
     // a pass that settles few vertices is not worth another full repack: the
     // pass after every batch picks up what is left
@@ -713,7 +811,7 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
     (void)hipGetLastError();
     return h_ctl->abort == 0;
   };
-  for (uint64_t lo = 0, len = 1; lo < n; lo += len, len *= 2) {
+  for (uint64_t lo = 0, len = 1; lo < n && R.na > 0; lo += len, len *= 2) {
     const uint32_t hi = (uint32_t)std::min<uint64_t>(n, lo + len);
     // every repeat settles at least one vertex of the range (each drawn
     // subproblem's bit-0 pivot), so more repeats than positions is a bug
@@ -721,7 +819,8 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
       if (rep > (uint64_t)(hi - lo)) return PASGAL_EINTERNAL;
       if ((e = launch_fill_u32(ctr, 3, 0u, s)) != hipSuccess) return fail(e);  // NPIV, DEFER, POOL
       hipLaunchKernelGGL(select_kernel, dim3(grid_for(hi - lo)), dim3(256), 0, s, (uint32_t)lo, hi, n, fh, seed,
-                         (const int32_t *)comp, (const uint32_t *)label, slot_cnt, piv_v, piv_bit, ctr);
+                         (const int32_t *)comp, (const uint32_t *)R.loc(), (const uint32_t *)R.label(), slot_cnt,
+                         piv_v, piv_bit, ctr);
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       if ((e = read_counters()) != hipSuccess) return fail(e);
       if (!collect()) return PASGAL_ETIMEOUT;
@@ -731,16 +830,23 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
       pivots += npiv;
       const int pg_grid = (int)((npiv + 255) / 256);
       hipLaunchKernelGGL(reserve_kernel, dim3(pg_grid), dim3(256), 0, s, npiv, (const uint32_t *)piv_v,
-                         (const uint32_t *)piv_bit, (const uint32_t *)label, (const uint32_t *)slot_cnt, slot_base,
-                         ctr);
+                         (const uint32_t *)piv_bit, (const uint32_t *)R.loc(), (const uint32_t *)R.label(),
+                         (const uint32_t *)slot_cnt, slot_base, ctr);
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
-      if ((e = launch_fill_u64((unsigned long long *)B.mask.p, n2, 0ull, s)) != hipSuccess) return fail(e);
-      if ((e = launch_fill_u32((uint32_t *)w->dirty.p, dwords, 0u, s)) != hipSuccess) return fail(e);
+      // the searches run on the packed graph of the 2 * na active copies
+      const uint64_t nv2 = 2ull * R.na, dw2 = (nv2 + 31) / 32;
+      if ((e = launch_fill_u64((unsigned long long *)B.mask.p, nv2, 0ull, s)) != hipSuccess) return fail(e);
+      if ((e = launch_fill_u32((uint32_t *)w->dirty.p, dw2, 0u, s)) != hipSuccess) return fail(e);
       if ((e = launch_fill_u32((uint32_t *)w->ctl.p, sizeof(Ctl) / 4, 0u, s)) != hipSuccess) return fail(e);
+      hipLaunchKernelGGL(set_query_kernel, dim3(1), dim3(64), 0, s, (QInfo *)w->qi.p, (int64_t *)w->qword.p,
+                         (uint32_t)nv2);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       a.off = R.off2(R.cur);
       a.tgt = R.tgt2(R.cur);
-      hipLaunchKernelGGL(seed_pivots_kernel, dim3(pg_grid), dim3(256), 0, s, a, n, npiv, (const uint32_t *)piv_v,
-                         (const uint32_t *)piv_bit, (const uint32_t *)label, (const uint32_t *)slot_base, pivtab);
+      a.dirty_words = (int64_t)dw2;
+      hipLaunchKernelGGL(seed_pivots_kernel, dim3(pg_grid), dim3(256), 0, s, a, R.na, npiv, (const uint32_t *)piv_v,
+                         (const uint32_t *)piv_bit, (const uint32_t *)R.loc(), (const uint32_t *)R.label(),
+                         (const uint32_t *)slot_base, pivtab);
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       if ((e = hipEventRecord(w->evk, s)) != hipSuccess) return fail(e);
       if ((e = launch_vgc(KIND_REACH, false, lg.pf, a, lg.grid, lg.block, lg.lds, coop_launch(o), s)) !=
@@ -750,21 +856,22 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
       if ((e = hipMemcpyAsync(h_ctl, w->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s)) != hipSuccess)
         return fail(e);
       pending_reach = true;
-      hipLaunchKernelGGL(refine_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, hmask,
-                         (const unsigned long long *)B.mask.p, comp, label, (const uint32_t *)slot_base,
-                         (const int32_t *)pivtab);
+      hipLaunchKernelGGL(refine_kernel, dim3(grid_for(R.na)), dim3(256), 0, s, R.na, hmask,
+                         (const unsigned long long *)B.mask.p, (const uint32_t *)R.act(), comp, R.label(),
+                         (const uint32_t *)slot_base, (const int32_t *)pivtab);
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       hipLaunchKernelGGL(clear_slots_kernel, dim3(pg_grid), dim3(256), 0, s, npiv, (const uint32_t *)piv_v,
-                         (const uint32_t *)label, slot_cnt);
+                         (const uint32_t *)R.loc(), (const uint32_t *)R.label(), slot_cnt);
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
-      if ((e = R.pack(R.packed_in(), R.cur ^ 1, comp, label)) != hipSuccess) return fail(e);
+      if ((e = R.compact_and_pack(R.packed_src(), R.cur ^ 1, comp)) != hipSuccess) return fail(e);
       R.cur ^= 1;
+      if (R.na == 0) break;  // every vertex is settled
       if (trim_rounds > 0) {
-        hipLaunchKernelGGL(trim_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const int32_t *)R.off2(R.cur), n,
-                           comp, ctr);
+        hipLaunchKernelGGL(trim_kernel, dim3(grid_for(R.na)), dim3(256), 0, s, (const int32_t *)R.off2(R.cur), R.na,
+                           (const uint32_t *)R.act(), comp, ctr);
         if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       }
-      if (split && (e = R.split_pieces(comp, label)) != hipSuccess) return fail(e);
+      if (split && (e = R.split_pieces(comp)) != hipSuccess) return fail(e);
       if (ndefer == 0) break;
     }
   }
