@@ -154,7 +154,8 @@ def suite_scc(args, pg, gg, torch):
         cpu_s, exp = _cpu_baseline_scc(g)
         entry = {"graph": name, "n": g.n, "m": g.m, "transpose_ms": round(t_ms, 3),
                  "cpu_baseline": {"tarjan_ms": round(cpu_s * 1e3, 1), "cores": 1, "kind": "oracle"}, "gpu": {}}
-        for label, kw in [("vgc", dict()), ("tau1", dict(mode="plain")), ("no_trim", dict(trim_rounds=0)),
+        for label, kw in [("vgc", dict()), ("tau1024", dict(tau=1024)), ("tau1", dict(mode="plain")),
+                          ("no_trim", dict(trim_rounds=0)),
                           ("no_split", dict(split=False))]:
             ts, st = [], None
             for _ in range(3):

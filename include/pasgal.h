@@ -93,9 +93,9 @@ typedef struct pasgal_opts {
   int32_t mode;              /* PASGAL_MODE_VGC or PASGAL_MODE_PLAIN */
   int32_t tau;               /* VGC: vertices a local search expands per frontier vertex before it
                                 publishes what is left (the paper's tau); <= 0 selects the entry
-                                point's default: 1024, except pasgal_sssp on a graph of mean out-degree
-                                above 8, where it selects 1. tau = 1 makes every round one BFS level
-                                inside the persistent kernel. */
+                                point's default: 1024, except pasgal_sssp and pasgal_scc on a graph of
+                                mean out-degree above 8, where it selects 1. tau = 1 makes every round
+                                one BFS level inside the persistent kernel. */
   int32_t wg_size;           /* threads per workgroup: 64..1024, multiple of 64; <= 0 selects 1024 */
   int32_t blocks_per_cu;     /* persistent workgroups per compute unit; <= 0 selects 1 */
   int64_t frontier_capacity; /* entries per frontier buffer; <= 0 selects max(2n, 65536). Smaller values

@@ -92,8 +92,8 @@ def _stream_ptr(stream) -> int:
 def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
           stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=False, test_first=False,
           spread_arcs=True, heavy_arcs=0, filter_slots=0, chunks_per_wave=0, half_device=False) -> L.Opts:
-    """tau: local-search budget (0 = the entry point's default: 1024, SSSP on
-    graphs of mean out-degree above 8: 1). window: BFS distance window per
+    """tau: local-search budget (0 = the entry point's default: 1024, SSSP and
+    SCC on graphs of mean out-degree above 8: 1). window: BFS distance window per
     round (0 or negative = none).
     heavy_arcs: rows with more arcs are cut into slices dealt to all
     wavefronts (0 = default 512, negative = never). filter_slots: per-wavefront
