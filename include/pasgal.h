@@ -78,7 +78,11 @@ typedef struct pasgal_csr {
 #define PASGAL_FLAG_PREFETCH 4u   /* VGC: local-queue entries carry their vertex's arc range, loaded while the
                                       relaxing atomic is in flight (default: loaded when the entry is expanded) */
 #define PASGAL_FLAG_TEST_FIRST 8u  /* VGC: read a target's state before the atomic and skip the atomic when
-                                      the relaxation cannot change it */
+                                      the relaxation cannot change it. On by default for pasgal_reach_ex
+                                      with k >= 2 sources on graphs with m >= 4n and for pasgal_scc on
+                                      graphs with m > 8n (most arcs there offer bits the target already
+                                      has); off by default elsewhere, where it measured slower */
+#define PASGAL_FLAG_NO_TEST_FIRST 64u /* VGC: never read before the atomic (overrides those defaults) */
 #define PASGAL_FLAG_ROW_PER_LANE 16u /* VGC: scan rows of <= 8 arcs lane by lane instead of dealing every
                                         vertex's arcs out across the wavefront (default: consecutive lanes take
                                         consecutive arcs, so one memory instruction touches few cache lines) */

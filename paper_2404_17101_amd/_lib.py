@@ -13,7 +13,8 @@ ERRORS = {
     -8: "ENOTFOUND", -9: "EINTERNAL",
 }
 MODE_VGC, MODE_PLAIN = 0, 1
-FLAG_VALIDATE, FLAG_ASYNC, FLAG_PREFETCH, FLAG_TEST_FIRST, FLAG_ROW_PER_LANE, FLAG_HALF_DEVICE = 1, 2, 4, 8, 16, 32
+FLAG_VALIDATE, FLAG_ASYNC, FLAG_PREFETCH, FLAG_TEST_FIRST, FLAG_ROW_PER_LANE, FLAG_HALF_DEVICE, FLAG_NO_TEST_FIRST = \
+    1, 2, 4, 8, 16, 32, 64
 BATCH_AUTOTUNE = 1
 REQ_BFS, REQ_REACH = 0, 1
 

@@ -154,7 +154,7 @@ Opts resolve_opts(const pasgal_opts *o) {
   r.window = o->window > 0 ? (uint32_t)o->window : (o->window == 0 ? 32u : 0u);
   r.min_chunk = o->min_chunk > 0 ? (uint32_t)std::min(o->min_chunk, 64) : 1u;
   r.prefetch = (o->flags & PASGAL_FLAG_PREFETCH) != 0;
-  r.test_first = (o->flags & PASGAL_FLAG_TEST_FIRST) != 0;
+  r.test_first = (o->flags & PASGAL_FLAG_TEST_FIRST) != 0;  // entry points may turn it on by default
   r.lane_arcs = (o->flags & PASGAL_FLAG_ROW_PER_LANE) ? 8u : 0u;
   r.heavy = o->heavy_arcs > 0 ? (uint32_t)o->heavy_arcs : (o->heavy_arcs == 0 ? 512u : 0u);
   r.cpw = o->chunks_per_wave > 0 ? (uint32_t)std::min(o->chunks_per_wave, 64) : 1u;
@@ -620,6 +620,11 @@ int pasgal_reach_ex(const pasgal_csr *g, const int32_t *sources, int32_t k, uint
     if (sources[i] < 0 || sources[i] >= g->n) return PASGAL_EINVAL;
   Opts o = resolve_opts(opts);
   if (o.mode == PASGAL_MODE_PLAIN && (o.flags & PASGAL_FLAG_ASYNC)) return PASGAL_EINVAL;
+  // several sources on a graph of mean out-degree >= 4: a vertex gets most
+  // of its bits before its last in-neighbours offer them again, so a plain
+  // read first skips most atomics (on sparser graphs the read only lengthens
+  // each level's chain of dependent accesses)
+  if (k >= 2 && (int64_t)g->m >= 4 * (int64_t)g->n && !(o.flags & PASGAL_FLAG_NO_TEST_FIRST)) o.test_first = true;
   const int W = (k + 63) / 64;
   if (W > 1 && (o.flags & PASGAL_FLAG_ASYNC)) return PASGAL_EINVAL;
   Workspace *w = workspace_for(o.stream);

@@ -661,6 +661,8 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
   // default tau by mean out-degree, as for SSSP: on dense low-diameter graphs
   // the searches reach everything in a few levels anyway
   if (!opts || opts->tau <= 0) o.tau = (int64_t)g->m > 8 * (int64_t)g->n ? 1u : 1024u;
+  // and a plain read before each OR there (most arcs offer bits already present)
+  if ((int64_t)g->m > 8 * (int64_t)g->n && !(o.flags & PASGAL_FLAG_NO_TEST_FIRST)) o.test_first = true;
   if (o.mode == PASGAL_MODE_PLAIN) o.tau = 1;
   if (trim_rounds < 0) trim_rounds = 1;  // later passes run after every batch anyway
   Workspace *w = workspace_for(o.stream);
