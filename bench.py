@@ -219,7 +219,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tau", type=int, default=1024)
-    ap.add_argument("--window", type=int, default=32)
+    ap.add_argument("--window", type=int, default=0,
+                    help="BFS distance window (default 24 concurrent, 32 sequential: measured best for each)")
     ap.add_argument("--wg", type=int, default=0, help="workgroup size (default 512 concurrent, 1024 sequential)")
     ap.add_argument("--schedule", choices=["concurrent", "sequential"], default="concurrent")
     ap.add_argument("--bpc", type=int, default=1)
@@ -240,6 +241,8 @@ def main():
                     help="write profiles/ summaries from rocprofv3 CSV output under DIR (prof_trace, prof_fetch, "
                          "prof_write, prof_cfetch, prof_cwrite)")
     args = ap.parse_args()
+    if args.window <= 0:
+        args.window = 24 if args.schedule == "concurrent" else 32
 
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args)
@@ -461,7 +464,7 @@ def main():
                                                "ms_per_query": round(el / len(sub) * 1e3, 3)}
         if conc:
             # the same job with the two launches one after the other, each on the whole device
-            full = dict(tau=args.tau, window=args.window, wg_size=1024, blocks_per_cu=1, stream=stream)
+            full = dict(tau=args.tau, window=32, wg_size=1024, blocks_per_cu=1, stream=stream)
             sb = pg.Batch(d, vb, np.zeros(nq, np.int32), np.array(srcs, np.int32),
                           np.arange(nq, dtype=np.int64) * n, dist16, **full)
             for rep_ in range(2):
