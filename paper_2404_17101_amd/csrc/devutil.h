@@ -47,6 +47,7 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint32_t mbcnt64(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, uint32_t ln) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -65,11 +66,62 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
   for (int d = 32; d >= 1; d >>= 1) x = min(x, (uint32_t)__shfl_xor(x, d));
   return x;
 }
+// The same scans with DPP row shifts and three lane reads instead of one
+// LDS permute round trip per doubling step. All 64 lanes must be active.
+// A row is 16 lanes; row_shr:n gives lane l the value of lane l - n of its
+// row, and 0 where that lies before the row's first lane.
+template <int N>
+__device__ __forceinline__ uint32_t row_shr(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x110 + N, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t lane_read(uint32_t x, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+// Inclusive prefix sum over the wavefront.
+__device__ __forceinline__ uint32_t wave_incl_sum_dpp(uint32_t x, uint32_t ln) {
+  x += row_shr<1>(x);
+  x += row_shr<2>(x);
+  x += row_shr<4>(x);
+  x += row_shr<8>(x);  // prefix sum within each row
+  const uint32_t r0 = lane_read(x, 15), r1 = lane_read(x, 31), r2 = lane_read(x, 47);
+  const uint32_t row = ln >> 4;
+  return x + (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
+}
+// Inclusive prefix maximum over the wavefront (unsigned).
+__device__ __forceinline__ uint32_t wave_incl_max_dpp(uint32_t x, uint32_t ln) {
+  x = max(x, row_shr<1>(x));
+  x = max(x, row_shr<2>(x));
+  x = max(x, row_shr<4>(x));
+  x = max(x, row_shr<8>(x));  // prefix maximum within each row
+  const uint32_t r0 = lane_read(x, 15), r1 = lane_read(x, 31), r2 = lane_read(x, 47);
+  const uint32_t row = ln >> 4;
+  const uint32_t before = row == 0 ? 0u : row == 1 ? r0 : row == 2 ? max(r0, r1) : max(max(r0, r1), r2);
+  return max(x, before);
+}
+// Maximum over the wavefront, the same in every lane.
+__device__ __forceinline__ uint32_t wave_max_dpp(uint32_t x, uint32_t ln) {
+  return lane_read(wave_incl_max_dpp(x, ln), 63);
+}
+// Arc dealing: lane L owns the arcs [excl, excl + deg) of a concatenation of
+// the lanes' rows (disjoint ranges that cover [0, total)). Returns the lane
+// that owns arc j0 + ln, for j0 < total; lanes past total get the last owner.
+// mk is 64 words of this wavefront's LDS. Each lane whose range meets
+// [j0, j0 + 64) marks where it starts there (position 0 for the range that
+// began earlier); a prefix maximum carries each mark forward over its range.
+__device__ __forceinline__ uint32_t wave_arc_owner(uint32_t excl, uint32_t deg, uint32_t j0, uint32_t *mk,
+                                                   uint32_t ln) {
+  mk[ln] = 0u;
+  wave_sync();
+  if (deg != 0u && excl < j0 + 64u && excl + deg > j0) mk[excl > j0 ? excl - j0 : 0u] = ln + 1u;
+  wave_sync();
+  const uint32_t m = mk[ln];
+  wave_sync();
+  return wave_incl_max_dpp(m, ln) - 1u;
+}
 __device__ __forceinline__ unsigned long long shfl64(unsigned long long x, int src) {
   uint32_t lo = __shfl((uint32_t)x, src), hi = __shfl((uint32_t)(x >> 32), src);
   return ((unsigned long long)hi << 32) | lo;
 }
-__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // Exclusive scan of one value per thread over a 256-thread workgroup; total
 // receives the sum of all 256 values.

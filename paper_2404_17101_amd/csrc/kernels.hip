@@ -398,8 +398,8 @@ struct Wave {
     const bool hv = act && (uint32_t)(e - b) > a.heavy;
     if (!__ballot(hv)) return;
     const uint32_t k = hv ? ((uint32_t)(e - b) + a.heavy - 1) / a.heavy : 0u;
-    const uint32_t incl = wave_incl_scan(k, ln);
-    const uint32_t tot = __shfl(incl, 63);
+    const uint32_t incl = wave_incl_sum_dpp(k, ln);
+    const uint32_t tot = lane_read(incl, 63);
     uint32_t base = 0;
     if (ln == 0) base = add_ag(&a.ctl->hcnt[nslot], tot);
     base = __shfl(base, 0);
@@ -460,8 +460,10 @@ struct Wave {
     st_expand += nexp;
     if (slice_ok) cut_heavy(act, v, q, val, b, e);
     const uint32_t deg = act ? (uint32_t)(e - b) : 0u;
-    const uint32_t maxd = wave_max(deg);
-    if (maxd == 0) return nexp;
+    // scans by DPP row shifts: no LDS round trip on the step's critical path
+    const uint32_t incl = wave_incl_sum_dpp(deg, ln);
+    const uint32_t total = lane_read(incl, 63);
+    if (total == 0) return nexp;
     // both paths count into these, and one epilogue adds them to the stats
     // (an update per path let the compiler merge the two into one store
     // through a selected address, which kept the counters in scratch memory)
@@ -469,6 +471,7 @@ struct Wave {
     // the row-per-lane path exists only in LANE instantiations: its eight
     // relaxation records in flight would otherwise set every kernel's
     // register budget
+    const uint32_t maxd = LANE ? wave_max_dpp(deg, ln) : 0u;
     if (LANE && maxd <= a.lane_arcs) {
       int32_t w[8];
 #pragma clang loop unroll(full)
@@ -492,16 +495,13 @@ struct Wave {
       }
     } else {
       // Flattened: the wave's arcs are dealt out 64 at a time; each lane finds
-      // its arc's owner lane by binary search over the inclusive degree scan.
+      // its arc's owner lane from marks in LDS carried forward by a prefix
+      // maximum (one LDS round trip per pass).
       // Up to RB such passes are issued together (target loads, then atomics,
       // then pushes), so a lane has RB relaxations in flight instead of one;
       // passes past the last arc are skipped whole (wave-uniform), so a thin
       // step costs one pass.
-      const uint32_t incl = wave_incl_scan(deg, ln);
-      const uint32_t total = __shfl(incl, 63);
       const uint32_t excl = incl - deg;
-      scan[ln] = incl;
-      wave_sync();
       arcs = total;
       constexpr int RB = MULTI ? 4 : 1;  // single-query steps are thin: one pass
       for (uint32_t j0 = 0; j0 < total; j0 += 64 * RB) {
@@ -520,11 +520,7 @@ struct Wave {
           sbo[r] = 0;
           vo[r] = 0;
           if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform: no arcs left for this pass
-          uint32_t pos = 0;
-  #pragma unroll
-          for (uint32_t step = 32; step >= 1; step >>= 1)
-            if (scan[pos + step - 1] <= ai) pos += step;
-          const int owner = (int)min(pos, 63u);
+          const int owner = (int)wave_arc_owner(excl, deg, j0 + (uint32_t)r * 64u, scan, ln);
           const int32_t bo = __shfl(b, owner);
           const uint32_t eo = __shfl(excl, owner);
           qo[r] = MULTI ? (uint32_t)__shfl(q, owner) : 0u;
