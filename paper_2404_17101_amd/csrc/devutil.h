@@ -95,8 +95,8 @@ __device__ __forceinline__ uint32_t wave_incl_max_dpp(uint32_t x, uint32_t ln) {
   x = max(x, row_shr<8>(x));  // prefix maximum within each row
   const uint32_t r0 = lane_read(x, 15), r1 = lane_read(x, 31), r2 = lane_read(x, 47);
   const uint32_t row = ln >> 4;
-  const uint32_t before = row == 0 ? 0u : row == 1 ? r0 : row == 2 ? max(r0, r1) : max(max(r0, r1), r2);
-  return max(x, before);
+  // selects, not a chain of conditionals (which compiles to branches)
+  return max(max(x, row >= 1 ? r0 : 0u), max(row >= 2 ? r1 : 0u, row >= 3 ? r2 : 0u));
 }
 // Maximum over the wavefront, the same in every lane.
 __device__ __forceinline__ uint32_t wave_max_dpp(uint32_t x, uint32_t ln) {

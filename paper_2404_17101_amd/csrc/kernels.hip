@@ -264,9 +264,14 @@ struct Wave {
   // when allowed and there is room, else to the staging buffer.
   __device__ __forceinline__ void push(bool p, uint32_t w, uint32_t q, Val nv, bool ring_ok, int32_t nb = 0,
                                       int32_t ne = 0) {
+    push_lim(p, w, q, nv, (DIST && a.window) ? limit_of(q) : 0xFFFFFFFFu, ring_ok, nb, ne);
+  }
+  // The same, with the round's limit of query q already looked up.
+  __device__ __forceinline__ void push_lim(bool p, uint32_t w, uint32_t q, Val nv, uint32_t lim, bool ring_ok,
+                                          int32_t nb, int32_t ne) {
     // BFS window: values at or beyond the round's limit wait for a later round
     if (DIST && a.window) {
-      const bool late = p && (uint32_t)nv >= limit_of(q);
+      const bool late = p && (uint32_t)nv >= lim;
       push_stage(late, w, q, nv);
       p = p && !late;
     }
@@ -374,11 +379,11 @@ struct Wave {
 
   // Only for a lane whose relax_issue ran (a valid arc); offered is the value
   // that relax_issue got (read for reach, whose records do not keep it).
-  __device__ __forceinline__ bool relax_finish(const Rx &x, int64_t sb, uint32_t w, Val offered, Val &nv) {
+  // key: the low 32 bits of w's state index (the LDS filter's key).
+  __device__ __forceinline__ bool relax_finish(const Rx &x, uint32_t key, Val offered, Val &nv) {
     if (DIST) {
       nv = x.nd;
       if (a.filt) {
-        const uint32_t key = (uint32_t)(sb + (int64_t)w);
         filt[filt_slot(key)] =
             ((unsigned long long)key << 32) | (unsigned long long)min((uint32_t)x.old, (uint32_t)x.nd);
       }
@@ -487,7 +492,7 @@ struct Wave {
       for (int u = 0; u < 8; u++) {
         if ((uint32_t)u < maxd) {  // wave-uniform
           Val nv = DIST ? x[u].nd : val;
-          const bool ok = (uint32_t)u < deg && relax_finish(x[u], sb, (uint32_t)w[u], val, nv);
+          const bool ok = (uint32_t)u < deg && relax_finish(x[u], (uint32_t)sb + (uint32_t)w[u], val, nv);
           arcs += __popcll(__ballot((uint32_t)u < deg));
           nsucc += __popcll(__ballot(ok));
           push(ok, (uint32_t)w[u], q, nv, ring_ok, x[u].nb, x[u].ne);
@@ -505,7 +510,7 @@ struct Wave {
       arcs = total;
       constexpr int RB = MULTI ? 4 : 1;  // single-query steps are thin: one pass
       for (uint32_t j0 = 0; j0 < total; j0 += 64 * RB) {
-        uint32_t w[RB], qo[RB];
+        uint32_t w[RB], qo[RB], sbl[RB], lim[RB];
         int32_t arc[RB];
         int64_t sbo[RB];
         Val vo[RB];
@@ -518,18 +523,24 @@ struct Wave {
           arc[r] = 0;
           qo[r] = 0;
           sbo[r] = 0;
+          sbl[r] = 0;
+          lim[r] = 0xFFFFFFFFu;
           vo[r] = 0;
           if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform: no arcs left for this pass
           const int owner = (int)wave_arc_owner(excl, deg, j0 + (uint32_t)r * 64u, scan, ln);
-          const int32_t bo = __shfl(b, owner);
-          const uint32_t eo = __shfl(excl, owner);
+          // the owner's first arc minus its first dealt position
+          const uint32_t bx = (uint32_t)__shfl((int)((uint32_t)b - excl), owner);
           qo[r] = MULTI ? (uint32_t)__shfl(q, owner) : 0u;
           sbo[r] = MULTI ? (int64_t)shfl64((unsigned long long)sb, owner) : 0;
+          sbl[r] = (uint32_t)sbo[r];
+          // looked up now, while the target load is in flight, rather than
+          // after the atomic returns
+          if (DIST && a.window) lim[r] = limit_of(qo[r]);
           if (DIST)
             vo[r] = (Val)__shfl((uint32_t)val, owner);
           else
             vo[r] = (Val)shfl64((unsigned long long)val, owner);
-          arc[r] = bo + (int32_t)(ai - eo);
+          arc[r] = (int32_t)(bx + ai);
           w[r] = okl[r] ? (uint32_t)a.tgt[arc[r]] : 0u;
         }
         Rx x[RB];
@@ -544,11 +555,9 @@ struct Wave {
         for (int r = 0; r < RB; r++) {
           if (j0 + (uint32_t)r * 64u >= total) break;  // wave-uniform
           Val nv = 0;
-          // the query's state base is looked up again (LDS query table) rather
-          // than kept live across the passes in flight
-          const bool ok = okl[r] && relax_finish(x[r], MULTI ? sbase_of(qo[r]) : 0, w[r], vo[r], nv);
+          const bool ok = okl[r] && relax_finish(x[r], sbl[r] + w[r], vo[r], nv);
           nsucc += __popcll(__ballot(ok));
-          push(ok, w[r], qo[r], nv, ring_ok, x[r].nb, x[r].ne);
+          push_lim(ok, w[r], qo[r], nv, lim[r], ring_ok, x[r].nb, x[r].ne);
         }
       }
       wave_sync();
