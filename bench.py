@@ -85,7 +85,8 @@ def _counter_means(path):
 
 SUITE_TRACES = {
     "scc": ("Kernel trace: SCC suite (road4096, knn 10M/5, RMAT-20; VGC, tau 1, no trim, no split; 3 runs each)",
-            "vgc_kernel<1, false, false, false> is the reach kernel running the forward and backward searches of a "
+            "vgc_kernel<1, false, true, false> is the reach kernel (arc-range prefetch on, the SCC default) running "
+            "the forward and backward searches of a "
             "batch together on the packed 2n-vertex graph; pack_kernel<false/true> count and scatter the arcs that "
             "stay inside one subproblem; union_kernel / piece_label_kernel are the weak-connectivity split; "
             "trim_kernel, select_kernel, refine_kernel and min_member_kernel are the per-batch steps."),
@@ -130,7 +131,7 @@ def summarize_profiles(d, args):
     import csv
 
     kb = "void pg::vgc_kernel<0, true, false, false>(pg::VgcArgs)"
-    kr = "void pg::vgc_kernel<1, false, false, false>(pg::VgcArgs)"
+    kr = "void pg::vgc_kernel<1, false, true, false>(pg::VgcArgs)"
     cp = "__amd_rocclr_copyBuffer"
     rows = list(csv.DictReader(open(os.path.join(d, "prof_trace", "run_kernel_stats.csv"))))
     F = _counter_means(os.path.join(d, "prof_fetch", "run_counter_collection.csv"))
@@ -173,8 +174,8 @@ def summarize_profiles(d, args):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                      f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |")
     lines += ["", "`vgc_kernel<0, true, false, false>` is the multi-query BFS kernel (kind 0 = BFS, multi-query, no "
-                  "arc-range prefetch, no row-per-lane path); `vgc_kernel<1, false, false, false>` is the single-query "
-                  "reach kernel, run with a 16-bit mask. "
+                  "arc-range prefetch, no row-per-lane path); `vgc_kernel<1, false, true, false>` is the single-query "
+                  "reach kernel with arc-range prefetch (the reach default), run with a 16-bit mask. "
                   "`__amd_rocclr_copyBuffer` dispatches are the graph upload before the timed steps."]
     with open(os.path.join(prof, "vgc_bfs_batched16_knn10m_trace.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -189,7 +190,7 @@ def summarize_profiles(d, args):
              "```", "", "Per dispatch (KiB as reported), averaged over the dispatches of each kernel:", "",
              "| kernel | FETCH_SIZE | WRITE_SIZE | HBM bytes (calibrated) |", "|---|---|---|---|",
              f"| `vgc_kernel<0, true, false, false>` (BFS, 16 queries) | {F[kb]:,.1f} | {W[kb]:,.1f} | {traffic_b / 1e9:.2f} GB |",
-             f"| `vgc_kernel<1, false, false, false>` (reach, k = 16) | {F[kr]:,.1f} | {W[kr]:,.1f} | {traffic_r / 1e9:.2f} GB |",
+             f"| `vgc_kernel<1, false, true, false>` (reach, k = 16) | {F[kr]:,.1f} | {W[kr]:,.1f} | {traffic_r / 1e9:.2f} GB |",
              f"| `{cp}`, 1 GiB copy (calibration) | {CF[cp]:,.1f} | {CW[cp]:,.1f} | 2.15 GB |", "",
              f"Calibration: a plain 1 GiB copy reads and writes 1 GiB; the counters report {CF[cp] / 1048576:.3f} GiB and "
              f"{CW[cp] / 1048576:.3f} GiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.",

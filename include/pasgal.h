@@ -76,13 +76,18 @@ typedef struct pasgal_csr {
 #define PASGAL_FLAG_VALIDATE 1u /* check the CSR on the device first (O(n+m)) */
 #define PASGAL_FLAG_ASYNC 2u    /* do not synchronize the stream before returning (VGC mode only) */
 #define PASGAL_FLAG_PREFETCH 4u   /* VGC: local-queue entries carry their vertex's arc range, loaded while the
-                                      relaxing atomic is in flight (default: loaded when the entry is expanded) */
+                                      relaxing atomic is in flight, instead of when the entry is expanded.
+                                      On by default for pasgal_reach_ex and pasgal_scc (4-8% faster there);
+                                      off by default for BFS and the batched and served forms, where it
+                                      measured neutral; pasgal_sssp ignores it */
 #define PASGAL_FLAG_TEST_FIRST 8u  /* VGC: read a target's state before the atomic and skip the atomic when
                                       the relaxation cannot change it. On by default for pasgal_reach_ex
                                       with k >= 2 sources on graphs with m >= 4n and for pasgal_scc on
                                       graphs with m > 8n (most arcs there offer bits the target already
                                       has); off by default elsewhere, where it measured slower */
 #define PASGAL_FLAG_NO_TEST_FIRST 64u /* VGC: never read before the atomic (overrides those defaults) */
+#define PASGAL_FLAG_NO_PREFETCH 128u  /* VGC: never carry arc ranges in the local queue (overrides those
+                                         defaults and PASGAL_FLAG_PREFETCH) */
 #define PASGAL_FLAG_ROW_PER_LANE 16u /* VGC: scan rows of <= 8 arcs lane by lane instead of dealing every
                                         vertex's arcs out across the wavefront (default: consecutive lanes take
                                         consecutive arcs, so one memory instruction touches few cache lines) */

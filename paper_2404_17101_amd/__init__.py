@@ -90,7 +90,7 @@ def _stream_ptr(stream) -> int:
 
 
 def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
-          stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=False, test_first=None,
+          stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=None, test_first=None,
           spread_arcs=True, heavy_arcs=0, filter_slots=0, chunks_per_wave=0, half_device=False) -> L.Opts:
     """tau: local-search budget (0 = the entry point's default: 1024, SSSP and
     SCC on graphs of mean out-degree above 8: 1). window: BFS distance window per
@@ -102,7 +102,9 @@ def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0,
     that a second such call on another stream runs beside it. test_first:
     None = the entry point's default (on for reach with several sources on
     graphs of mean degree >= 4 and for SCC on graphs of mean degree > 8),
-    True / False = always / never read before the atomic."""
+    True / False = always / never read before the atomic. prefetch: None =
+    the entry point's default (on for reach and SCC), True / False = always /
+    never carry arc ranges in the local queue."""
     o = L.Opts()
     L.load().pasgal_opts_default(ctypes.byref(o))
     o.mode = {"vgc": L.MODE_VGC, "plain": L.MODE_PLAIN}[mode]
@@ -111,7 +113,7 @@ def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0,
     o.blocks_per_cu = int(blocks_per_cu)
     o.frontier_capacity = int(frontier_capacity)
     o.flags = ((L.FLAG_VALIDATE if validate else 0) | (L.FLAG_ASYNC if asynchronous else 0) |
-               (L.FLAG_PREFETCH if prefetch else 0) |
+               (0 if prefetch is None else (L.FLAG_PREFETCH if prefetch else L.FLAG_NO_PREFETCH)) |
                (0 if test_first is None else (L.FLAG_TEST_FIRST if test_first else L.FLAG_NO_TEST_FIRST)) |
                (0 if spread_arcs else L.FLAG_ROW_PER_LANE) | (L.FLAG_HALF_DEVICE if half_device else 0))
     o.timeout_ms = int(timeout_ms)

@@ -315,7 +315,8 @@ struct Wave {
   //  * LDS filter (distances): values this wavefront saw in the state; for the
   //    same reason a remembered value <= the new one proves the atomic
   //    cannot win.
-  //  * PF: the arc range of w is loaded alongside.
+  //  * PF: the arc range of w is loaded alongside the atomic (not for a
+  //    relaxation a filter ruled out: it pushes nothing).
   // A relaxation that a filter rules out keeps, as its "old" value, the value
   // that proved it (<= the offered one for distances, a superset mask for
   // reach), so finish() sees no change and the LDS filter entry it rewrites
@@ -332,10 +333,6 @@ struct Wave {
   __device__ __forceinline__ Rx relax_issue(int64_t sb, uint32_t w, int32_t arc, Val val) {
     Rx x;
     x.nb = x.ne = 0;
-    if (PF) {
-      x.nb = a.off[w];
-      x.ne = a.off[w + 1];
-    }
     if (DIST) {
       // SSSP distances saturate below the "unreached" value
       const uint32_t nd = (KIND == KIND_SSSP)
@@ -360,6 +357,10 @@ struct Wave {
           return x;
         }
       }
+      if (PF) {  // only for relaxations that reach the atomic
+        x.nb = a.off[w];
+        x.ne = a.off[w + 1];
+      }
       x.old = (Val)min_ag(p, nd);
     } else {
       unsigned long long *p = (unsigned long long *)&state[sb + w];
@@ -371,6 +372,10 @@ struct Wave {
           x.old = (Val)cur;
           return x;
         }
+      }
+      if (PF) {
+        x.nb = a.off[w];
+        x.ne = a.off[w + 1];
       }
       x.old = (Val)or_ag(p, m);
     }
