@@ -121,3 +121,19 @@ def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
     o = L.Opts()
     lib.pasgal_opts_default(ctypes.byref(o))
     assert (o.heavy_arcs, o.filter_slots, o.window) == (512, 256, 0)
+
+
+def test_constants_match_header():
+    """The binding's flag, mode and request constants carry the values that
+    include/pasgal.h defines."""
+    from paper_2404_17101_amd import _lib as L
+    txt = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define PASGAL_(\w+) \(?(-?\d+)u?\)?", txt)}
+    checked = 0
+    for name, val in defs.items():
+        if name.startswith(("FLAG_", "MODE_", "REQ_", "SCC_", "BATCH_")):
+            assert getattr(L, name) == val, name
+            checked += 1
+    assert checked >= 12
+    for code, text in L.ERRORS.items():
+        assert defs[text] == code, (code, text)
