@@ -95,8 +95,8 @@ SUITE_TRACES = {
              "mean-weight reduction behind the default bucket width."),
     "bfs_do": ("Kernel trace: direction-optimizing BFS suite (RMAT-24 and knn 10M/5, 4 sources each)",
                "bottom_up_kernel, collect_kernel and degsum_kernel belong to the direction-optimizing BFS; "
-               "plain_level_kernel<0> runs its top-down levels and the plain BFS; vgc_kernel<0, false, false, false> is the "
-               "VGC BFS."),
+               "plain_level_kernel<0> runs its top-down levels and the plain BFS; vgc_kernel<0, false, true, false> is the "
+               "VGC BFS (arc-range prefetch on, the single-source default)."),
 }
 
 

@@ -77,9 +77,9 @@ typedef struct pasgal_csr {
 #define PASGAL_FLAG_ASYNC 2u    /* do not synchronize the stream before returning (VGC mode only) */
 #define PASGAL_FLAG_PREFETCH 4u   /* VGC: local-queue entries carry their vertex's arc range, loaded while the
                                       relaxing atomic is in flight, instead of when the entry is expanded.
-                                      On by default for pasgal_reach_ex and pasgal_scc (4-8% faster there);
-                                      off by default for BFS and the batched and served forms, where it
-                                      measured neutral; pasgal_sssp ignores it */
+                                      On by default for pasgal_bfs_ex, pasgal_reach_ex and pasgal_scc
+                                      (4-8% faster there); off by default for the batched and served
+                                      forms, where it measured neutral; pasgal_sssp ignores it */
 #define PASGAL_FLAG_TEST_FIRST 8u  /* VGC: read a target's state before the atomic and skip the atomic when
                                       the relaxation cannot change it. On by default for pasgal_reach_ex
                                       with k >= 2 sources on graphs with m >= 4n and for pasgal_scc on

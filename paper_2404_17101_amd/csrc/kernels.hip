@@ -340,44 +340,51 @@ struct Wave {
                               : (uint32_t)val + 1u;
       x.nd = (Val)nd;
       uint32_t *p = (uint32_t *)&state[sb + w];
-      if (a.test_first) {
+      // straight-line: each filter narrows one predicate, then a single
+      // masked region performs the atomic (nested early exits compiled to
+      // long chains of exec-mask updates)
+      bool go = true;
+      uint32_t old = 0xFFFFFFFFu;
+      if (a.test_first) {  // wave-uniform
         const uint32_t cur = *(const uint32_t *)p;
-        if (cur <= nd) {
-          st_filt_lane++;
-          x.old = (Val)cur;
-          return x;
-        }
+        go = cur > nd;
+        old = cur;
       }
-      if (a.filt) {
+      if (a.filt) {  // wave-uniform
         const uint32_t key = (uint32_t)(sb + (int64_t)w);
         const unsigned long long e = filt[filt_slot(key)];
-        if ((uint32_t)(e >> 32) == key && (uint32_t)e <= nd) {
-          st_filt_lane++;
-          x.old = (Val)(uint32_t)e;
-          return x;
+        const bool hit = (uint32_t)(e >> 32) == key && (uint32_t)e <= nd;
+        old = (go && hit) ? (uint32_t)e : old;
+        go = go && !hit;
+      }
+      st_filt_lane += go ? 0u : 1u;
+      if (go) {
+        if (PF) {  // only for relaxations that reach the atomic
+          x.nb = a.off[w];
+          x.ne = a.off[w + 1];
         }
+        old = min_ag(p, nd);
       }
-      if (PF) {  // only for relaxations that reach the atomic
-        x.nb = a.off[w];
-        x.ne = a.off[w + 1];
-      }
-      x.old = (Val)min_ag(p, nd);
+      x.old = (Val)old;
     } else {
       unsigned long long *p = (unsigned long long *)&state[sb + w];
       const unsigned long long m = (unsigned long long)val;
-      if (a.test_first) {
+      bool go = true;
+      unsigned long long old = 0;
+      if (a.test_first) {  // wave-uniform
         const unsigned long long cur = *(const unsigned long long *)p;
-        if ((cur & m) == m) {
-          st_filt_lane++;
-          x.old = (Val)cur;
-          return x;
+        go = (cur & m) != m;
+        old = cur;
+      }
+      st_filt_lane += go ? 0u : 1u;
+      if (go) {
+        if (PF) {
+          x.nb = a.off[w];
+          x.ne = a.off[w + 1];
         }
+        old = or_ag(p, m);
       }
-      if (PF) {
-        x.nb = a.off[w];
-        x.ne = a.off[w + 1];
-      }
-      x.old = (Val)or_ag(p, m);
+      x.old = (Val)old;
     }
     return x;
   }
