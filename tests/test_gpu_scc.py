@@ -87,8 +87,10 @@ def test_scc_shapes_default(pg, name, make):
 
 @pytest.mark.parametrize("kw", [dict(trim_rounds=0), dict(mode="plain"), dict(tau=16), dict(tau=4096),
                                 dict(frontier_capacity=64), dict(trim_rounds=0, frontier_capacity=64, tau=64),
-                                dict(wg_size=256, blocks_per_cu=2)],
-                         ids=["notrim", "plain", "tau16", "tau4096", "cap64", "notrim_cap64_tau64", "wg256x2"])
+                                dict(wg_size=256, blocks_per_cu=2), dict(prefetch=False),
+                                dict(prefetch=False, test_first=True), dict(test_first=False)],
+                         ids=["notrim", "plain", "tau16", "tau4096", "cap64", "notrim_cap64_tau64", "wg256x2",
+                              "no_prefetch", "no_prefetch_test_first", "no_test_first"])
 def test_scc_schedules(pg, kw):
     for g in [gg.road(128, 3), gg.random_graph(3000, 4500, 42), gg.rmat(11, 8, 3)]:
         exp = oracle.scc_min_label(g)
