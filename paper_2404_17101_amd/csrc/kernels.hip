@@ -1038,26 +1038,20 @@ __global__ void __launch_bounds__(256) plain_level_kernel(const int32_t *off, co
       if (KIND == KIND_REACH) m = ld_ag(&((unsigned long long *)statev)[v]);
     }
     const uint32_t deg = act ? (uint32_t)(e - b) : 0u;
-    const uint32_t incl = wave_incl_scan(deg, ln);
-    const uint32_t total = __shfl(incl, 63);
+    const uint32_t incl = wave_incl_sum_dpp(deg, ln);
+    const uint32_t total = lane_read(incl, 63);
     const uint32_t excl = incl - deg;
-    scan_s[wid][ln] = incl;
-    wave_sync();
     arcs += total;
     for (uint32_t j = 0; j < total; j += 64) {
       const uint32_t ai = j + ln;
-      uint32_t pos = 0;
-#pragma unroll
-      for (uint32_t step = 32; step >= 1; step >>= 1)
-        if (scan_s[wid][pos + step - 1] <= ai) pos += step;
-      const int owner = (int)min(pos, 63u);
-      const int32_t bo = __shfl(b, owner);
-      const uint32_t eo = __shfl(excl, owner);
+      // the lane that owns arc ai, and its first arc minus its first dealt position
+      const int owner = (int)wave_arc_owner(excl, deg, j, scan_s[wid], ln);
+      const uint32_t bx = (uint32_t)__shfl((int)((uint32_t)b - excl), owner);
       const unsigned long long mo = (KIND == KIND_REACH) ? shfl64(m, owner) : 0ull;
       bool ok = false;
       uint32_t w = 0;
       if (ai < total) {
-        w = (uint32_t)tgt[bo + (int32_t)(ai - eo)];
+        w = (uint32_t)tgt[(int32_t)(bx + ai)];
         if (KIND == KIND_BFS) {
           ok = cas_ag(&((uint32_t *)statev)[w], INF32, level + 1) == INF32;
         } else {
