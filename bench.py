@@ -66,7 +66,7 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kern.h"):
+    for f in ("kernels.hip", "kern.h", "devutil.h"):
         with open(os.path.join(ROOT, "paper_2404_17101_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
