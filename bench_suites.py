@@ -250,9 +250,14 @@ def suite_bfs_do(args, pg, gg, torch):
         srcs = [int(x) for x in gg.sources(g, 4, 1005, min_degree=1)]
         import oracle
 
+        # the oracle's queue BFS, one core: the baseline column (its output
+        # also checks the GPU results)
+        t0 = time.perf_counter()
         exp = oracle.bfs(g, srcs[0])
+        cpu_ms = (time.perf_counter() - t0) * 1e3
         arcs = int(np.diff(g.offsets)[exp >= 0].sum())
-        entry = {"graph": name, "n": g.n, "m": g.m, "reached_arcs_src0": arcs, "gpu": {}}
+        entry = {"graph": name, "n": g.n, "m": g.m, "reached_arcs_src0": arcs,
+                 "cpu_baseline": {"bfs_ms_src0": round(cpu_ms, 1), "cores": 1, "kind": "oracle"}, "gpu": {}}
         for label, fn in [("vgc", lambda s: pg.bfs(d, s)), ("plain", lambda s: pg.bfs(d, s, mode="plain")),
                           ("direction_optimizing", lambda s: pg.bfs_do(d, s, transpose=t)),
                           ("direction_optimizing_alpha14", lambda s: pg.bfs_do(d, s, transpose=t, alpha=14))]:
