@@ -91,7 +91,9 @@ SUITE_TRACES = {
             "stay inside one subproblem; union_kernel / piece_label_kernel are the weak-connectivity split; "
             "trim_kernel, select_kernel, refine_kernel and min_member_kernel are the per-batch steps."),
     "sssp": ("Kernel trace: SSSP suite (knn 10M/5, road4096, RMAT-22; weights uniform in [1, 1000]; VGC and tau 1)",
-             "vgc_kernel<2, false, false, false> is the SSSP kernel (kind 2 = weighted distances); sum_u32_kernel is the "
+             "vgc_kernel<2, false, true, false> is the SSSP kernel (kind 2 = weighted distances) with arc-range "
+             "prefetch, the default at tau above 1, and vgc_kernel<2, false, false, false> the same without it "
+             "(tau 1: RMAT-22 and the tau1 rows); sum_u32_kernel is the "
              "mean-weight reduction behind the default bucket width."),
     "bfs_do": ("Kernel trace: direction-optimizing BFS suite (RMAT-24 and knn 10M/5, 4 sources each)",
                "bottom_up_kernel, collect_kernel and degsum_kernel belong to the direction-optimizing BFS; "

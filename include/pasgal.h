@@ -77,9 +77,10 @@ typedef struct pasgal_csr {
 #define PASGAL_FLAG_ASYNC 2u    /* do not synchronize the stream before returning (VGC mode only) */
 #define PASGAL_FLAG_PREFETCH 4u   /* VGC: local-queue entries carry their vertex's arc range, loaded while the
                                       relaxing atomic is in flight, instead of when the entry is expanded.
-                                      On by default for pasgal_bfs_ex, pasgal_reach_ex and pasgal_scc
-                                      (4-8% faster there); off by default for the batched and served
-                                      forms, where it measured neutral; pasgal_sssp ignores it */
+                                      On by default for pasgal_bfs_ex, pasgal_sssp, pasgal_reach_ex and
+                                      pasgal_scc when their tau is above 1 (1-8% faster there; at tau 1
+                                      no carried range is used); off by default for the batched and
+                                      served forms, where it measured neutral */
 #define PASGAL_FLAG_TEST_FIRST 8u  /* VGC: read a target's state before the atomic and skip the atomic when
                                       the relaxation cannot change it. On by default for pasgal_reach_ex
                                       with k >= 2 sources on graphs with m >= 4n and for pasgal_scc on
@@ -182,7 +183,7 @@ int pasgal_bfs_ex(const pasgal_csr *g, int32_t src, int32_t *dist_out, const pas
  * > 0 as given, 0 selects 8 times the mean arc weight (computed on the
  * device), < 0 no buckets (every tentative distance may be expanded at once).
  * PASGAL_MODE_PLAIN runs tau = 1 (one expansion per local search, VGC off) in
- * the same kernel; PASGAL_FLAG_PREFETCH is ignored. opts->tau <= 0 selects 1
+ * the same kernel. opts->tau <= 0 selects 1
  * when m > 8n and 1024 otherwise: on dense low-diameter graphs a deep local
  * search mostly lowers distances that a later search lowers again (RMAT-22:
  * 7-8 expansions per vertex and 44-48 ms at tau 1024, 3.8 and 21-23 ms at

@@ -103,7 +103,7 @@ def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0,
     None = the entry point's default (on for reach with several sources on
     graphs of mean degree >= 4 and for SCC on graphs of mean degree > 8),
     True / False = always / never read before the atomic. prefetch: None =
-    the entry point's default (on for single-source BFS, reach and SCC), True / False = always /
+    the entry point's default (on for single-source BFS, SSSP, reach and SCC), True / False = always /
     never carry arc ranges in the local queue."""
     o = L.Opts()
     L.load().pasgal_opts_default(ctypes.byref(o))

@@ -988,10 +988,9 @@ static const void *vgc_variant(bool pf, bool lane) {
 }
 
 const void *vgc_kernel_ptr(int kind, bool multi, bool pf, bool lane) {
-  if (kind == KIND_SSSP) {  // one query per launch, arc ranges loaded when expanded
-    if (multi || pf) return nullptr;
-    return lane ? (const void *)vgc_kernel<KIND_SSSP, false, false, true>
-                : (const void *)vgc_kernel<KIND_SSSP, false, false, false>;
+  if (kind == KIND_SSSP) {  // one query per launch
+    if (multi) return nullptr;
+    return vgc_variant<KIND_SSSP, false>(pf, lane);
   }
   if (kind == KIND_BFS) return multi ? vgc_variant<KIND_BFS, true>(pf, lane) : vgc_variant<KIND_BFS, false>(pf, lane);
   return multi ? vgc_variant<KIND_REACH, true>(pf, lane) : vgc_variant<KIND_REACH, false>(pf, lane);

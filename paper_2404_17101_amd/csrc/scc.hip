@@ -663,9 +663,10 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
   if (!opts || opts->tau <= 0) o.tau = (int64_t)g->m > 8 * (int64_t)g->n ? 1u : 1024u;
   // and a plain read before each OR there (most arcs offer bits already present)
   if ((int64_t)g->m > 8 * (int64_t)g->n && !(o.flags & PASGAL_FLAG_NO_TEST_FIRST)) o.test_first = true;
-  // arc ranges carried in the local queue, as for pasgal_reach_ex (4-5% faster on road and k-NN graphs)
-  if (!(o.flags & PASGAL_FLAG_NO_PREFETCH)) o.prefetch = true;
   if (o.mode == PASGAL_MODE_PLAIN) o.tau = 1;
+  // arc ranges carried in the local queue, as for pasgal_reach_ex (4-5% faster on road and k-NN
+  // graphs); at tau 1 no carried range is used
+  if (!(o.flags & PASGAL_FLAG_NO_PREFETCH) && o.tau > 1) o.prefetch = true;
   if (trim_rounds < 0) trim_rounds = 1;  // later passes run after every batch anyway
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;
