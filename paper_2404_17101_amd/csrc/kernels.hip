@@ -520,9 +520,9 @@ struct Wave {
       // step costs one pass.
       const uint32_t excl = incl - deg;
       arcs = total;
-      // single-query distance steps are thin (one pass); reach steps (deep LIFO
-      // searches) and multi-query steps are several passes wide
-      constexpr int RB = (MULTI || KIND == KIND_REACH) ? 4 : 1;
+      // single-query BFS steps are thin (one pass); reach steps (deep LIFO
+      // searches), SSSP steps and multi-query steps are several passes wide
+      constexpr int RB = (MULTI || KIND != KIND_BFS) ? 4 : 1;
       for (uint32_t j0 = 0; j0 < total; j0 += 64 * RB) {
         uint32_t w[RB], qo[RB], sbl[RB], lim[RB];
         int32_t arc[RB];
