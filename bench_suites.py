@@ -50,6 +50,49 @@ def _work(offsets, dist):
     return int(r.sum()), int(deg[r].sum())
 
 
+def _cpu_bfs(g, srcs, arcs_per_src=None, budget_s=15.0):
+    """The oracle's queue BFS on one host thread over a bounded sample of
+    the sources (the baseline column, never the target)."""
+    import oracle
+
+    used, arcs, done = 0.0, 0, 0
+    deg = np.diff(g.offsets).astype(np.int64)
+    for s in srcs:
+        if used > budget_s:
+            break
+        a = time.perf_counter()
+        d = oracle.bfs(g, int(s))
+        used += time.perf_counter() - a
+        arcs += int(deg[d >= 0].sum())
+        done += 1
+    return {"value": round(arcs / used / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"queue BFS from {done} of {len(srcs)} sources in {used:.1f} s"}
+
+
+def _bfs_certificate(g, s, d):
+    """d is the exact hop distance from s iff d(s) = 0, every arc out of a
+    reached vertex satisfies d(w) <= d(u) + 1 with w reached, and every other
+    reached vertex has an in-arc from a vertex one level closer."""
+    d = np.asarray(d, dtype=np.int64)
+    if d[s] != 0:
+        return False
+    u = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    w = g.targets.astype(np.int64)
+    ru = d[u] >= 0
+    if np.any(d[w[ru]] < 0) or np.any(d[w[ru]] > d[u[ru]] + 1):
+        return False
+    tight = np.zeros(g.n, dtype=bool)
+    sel = ru & (d[w] == d[u] + 1)
+    tight[w[sel]] = True
+    need = (d >= 0)
+    need[s] = False
+    return bool(np.all(tight[need]))
+
+
+def _frac(alg_bytes, ms):
+    return round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6) if ms > 0 else None
+
+
 def suite_c1(args, pg, gg, torch):
     g = gg.grid(256, 256)
     d = pg.DeviceGraph.from_graph(g)
@@ -74,7 +117,7 @@ def suite_c1(args, pg, gg, torch):
                       "kernel_ms": round(float(np.median(ks)), 4),
                       "roofline_frac": round(alg / (float(np.median(ks)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
     return {"suite": "c1", "workload": "grid 256x256, src 0, BFS", "n": g.n, "m": g.m, "reached_arcs": mr,
-            "results": out}
+            "alg_bytes": alg, "results": out, "cpu_baseline": _cpu_bfs(g, [0], mr)}
 
 
 def suite_c3(args, pg, gg, torch):
@@ -94,19 +137,30 @@ def suite_c3(args, pg, gg, torch):
     for i in range(64):
         credit += int(deg[((fw >> np.uint64(i)) & np.uint64(1)).astype(bool)].sum())
         credit += int(tdeg[((bw >> np.uint64(i)) & np.uint64(1)).astype(bool)].sum())
+    # algorithmic bytes: one 64-bit mask word per vertex and direction, 20 B
+    # per vertex some pivot reaches and 12 B per arc out of one
+    alg = (20 * int((fw != 0).sum()) + 12 * int(deg[fw != 0].sum()) +
+           20 * int((bw != 0).sum()) + 12 * int(tdeg[bw != 0].sum()))
+    piv_dev = pg.device_sources(pivots, "cuda")
     out = {}
     for label, kw in [("plain", dict(mode="plain")), ("tau256", dict(tau=256)), ("tau1024", dict(tau=1024)),
                       ("tau4096", dict(tau=4096))]:
-        ts = []
+        ts, ks, ex = [], [], []
         for _ in range(3):
             torch.cuda.synchronize()
             a = time.perf_counter()
-            pg.reach(d, pivots, **kw)
-            pg.reach(t, pivots, **kw)
+            _, sf = pg.reach(d, piv_dev, stats=True, **kw)
+            _, sb = pg.reach(t, piv_dev, stats=True, **kw)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - a)
+            ks.append(sf["kernel_ms"] + sb["kernel_ms"])
+            ex.append(sf["expansions"] + sb["expansions"])
         el = float(np.median(ts))
-        out[label] = {"ms_forward_plus_backward": round(el * 1e3, 3), "gteps": round(credit / el / 1e9, 3)}
+        kms = float(np.median(ks))
+        out[label] = {"ms_forward_plus_backward": round(el * 1e3, 3), "gteps": round(credit / el / 1e9, 3),
+                      "kernel_ms": round(kms, 3), "roofline_frac": _frac(alg, kms),
+                      "expansions_per_reached": round(float(np.median(ex)) / max(1, int((fw != 0).sum()) +
+                                                                               int((bw != 0).sum())), 3)}
     # forward and backward at the same time on two streams, each launch on
     # half of every compute unit; both results are checked against the above
     sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
@@ -125,9 +179,28 @@ def suite_c3(args, pg, gg, torch):
           np.array_equal(mb.cpu().numpy().view(np.uint64)[:, 0], bw))
     el = float(np.median(ts))
     out["tau1024_concurrent_half_device"] = {"ms_forward_plus_backward": round(el * 1e3, 3),
-                                             "gteps": round(credit / el / 1e9, 3), "matches_full_device": ok}
+                                             "gteps": round(credit / el / 1e9, 3), "matches_full_device": ok,
+                                             "roofline_frac": _frac(alg, el * 1e3)}
+    # the oracle's DFS reach on one host thread, a bounded sample of pivots
+    # in each direction; its rate in the same per-source TEPS credit
+    import oracle
+
+    gt = gg.Graph(t.offsets.cpu().numpy(), t.targets.cpu().numpy())
+    used, arcs, done = 0.0, 0, 0
+    for i in range(64):
+        if used > 15.0:
+            break
+        a = time.perf_counter()
+        rf = oracle.reach(g, [int(pivots[i])])[:, 0] != 0
+        rb = oracle.reach(gt, [int(pivots[i])])[:, 0] != 0
+        used += time.perf_counter() - a
+        arcs += int(deg[rf].sum()) + int(tdeg[rb].sum())
+        done += 1
+    cpu = {"value": round(arcs / used / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+           "sample": f"DFS reach forward and backward from {done} of the 64 pivots in {used:.1f} s"}
     return {"suite": "c3", "workload": "road grid 4096x4096 (seed 3), 64 pivots, forward + backward reach",
-            "n": g.n, "m": g.m, "transpose_ms": round(t_ms, 3), "teps_credit_arcs": credit, "results": out}
+            "n": g.n, "m": g.m, "transpose_ms": round(t_ms, 3), "teps_credit_arcs": credit,
+            "alg_bytes_forward_plus_backward": alg, "results": out, "cpu_baseline": cpu}
 
 
 def _cpu_baseline_scc(g):
@@ -153,7 +226,10 @@ def suite_scc(args, pg, gg, torch):
         t_ms = (time.perf_counter() - a) * 1e3
         cpu_s, exp = _cpu_baseline_scc(g)
         entry = {"graph": name, "n": g.n, "m": g.m, "transpose_ms": round(t_ms, 3),
-                 "cpu_baseline": {"tarjan_ms": round(cpu_s * 1e3, 1), "cores": 1, "kind": "oracle"}, "gpu": {}}
+                 "alg_bytes": 2 * (20 * g.n + 12 * g.m),
+                 "cpu_baseline": {"tarjan_ms": round(cpu_s * 1e3, 1), "cores": 1, "kind": "oracle",
+                                  "value": round(cpu_s * 1e3, 1), "unit": "ms per call",
+                                  "sample": "one whole call of Tarjan's algorithm"}, "gpu": {}}
         for label, kw in [("vgc", dict()), ("tau1024", dict(tau=1024)), ("tau1", dict(mode="plain")),
                           ("no_trim", dict(trim_rounds=0)),
                           ("no_split", dict(split=False))]:
@@ -166,7 +242,12 @@ def suite_scc(args, pg, gg, torch):
                 ts.append(time.perf_counter() - a)
             ok = bool(np.array_equal(comp.cpu().numpy(), exp))
             el = float(np.median(ts))
+            # one 64-bit mask word per vertex and one pass over the arcs in each
+            # direction: a lower bound of what the searches must move
+            scc_alg = 2 * (20 * g.n + 12 * g.m)
             entry["gpu"][label] = {"ms": round(el * 1e3, 2), "matches_oracle": ok,
+                                   "roofline_frac_reach": _frac(scc_alg, st["reach_ms"]),
+                                   "roofline_frac_call": _frac(scc_alg, el * 1e3),
                                    "speedup_vs_tarjan": round(cpu_s / el, 2),
                                    "reach_ms": round(st["reach_ms"], 2), "batches": st["batches"],
                                    "pivots": st["pivots"], "rounds": st["rounds"], "trimmed": st["trimmed"],
@@ -219,9 +300,14 @@ def suite_sssp(args, pg, gg, torch):
         cpu_s, exp = _cpu_baseline_sssp(g, w, s)
         reached = exp >= 0
         arcs = int(np.diff(g.offsets)[reached].sum())
+        # algorithmic bytes: BFS's 16 B per reached vertex and 8 B per arc of
+        # one, plus the 4-byte weight of every such arc
+        alg = 16 * int(reached.sum()) + 12 * arcs
         entry = {"graph": name, "n": g.n, "m": g.m, "source": s, "weights": "uniform [1, 1000], seed 2002",
-                 "reached_arcs": arcs,
-                 "cpu_baseline": {"dijkstra_ms": round(cpu_s * 1e3, 1), "cores": 1, "kind": "oracle"}, "gpu": {}}
+                 "reached_arcs": arcs, "alg_bytes": alg,
+                 "cpu_baseline": {"dijkstra_ms": round(cpu_s * 1e3, 1), "cores": 1, "kind": "oracle",
+                                  "value": round(arcs / cpu_s / 1e9, 5), "unit": "GTEPS",
+                                  "sample": "Dijkstra from the suite's source"}, "gpu": {}}
         # "vgc" is the library default (tau by mean degree: 1 on RMAT-22, 1024 on the others)
         for label, kw in [("vgc", dict()), ("tau1024", dict(tau=1024)), ("tau1", dict(mode="plain"))]:
             ms, (out, st) = _median_ms(lambda: pg.sssp(d, wd, s, stats=True, **kw))
@@ -231,7 +317,8 @@ def suite_sssp(args, pg, gg, torch):
                                    "matches_oracle": bool(np.array_equal(got, exp)),
                                    "speedup_vs_dijkstra": round(cpu_s * 1e3 / ms, 1), "rounds": st["rounds"],
                                    "expansions_per_reached": round(st["expansions"] / max(1, int(reached.sum())), 3),
-                                   "gteps": round(arcs / (ms * 1e-3) / 1e9, 3)}
+                                   "gteps": round(arcs / (ms * 1e-3) / 1e9, 3),
+                                   "roofline_frac": _frac(alg, st["kernel_ms"])}
             _log(f"sssp {name} {label}: {entry['gpu'][label]}")
         res.append(entry)
         del d, wd
@@ -256,8 +343,11 @@ def suite_bfs_do(args, pg, gg, torch):
         exp = oracle.bfs(g, srcs[0])
         cpu_ms = (time.perf_counter() - t0) * 1e3
         arcs = int(np.diff(g.offsets)[exp >= 0].sum())
-        entry = {"graph": name, "n": g.n, "m": g.m, "reached_arcs_src0": arcs,
-                 "cpu_baseline": {"bfs_ms_src0": round(cpu_ms, 1), "cores": 1, "kind": "oracle"}, "gpu": {}}
+        alg = 16 * int((exp >= 0).sum()) + 8 * arcs
+        entry = {"graph": name, "n": g.n, "m": g.m, "reached_arcs_src0": arcs, "alg_bytes_src0": alg,
+                 "cpu_baseline": {"bfs_ms_src0": round(cpu_ms, 1), "cores": 1, "kind": "oracle",
+                                  "value": round(arcs / (cpu_ms * 1e-3) / 1e9, 5), "unit": "GTEPS",
+                                  "sample": "queue BFS from the first source"}, "gpu": {}}
         for label, fn in [("vgc", lambda s: pg.bfs(d, s)), ("plain", lambda s: pg.bfs(d, s, mode="plain")),
                           ("direction_optimizing", lambda s: pg.bfs_do(d, s, transpose=t)),
                           ("direction_optimizing_alpha14", lambda s: pg.bfs_do(d, s, transpose=t, alpha=14))]:
@@ -267,7 +357,8 @@ def suite_bfs_do(args, pg, gg, torch):
                 ms, _ = _median_ms(lambda: fn(s), reps=1)
                 ts.append(ms)
             entry["gpu"][label] = {"ms_median_of_4_sources": round(float(np.median(ts)), 2), "matches_oracle": ok,
-                                   "gteps_src0_arcs": round(arcs / (float(np.median(ts)) * 1e-3) / 1e9, 3)}
+                                   "gteps_src0_arcs": round(arcs / (float(np.median(ts)) * 1e-3) / 1e9, 3),
+                                   "roofline_frac_src0_bytes": _frac(alg, float(np.median(ts)))}
             _log(f"bfs_do {name} {label}: {entry['gpu'][label]}")
         res.append(entry)
         del d, t
@@ -306,6 +397,31 @@ def suite_c4(args, pg, gg, torch):
         r = got[qo[j]:qo[j] + graphs[gi].n] >= 0
         arcs += int(np.diff(graphs[gi].offsets)[r].sum())
         nverts += int(r.sum())
+    # every query of the autotuned launch: grids by the closed form
+    # (Manhattan distance), 5-NN graphs by the oracle on a bounded sample
+    # (timed: the CPU baseline) and by the BFS certificate otherwise
+    import oracle
+
+    grids_ok, cert_ok, exact_ok, cpu_s, cpu_arcs, cpu_n = True, True, True, 0.0, 0, 0
+    for j in range(nq):
+        kind, g = rec[qg[j]], graphs[qg[j]]
+        out = got[qo[j]:qo[j] + g.n]
+        if kind[0] == "grid":
+            side = kind[1]
+            rr, cc = np.divmod(np.arange(g.n), side)
+            r0, c0 = divmod(qs[j], side)
+            grids_ok &= bool(np.array_equal(out, np.abs(rr - r0) + np.abs(cc - c0)))
+        elif cpu_s < 15.0 and j % 4 == 0:
+            a = time.perf_counter()
+            exp = oracle.bfs(g, qs[j])
+            cpu_s += time.perf_counter() - a
+            cpu_arcs += int(np.diff(g.offsets)[exp >= 0].sum())
+            cpu_n += 1
+            exact_ok &= bool(np.array_equal(out, exp))
+        else:
+            cert_ok &= _bfs_certificate(g, qs[j], out)
+    checks = {"grids_closed_form": grids_ok, "knn_oracle_sample": exact_ok, "knn_certificate_rest": cert_ok,
+              "knn_oracle_queries": cpu_n}
     ts = []
     for _ in range(3):
         st = b.run()
@@ -331,6 +447,11 @@ def suite_c4(args, pg, gg, torch):
     return {"suite": "c4", "workload": "256 graphs (128 grids 64..2048, 128 5-NN 1e4..1e6 points, seed 4), "
                                        "1024 BFS queries (seed 1004)",
             "n": packed.n, "m": packed.m, "queries": nq, "autotune_s": round(tune_s, 2), "chosen": cfg,
+            "alg_bytes": alg, "checks": checks,
+            "cpu_baseline": {"value": round(cpu_arcs / cpu_s / 1e9, 5) if cpu_s else None, "unit": "GTEPS",
+                             "cores": 1, "kind": "oracle",
+                             "queries_per_s": round(cpu_n / cpu_s, 2) if cpu_s else None,
+                             "sample": f"queue BFS of {cpu_n} 5-NN queries (every 4th) in {cpu_s:.1f} s"},
             "batched": {"ms": round(batched_ms, 3), "queries_per_s": round(nq / batched_ms * 1e3, 1),
                         "gteps": round(arcs / batched_ms / 1e6, 3),
                         "roofline_frac": round(alg / (batched_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},

@@ -74,7 +74,11 @@ typedef struct pasgal_csr {
 #define PASGAL_MODE_PLAIN 1 /* level-synchronous frontier rounds, one launch per round (Algorithm 1, VGC off) */
 
 #define PASGAL_FLAG_VALIDATE 1u /* check the CSR on the device first (O(n+m)) */
-#define PASGAL_FLAG_ASYNC 2u    /* do not synchronize the stream before returning (VGC mode only) */
+#define PASGAL_FLAG_ASYNC 2u    /* do not synchronize the stream before returning (VGC mode only). The
+                                   launch's timeout status is read later: by pasgal_wait on the same
+                                   stream, or else by the next call on that stream, which then returns
+                                   PASGAL_ETIMEOUT (and does nothing else) if the asynchronous launch
+                                   timed out */
 #define PASGAL_FLAG_PREFETCH 4u   /* VGC: local-queue entries carry their vertex's arc range, loaded while the
                                       relaxing atomic is in flight, instead of when the entry is expanded.
                                       On by default for pasgal_bfs_ex, pasgal_sssp, pasgal_reach_ex and
@@ -89,9 +93,6 @@ typedef struct pasgal_csr {
 #define PASGAL_FLAG_NO_TEST_FIRST 64u /* VGC: never read before the atomic (overrides those defaults) */
 #define PASGAL_FLAG_NO_PREFETCH 128u  /* VGC: never carry arc ranges in the local queue (overrides those
                                          defaults and PASGAL_FLAG_PREFETCH) */
-#define PASGAL_FLAG_ROW_PER_LANE 16u /* VGC: scan rows of <= 8 arcs lane by lane instead of dealing every
-                                        vertex's arcs out across the wavefront (default: consecutive lanes take
-                                        consecutive arcs, so one memory instruction touches few cache lines) */
 #define PASGAL_FLAG_HALF_DEVICE 32u /* VGC: size the persistent launch to half of every compute unit (LDS and
                                        wave slots for 2 x blocks_per_cu workgroups per CU; PASGAL_EINVAL if
                                        that many do not fit) and launch it as an ordinary kernel, so that a
@@ -159,9 +160,26 @@ const char *pasgal_strerror(int code);
 int pasgal_last_hip_error(void); /* hipError_t of the last EHIP in this thread */
 int pasgal_version(void);
 
-/* BFS from src. dist_out[v] = hop distance from src along out-arcs, or -1 if
- * v is unreachable. dist_out: device, n int32, written entirely. Synchronous
- * on the null stream. */
+/* Waits for the work the library enqueued on `stream` (a hipStream_t; NULL =
+ * the null stream) and reports the status of asynchronous launches there:
+ * PASGAL_ETIMEOUT if one of them ended because a bounded device-side wait
+ * expired (its results are invalid), else PASGAL_OK. */
+int pasgal_wait(void *stream);
+
+/* Releases everything the library owns outside batches and servers: the
+ * per-stream workspaces (frontier buffers, bitmaps, control blocks, pinned
+ * staging buffers) and their events, on every device, after waiting for each
+ * device. Destroy batches and servers first; call from one thread, with no
+ * other call in flight. The library stays usable: workspaces are re-created
+ * on demand. The Python binding calls it at interpreter exit. */
+void pasgal_shutdown(void);
+
+/* BFS from src (Parallel BFS paragraph of the Other Algorithms section: hop
+ * distances by the frontier framework of Algorithm 1, here with VGC local
+ * searches). dist_out[v] = hop distance from src along out-arcs, or -1 if v
+ * is unreachable. dist_out: device, n int32, written entirely. Synchronous on
+ * the null stream. PASGAL_EINVAL (nothing written): null pointer, n <= 0,
+ * m < 0, src outside [0, n). */
 int pasgal_bfs(const pasgal_csr *g, int32_t src, int32_t *dist_out);
 /* Same with options and optional counters (stats may be NULL). Runs on
  * opts->stream; returns after the stream is synchronized unless
@@ -210,18 +228,29 @@ int pasgal_sssp(const pasgal_csr *g, const uint32_t *weights, int32_t src, uint3
 int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t src, int32_t *dist_out, int32_t alpha,
                   int32_t beta, const pasgal_opts *opts, pasgal_stats *stats);
 
-/* Multi-source reachability. sources: HOST array of k vertex ids (repeats
- * allowed), k >= 1. label_out: device, n * W uint64 with W = ceil(k/64);
- * bit (i % 64) of label_out[v*W + i/64] is set iff sources[i] reaches v
- * (v = sources[i] included). Written entirely. */
+/* Multi-source reachability (Parallel SCC section: a reachability search from
+ * a vertex finds every vertex it reaches; the sources form the initial
+ * frontier F0 of Algorithm 1). sources: DEVICE array of k int32 vertex ids
+ * (repeats allowed), k >= 1; the call reads it on its stream, after the
+ * stream's earlier work, with one small device-to-host copy and a wait, and
+ * checks it before anything is written. label_out: device, n * W uint64 with
+ * W = ceil(k/64); bit (i % 64) of label_out[v*W + i/64] is set iff
+ * sources[i] reaches v (v = sources[i] included). Written entirely.
+ * PASGAL_EINVAL (nothing written): null pointer, k <= 0, a source outside
+ * [0, n). Synchronous on the null stream. */
 int pasgal_reach(const pasgal_csr *g, const int32_t *sources, int32_t k, uint64_t *label_out);
+/* Same with options and optional counters, on opts->stream; with k > 64 the
+ * mask words are computed one after the other (PASGAL_FLAG_ASYNC is then
+ * rejected). */
 int pasgal_reach_ex(const pasgal_csr *g, const int32_t *sources, int32_t k, uint64_t *label_out,
                     const pasgal_opts *opts, pasgal_stats *stats);
 
-/* G^T (needed for backward reachability): t_offsets device n+1, t_targets
- * device m. Row v of G^T lists every u with an arc u->v, once per arc; the
- * order inside a row is unspecified. Synchronous on opts->stream (opts may be
- * NULL). */
+/* G^T (Parallel SCC section: the backward search from a pivot follows
+ * in-arcs, i.e. it is a forward search on G^T). t_offsets device n+1,
+ * t_targets device m, owned by the caller. Row v of G^T lists every u with an
+ * arc u->v, once per arc; the order inside a row is unspecified. Synchronous
+ * on opts->stream (opts may be NULL). PASGAL_EINVAL (nothing written): null
+ * pointer, n <= 0, m < 0. */
 int pasgal_transpose(const pasgal_csr *g, int32_t *t_offsets, int32_t *t_targets, const pasgal_opts *opts);
 
 /* Device-side CSR check (monotone offsets, offsets[0]=0, offsets[n]=m,

@@ -21,8 +21,8 @@ import numpy as np
 
 from . import _lib as L
 
-__all__ = ["DeviceGraph", "PasgalError", "bfs", "bfs_do", "sssp", "reach", "transpose", "validate", "scc",
-           "Batch", "Server", "load"]
+__all__ = ["DeviceGraph", "PasgalError", "bfs", "bfs_do", "sssp", "reach", "device_sources", "wait", "transpose",
+           "validate", "scc", "Batch", "Server", "load"]
 
 load = L.load
 
@@ -91,7 +91,7 @@ def _stream_ptr(stream) -> int:
 
 def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
           stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=None, test_first=None,
-          spread_arcs=True, heavy_arcs=0, filter_slots=0, chunks_per_wave=0, half_device=False) -> L.Opts:
+          heavy_arcs=0, filter_slots=0, chunks_per_wave=0, half_device=False) -> L.Opts:
     """tau: local-search budget (0 = the entry point's default: 1024, SSSP and
     SCC on graphs of mean out-degree above 8: 1). window: BFS distance window per
     round (0 or negative = none).
@@ -115,7 +115,7 @@ def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0,
     o.flags = ((L.FLAG_VALIDATE if validate else 0) | (L.FLAG_ASYNC if asynchronous else 0) |
                (0 if prefetch is None else (L.FLAG_PREFETCH if prefetch else L.FLAG_NO_PREFETCH)) |
                (0 if test_first is None else (L.FLAG_TEST_FIRST if test_first else L.FLAG_NO_TEST_FIRST)) |
-               (0 if spread_arcs else L.FLAG_ROW_PER_LANE) | (L.FLAG_HALF_DEVICE if half_device else 0))
+               (L.FLAG_HALF_DEVICE if half_device else 0))
     o.timeout_ms = int(timeout_ms)
     o.stream = _stream_ptr(stream)
     o.window = int(window) if int(window) > 0 else -1
@@ -179,21 +179,43 @@ def sssp(g: DeviceGraph, weights, src: int, dist_out=None, stats: bool = False, 
     return (dist_out, st.as_dict()) if stats else dist_out
 
 
+def device_sources(sources, device, stream=None):
+    """The int32 device array of source ids that pasgal_reach takes: a CUDA
+    tensor is used as it is (converted to contiguous int32 if needed), host
+    data is copied on `stream` (default: the current stream), so that the
+    library, reading it on that stream, sees the copy."""
+    torch = _torch()
+    if isinstance(sources, torch.Tensor) and sources.is_cuda:
+        return sources.to(torch.int32).contiguous().view(-1)
+    src = torch.from_numpy(np.ascontiguousarray(np.asarray(sources, dtype=np.int32).ravel()))
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+        return src.to(device)
+
+
 def reach(g: DeviceGraph, sources, label_out=None, stats: bool = False, **opts):
     """Reachability masks: int64 tensor [n, ceil(k/64)]; bit i%64 of word i/64
-    of row v is set iff sources[i] reaches v."""
+    of row v is set iff sources[i] reaches v. sources: a CUDA int32 tensor
+    (passed to the library as it is) or host ids (copied to the device on the
+    call's stream)."""
     torch = _torch()
-    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).ravel())
-    k = int(src.size)
+    src = device_sources(sources, g.offsets.device, opts.get("stream"))
+    k = int(src.numel())
     words = max(1, (k + 63) // 64)
     if label_out is None:
         label_out = torch.empty((g.n, words), dtype=torch.int64, device=g.offsets.device)
     csr = g.csr()
     o = _opts(**opts)
     st = L.Stats()
-    _check(L.load().pasgal_reach_ex(ctypes.byref(csr), src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k,
+    _check(L.load().pasgal_reach_ex(ctypes.byref(csr), ctypes.cast(src.data_ptr(), ctypes.POINTER(ctypes.c_int32)), k,
                                     label_out.data_ptr(), ctypes.byref(o), ctypes.byref(st)), "pasgal_reach")
     return (label_out, st.as_dict()) if stats else label_out
+
+
+def wait(stream=None):
+    """pasgal_wait: wait for the library's work on the stream (default: the
+    current one); raises PasgalError (ETIMEOUT) if an asynchronous launch there
+    timed out."""
+    _check(L.load().pasgal_wait(_stream_ptr(stream)), "pasgal_wait")
 
 
 def transpose(g: DeviceGraph, **opts) -> DeviceGraph:

@@ -1,6 +1,7 @@
 """ctypes declarations of libpasgal.so (mirrors include/pasgal.h)."""
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -13,15 +14,15 @@ ERRORS = {
     -8: "ENOTFOUND", -9: "EINTERNAL",
 }
 MODE_VGC, MODE_PLAIN = 0, 1
-FLAG_VALIDATE, FLAG_ASYNC, FLAG_PREFETCH, FLAG_TEST_FIRST, FLAG_ROW_PER_LANE, FLAG_HALF_DEVICE, FLAG_NO_TEST_FIRST = \
-    1, 2, 4, 8, 16, 32, 64
+FLAG_VALIDATE, FLAG_ASYNC, FLAG_PREFETCH, FLAG_TEST_FIRST, FLAG_HALF_DEVICE, FLAG_NO_TEST_FIRST = 1, 2, 4, 8, 32, 64
 FLAG_NO_PREFETCH = 128
 BATCH_AUTOTUNE = 1
 REQ_BFS, REQ_REACH = 0, 1
 
 # every function include/pasgal.h declares
 EXPORTS = [
-    "pasgal_opts_default", "pasgal_strerror", "pasgal_last_hip_error", "pasgal_version",
+    "pasgal_opts_default", "pasgal_strerror", "pasgal_last_hip_error", "pasgal_version", "pasgal_wait",
+    "pasgal_shutdown",
     "pasgal_bfs", "pasgal_bfs_ex", "pasgal_bfs_do", "pasgal_sssp", "pasgal_reach", "pasgal_reach_ex", "pasgal_transpose", "pasgal_validate",
     "pasgal_probe_latency",
     "pasgal_scc", "pasgal_batch_create", "pasgal_batch_run", "pasgal_batch_config", "pasgal_batch_destroy",
@@ -114,6 +115,10 @@ def load(path: str = LIB_PATH):
     lib.pasgal_strerror.restype = ctypes.c_char_p
     lib.pasgal_last_hip_error.restype = c_int
     lib.pasgal_version.restype = c_int
+    lib.pasgal_wait.argtypes = [vp]
+    lib.pasgal_wait.restype = c_int
+    lib.pasgal_shutdown.argtypes = []
+    lib.pasgal_shutdown.restype = None
     lib.pasgal_bfs.argtypes = [P(Csr), i32, vp]
     lib.pasgal_bfs_ex.argtypes = [P(Csr), i32, vp, P(Opts), P(Stats)]
     lib.pasgal_bfs_do.argtypes = [P(Csr), P(Csr), i32, vp, i32, i32, P(Opts), P(Stats)]
@@ -144,4 +149,6 @@ def load(path: str = LIB_PATH):
               "pasgal_server_drain", "pasgal_server_load"):
         getattr(lib, f).restype = c_int
     _lib = lib
+    # release the library's workspaces before the HIP runtime tears down
+    atexit.register(lib.pasgal_shutdown)
     return lib

@@ -91,7 +91,6 @@ struct pasgal_batch {
     args.chunks_per_wave = o.cpw;
     args.window = o.window;
     args.test_first = o.test_first ? 1u : 0u;
-    args.lane_arcs = o.lane_arcs;
     // filter keys are 32-bit state indices: exact only below 2^32 values
     args.filt = dist_len < (int64_t(1) << 32) ? lg.filt : 0u;
     args.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;

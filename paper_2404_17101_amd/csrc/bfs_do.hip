@@ -142,6 +142,7 @@ extern "C" int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t 
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;
   std::lock_guard<std::mutex> lk(w->mu);
+  if (int arc = collect_async(*w)) return arc;
   hipStream_t s = o.stream;
   int rc;
   if (o.flags & PASGAL_FLAG_VALIDATE) {

@@ -50,7 +50,10 @@ struct Workspace {
   hipStream_t stream = nullptr;
   DBuf ctl, fv[2], fq[2], fval[2], dirty, qi, qword, seeds, pf[2], stamp, tmp_state, tscratch, plain_src, aux;
   uint32_t cap = 0;
-  HBuf h_ctl, h_stage, h_aux;
+  HBuf h_ctl, h_stage, h_aux, h_src;
+  // An asynchronous launch (PASGAL_FLAG_ASYNC) returned before its control
+  // block was read: the next call on this stream, or pasgal_wait, reads it.
+  bool async_pending = false;
   SliceBufs slices;
   hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;
   void *ext = nullptr;                   // buffers of a larger driver (SCC), freed by ext_free
@@ -71,7 +74,6 @@ struct Opts {
   uint32_t min_chunk = 1;
   bool prefetch = false;
   bool test_first = false;
-  uint32_t lane_arcs = 0;
   uint32_t heavy = 512;  // 0 = never cut heavy rows
   uint32_t filt = 256;   // LDS filter entries per wavefront wanted (0 = none)
   uint32_t cpw = 1;      // frontier chunks per wavefront and round
@@ -106,6 +108,11 @@ uint64_t default_cap(int64_t requested, uint64_t nvert);
 int ensure_frontier(Workspace &w, uint64_t cap, bool multi);
 void fill_stats_from_ctl(const Ctl &c, pasgal_stats *st, bool add);
 int validate_csr_device(Workspace &w, const pasgal_csr *g, hipStream_t s);
+// Under w.mu, first thing in every entry point that uses a workspace: when an
+// asynchronous launch on this stream has not been checked yet, wait for it
+// and return PASGAL_ETIMEOUT if its bounded waits expired (its results are
+// then invalid), else PASGAL_OK.
+int collect_async(Workspace &w);
 
 hipError_t launch_strided_u64(unsigned long long *dst, int stride, int word, const unsigned long long *src,
                               uint64_t n, hipStream_t s);

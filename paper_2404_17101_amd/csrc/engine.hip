@@ -110,6 +110,7 @@ Workspace::~Workspace() {
   free_hbuf(h_ctl);
   free_hbuf(h_stage);
   free_hbuf(h_aux);
+  free_hbuf(h_src);
   if (ext_free) ext_free(ext);
   if (ev0) hipEventDestroy(ev0);
   if (evk) hipEventDestroy(evk);
@@ -138,6 +139,36 @@ Workspace *workspace_for(hipStream_t s) {
   return w;
 }
 
+int collect_async(Workspace &w) {
+  if (!w.async_pending) return PASGAL_OK;
+  hipError_t e = hipStreamSynchronize(w.stream);
+  if (e != hipSuccess) return hip_fail(e);
+  w.async_pending = false;
+  return ((const Ctl *)w.h_ctl.p)->abort ? PASGAL_ETIMEOUT : PASGAL_OK;
+}
+
+// Every workspace, on every device (pasgal_shutdown).
+static void destroy_workspaces() {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  int cur = 0;
+  hipGetDevice(&cur);
+  int last = -1;
+  for (auto &kv : g_ws) {
+    Workspace *w = kv.second;
+    { std::lock_guard<std::mutex> wl(w->mu); }  // a call still inside it finishes first
+    if (kv.first.first != last) {
+      // kernels still running may use the buffers: wait for the device
+      hipSetDevice(kv.first.first);
+      hipDeviceSynchronize();
+      last = kv.first.first;
+    }
+    delete w;
+  }
+  g_ws.clear();
+  hipSetDevice(cur);
+  (void)hipGetLastError();
+}
+
 Opts resolve_opts(const pasgal_opts *o) {
   Opts r;
   pasgal_opts d;
@@ -155,7 +186,6 @@ Opts resolve_opts(const pasgal_opts *o) {
   r.min_chunk = o->min_chunk > 0 ? (uint32_t)std::min(o->min_chunk, 64) : 1u;
   r.prefetch = (o->flags & PASGAL_FLAG_PREFETCH) != 0 && !(o->flags & PASGAL_FLAG_NO_PREFETCH);
   r.test_first = (o->flags & PASGAL_FLAG_TEST_FIRST) != 0;  // entry points may turn it on by default
-  r.lane_arcs = (o->flags & PASGAL_FLAG_ROW_PER_LANE) ? 8u : 0u;
   r.heavy = o->heavy_arcs > 0 ? (uint32_t)o->heavy_arcs : (o->heavy_arcs == 0 ? 512u : 0u);
   r.cpw = o->chunks_per_wave > 0 ? (uint32_t)std::min(o->chunks_per_wave, 64) : 1u;
   r.half = (o->flags & PASGAL_FLAG_HALF_DEVICE) != 0;
@@ -251,7 +281,7 @@ int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   lg.block = o.wg;
   lg.pf = pf;
   lg.lds = vgc_lds_bytes(kind, multi, pf, waves, Q, S, F);
-  const void *fn = vgc_kernel_ptr(kind, multi, pf, o.lane_arcs != 0);
+  const void *fn = vgc_kernel_ptr(kind, multi, pf, o.test_first);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lg.lds);
   if (e != hipSuccess) {
     hipGetLastError();
@@ -375,7 +405,6 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   a.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
   a.round_base = 0;
   a.test_first = o.test_first ? 1u : 0u;
-  a.lane_arcs = o.lane_arcs;
   a.filt = lg.filt;  // single query: keys are vertex ids
   a.ctl = (Ctl *)w.ctl.p;
   w.slices.apply(a, o.heavy, hcap, false);
@@ -396,7 +425,10 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   if ((e = hipEventRecord(w.ev1, s)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpyAsync(w.h_ctl.p, w.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(e);
-  if (o.flags & PASGAL_FLAG_ASYNC) return PASGAL_OK;
+  if (o.flags & PASGAL_FLAG_ASYNC) {
+    w.async_pending = true;
+    return PASGAL_OK;
+  }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
   const Ctl &c = *(const Ctl *)w.h_ctl.p;
   if (c.abort) return PASGAL_ETIMEOUT;
@@ -555,6 +587,18 @@ const char *pasgal_strerror(int code) {
 int pasgal_last_hip_error(void) { return g_last_hip; }
 int pasgal_version(void) { return PASGAL_VERSION; }
 
+void pasgal_shutdown(void) { destroy_workspaces(); }
+
+int pasgal_wait(void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  Workspace *w = workspace_for(s);
+  if (!w) return PASGAL_ENOMEM;
+  std::lock_guard<std::mutex> lk(w->mu);
+  if (int rc = collect_async(*w)) return rc;
+  hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? PASGAL_OK : hip_fail(e);
+}
+
 int pasgal_bfs_ex(const pasgal_csr *g, int32_t src, int32_t *dist_out, const pasgal_opts *opts, pasgal_stats *stats) {
   if (!csr_valid(g) || !dist_out || src < 0 || src >= g->n || !opts_valid(opts)) return PASGAL_EINVAL;
   Opts o = resolve_opts(opts);
@@ -565,6 +609,7 @@ int pasgal_bfs_ex(const pasgal_csr *g, int32_t src, int32_t *dist_out, const pas
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;
   std::lock_guard<std::mutex> lk(w->mu);
+  if (int arc = collect_async(*w)) return arc;
   int rc;
   if (o.flags & PASGAL_FLAG_VALIDATE) {
     if ((rc = validate_csr_device(*w, g, o.stream))) return rc;
@@ -590,6 +635,7 @@ int pasgal_sssp(const pasgal_csr *g, const uint32_t *weights, int32_t src, uint3
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;
   std::lock_guard<std::mutex> lk(w->mu);
+  if (int arc = collect_async(*w)) return arc;
   int rc;
   hipError_t e;
   if (o.flags & PASGAL_FLAG_VALIDATE) {
@@ -621,8 +667,6 @@ int pasgal_bfs(const pasgal_csr *g, int32_t src, int32_t *dist_out) {
 int pasgal_reach_ex(const pasgal_csr *g, const int32_t *sources, int32_t k, uint64_t *label_out,
                     const pasgal_opts *opts, pasgal_stats *stats) {
   if (!csr_valid(g) || !label_out || !sources || k <= 0 || !opts_valid(opts)) return PASGAL_EINVAL;
-  for (int32_t i = 0; i < k; i++)
-    if (sources[i] < 0 || sources[i] >= g->n) return PASGAL_EINVAL;
   Opts o = resolve_opts(opts);
   if (o.mode == PASGAL_MODE_PLAIN && (o.flags & PASGAL_FLAG_ASYNC)) return PASGAL_EINVAL;
   // several sources on a graph of mean out-degree >= 4: a vertex gets most
@@ -638,7 +682,17 @@ int pasgal_reach_ex(const pasgal_csr *g, const int32_t *sources, int32_t k, uint
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;
   std::lock_guard<std::mutex> lk(w->mu);
+  if (int arc = collect_async(*w)) return arc;
   int rc;
+  // the sources are a device array: read them (after the stream's earlier
+  // work, which may produce them) and check them before anything is written
+  if ((rc = grow_host(w->h_src, 4 * (size_t)k))) return rc;
+  hipError_t es = hipMemcpyAsync(w->h_src.p, sources, 4 * (size_t)k, hipMemcpyDeviceToHost, o.stream);
+  if (es == hipSuccess) es = hipStreamSynchronize(o.stream);
+  if (es != hipSuccess) return hip_fail(es);
+  sources = (const int32_t *)w->h_src.p;
+  for (int32_t i = 0; i < k; i++)
+    if (sources[i] < 0 || sources[i] >= g->n) return PASGAL_EINVAL;
   if (o.flags & PASGAL_FLAG_VALIDATE) {
     if ((rc = validate_csr_device(*w, g, o.stream))) return rc;
   }
@@ -681,6 +735,7 @@ int pasgal_transpose(const pasgal_csr *g, int32_t *t_offsets, int32_t *t_targets
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;
   std::lock_guard<std::mutex> lk(w->mu);
+  if (int arc = collect_async(*w)) return arc;
   int rc;
   if (o.flags & PASGAL_FLAG_VALIDATE) {
     if ((rc = validate_csr_device(*w, g, o.stream))) return rc;
@@ -699,6 +754,7 @@ int pasgal_validate(const pasgal_csr *g, const pasgal_opts *opts) {
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;
   std::lock_guard<std::mutex> lk(w->mu);
+  if (int arc = collect_async(*w)) return arc;
   return validate_csr_device(*w, g, o.stream);
 }
 

@@ -97,12 +97,10 @@ struct VgcArgs {
   uint32_t window;        // BFS / SSSP: round r of query q expands only distances below
                           // (round_base + r + 1 - qi[q].r0) * window; 0 = no limit
   uint32_t round_base;    // absolute number of the launch's first round
-  uint32_t test_first;    // plain load before each atomic to skip relaxations that cannot succeed
+  uint32_t test_first;    // plain load before each atomic to skip relaxations that cannot succeed (selects
+                          // the kernel variant)
   uint32_t filt;          // BFS / SSSP: entries of each wavefront's LDS filter of values it wrote (power of
                           // two; 0 = off). Keys are 32-bit state indices, so the state must hold < 2^32 values
-  uint32_t lane_arcs;     // rows of at most this many arcs (<= 8) are scanned lane by lane; longer rows, or
-                          // every row when 0, are dealt out across the wavefront (consecutive lanes take
-                          // consecutive arcs)
   long long timeout_ticks;
   Ctl *ctl;
   // Heavy rows: an expanded vertex with more than `heavy` out-arcs (0 = never)
@@ -125,13 +123,14 @@ struct SeedEnt {
 
 // LDS of a persistent launch: per wavefront a ring (local queue) of ring_cap
 // entries and a staging buffer of stage_cap entries ({v, val[, q]} each, SoA),
-// 64 words of scan scratch and a filter of filt 8-byte entries, 16-byte
+// 64 words of arc-owner marks, 64 per-step entry records (16 bytes, plus 8
+// with several queries) and a filter of filt 8-byte entries, 16-byte
 // aligned.
 __host__ __device__ inline size_t vgc_lds_bytes(int kind, bool multi, bool pf, int waves, uint32_t ring_cap,
                                                 uint32_t stage_cap, uint32_t filt) {
   const size_t vsz = (kind == KIND_REACH) ? 8 : 4;
   size_t per = (size_t)(ring_cap + stage_cap) * (vsz + 4 + (multi ? 4 : 0)) + (pf ? 8 * (size_t)ring_cap : 0) +
-               64 * 4 + 8 * (size_t)filt;
+               64 * 4 + 64 * (multi ? 24 : 16) + 8 * (size_t)filt;
   per = (per + 15) & ~(size_t)15;
   return per * (size_t)waves;
 }
@@ -147,8 +146,8 @@ hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_
                        uint32_t start_ovf, hipStream_t s);
 hipError_t launch_vgc(int kind, bool multi, bool pf, const VgcArgs &a, int grid, int block, size_t lds,
                       bool cooperative, hipStream_t s);
-// lane: the row-per-lane variant (VgcArgs::lane_arcs != 0)
-const void *vgc_kernel_ptr(int kind, bool multi, bool pf, bool lane);
+// tf: the test-first variant (VgcArgs::test_first != 0)
+const void *vgc_kernel_ptr(int kind, bool multi, bool pf, bool tf);
 
 // Plain level-synchronous rounds (one launch per BFS level).
 hipError_t launch_plain_bfs_level(const int32_t *off, const int32_t *tgt, uint32_t *dist, const uint32_t *cur,

@@ -51,6 +51,10 @@ struct QLite {
   uint32_t r0, pad;
 };
 constexpr int QLITE = 64;
+// Typed as LDS so that a lookup is a ds_read: through a generic pointer the
+// compiler merges it with the global fallback into a flat load, whose wait
+// also waits for every relaxation in flight.
+typedef __attribute__((address_space(3))) QLite LdsQLite;
 
 // Grid barrier for a persistent launch whose workgroups are all resident.
 // Fence-free: callers keep cross-workgroup data in agent-scope atomics.
@@ -92,13 +96,20 @@ struct ValT<KIND_REACH> { using T = unsigned long long; };
 template <>
 struct ValT<KIND_SSSP> { using T = uint32_t; };
 
-template <int KIND, bool MULTI, bool PF, bool LANE>
+template <int KIND, bool MULTI, bool PF, bool TF>
 struct Wave {
   using Val = typename ValT<KIND>::T;
   static constexpr bool FIFO = (KIND != KIND_REACH);  // distances: local BFS order; reach: LIFO (deep first)
   static constexpr bool DIST = (KIND != KIND_REACH);  // BFS and SSSP: uint32 distances lowered by atomicMin
   // PF: local-queue entries carry their vertex's arc range, loaded while the
   // relaxing atomic is in flight, so expanding them starts at the targets.
+  // TF: a plain load of the target's state before the atomic rules out
+  // relaxations that cannot change it (test-first).
+  // Most passes of up to this many 64-arc batches are issued together
+  // (target loads, then atomics, then pushes), so that a lane has several
+  // relaxations in flight: single-query BFS steps are thin (one pass); reach
+  // steps (deep LIFO searches), SSSP steps and multi-query steps are wider.
+  static constexpr int RB = (MULTI || KIND != KIND_BFS) ? 4 : 1;
 
   const VgcArgs &a;
   Val *state;
@@ -106,6 +117,13 @@ struct Wave {
   Val *rval, *sval;
   uint32_t *rv, *sv, *rq, *sq, *scan;
   int32_t *rb, *re;
+  // Per-step record of each expanded entry (indexed by its lane), read by the
+  // lanes its arcs are dealt to: the entry's first arc minus its first dealt
+  // position, its value, and with several queries its query, round limit and
+  // state base (recB).
+  uint4 *recA;
+  uint2 *recB;
+  uint32_t mstamp;  // pass number, tags the arc-owner marks of the current pass
   unsigned long long *filt;  // LDS filter: (32-bit state index << 32) | a value this wavefront saw stored there
   uint32_t fshift;           // slot = (key * golden) >> fshift
   uint32_t Q, S, ln;
@@ -144,9 +162,15 @@ struct Wave {
     }
     scan = (uint32_t *)p;
     p += 64 * 4;
+    recA = (uint4 *)p;
+    p += 64 * 16;
+    recB = (uint2 *)p;
+    if (MULTI) p += 64 * 8;
     filt = (unsigned long long *)p;
     fshift = 32u - (uint32_t)__builtin_ctz(a.filt ? a.filt : 1u);
     for (uint32_t i = ln; i < a.filt; i += 64) filt[i] = ~0ull;  // key 0xFFFFFFFF: empty
+    scan[ln] = 0u;  // no mark carries stamp 0
+    mstamp = 0;
     wave_sync();
     head = tail = scount = 0;
     nslot = nbuf = 0;
@@ -154,22 +178,26 @@ struct Wave {
     root_end = 0;
     slice_ok = 0;
     qlite = nullptr;
+    qlite_ok = false;
     st_expand = st_arcs = st_success = st_publish = st_overflow = st_stale = st_steps = 0;
     st_filt_lane = 0;
   }
 
-  const QLite *qlite;  // LDS copy of the query table, or null
+  const LdsQLite *qlite;  // LDS copy of the query table (valid when qlite_ok)
+  bool qlite_ok;
 
   __device__ __forceinline__ int64_t sbase_of(uint32_t q) const {
     if (!MULTI) return 0;
-    return qlite ? qlite[q].sbase : a.qi[q].sbase;
+    if (qlite_ok) return qlite[q].sbase;
+    return a.qi[q].sbase;
   }
 
   // BFS window: distances below the limit may be expanded in this round;
   // the rest wait in the frontier (bucket width a.window per round).
   __device__ __forceinline__ uint32_t limit_of(uint32_t q) const {
     if (!DIST || a.window == 0) return 0xFFFFFFFFu;
-    const uint32_t r0 = MULTI ? (qlite ? qlite[q].r0 : a.qi[q].r0) : 0u;
+    uint32_t r0 = 0;
+    if (MULTI) r0 = qlite_ok ? qlite[q].r0 : a.qi[q].r0;
     const uint64_t lim = (uint64_t)(rabs + 1u - r0) * a.window;
     return lim > 0xFFFFFFFEull ? 0xFFFFFFFFu : (uint32_t)lim;
   }
@@ -330,24 +358,24 @@ struct Wave {
 
   __device__ __forceinline__ uint32_t filt_slot(uint32_t key) const { return (key * 0x9E3779B1u) >> fshift; }
 
-  __device__ __forceinline__ Rx relax_issue(int64_t sb, uint32_t w, int32_t arc, Val val) {
+  // ok: the lane holds a dealt arc (lanes without one pass a valid target,
+  // so that every load is issued unconditionally; only the atomic is masked).
+  __device__ __forceinline__ Rx relax_issue(bool ok, int64_t sb, uint32_t w, uint32_t wt, Val val) {
     Rx x;
     x.nb = x.ne = 0;
     if (DIST) {
       // SSSP distances saturate below the "unreached" value
-      const uint32_t nd = (KIND == KIND_SSSP)
-                              ? (uint32_t)min((unsigned long long)val + a.wgt[arc], 0xFFFFFFFEull)
-                              : (uint32_t)val + 1u;
+      const uint32_t nd = (KIND == KIND_SSSP) ? (uint32_t)min((unsigned long long)val + wt, 0xFFFFFFFEull)
+                                              : (uint32_t)val + 1u;
       x.nd = (Val)nd;
       uint32_t *p = (uint32_t *)&state[sb + w];
       // straight-line: each filter narrows one predicate, then a single
-      // masked region performs the atomic (nested early exits compiled to
-      // long chains of exec-mask updates)
-      bool go = true;
+      // masked region performs the atomic
+      bool go = ok;
       uint32_t old = 0xFFFFFFFFu;
-      if (a.test_first) {  // wave-uniform
+      if (TF) {
         const uint32_t cur = *(const uint32_t *)p;
-        go = cur > nd;
+        go = go && cur > nd;
         old = cur;
       }
       if (a.filt) {  // wave-uniform
@@ -357,7 +385,7 @@ struct Wave {
         old = (go && hit) ? (uint32_t)e : old;
         go = go && !hit;
       }
-      st_filt_lane += go ? 0u : 1u;
+      st_filt_lane += (ok && !go) ? 1u : 0u;
       if (go) {
         if (PF) {  // only for relaxations that reach the atomic
           x.nb = a.off[w];
@@ -369,14 +397,14 @@ struct Wave {
     } else {
       unsigned long long *p = (unsigned long long *)&state[sb + w];
       const unsigned long long m = (unsigned long long)val;
-      bool go = true;
+      bool go = ok;
       unsigned long long old = 0;
-      if (a.test_first) {  // wave-uniform
+      if (TF) {
         const unsigned long long cur = *(const unsigned long long *)p;
-        go = (cur & m) != m;
+        go = go && (cur & m) != m;
         old = cur;
       }
-      st_filt_lane += go ? 0u : 1u;
+      st_filt_lane += (ok && !go) ? 1u : 0u;
       if (go) {
         if (PF) {
           x.nb = a.off[w];
@@ -458,14 +486,96 @@ struct Wave {
     }
   }
 
+  // Arc dealing: the lane that owns arc j0 + ln (see wave_arc_owner), with
+  // marks tagged by the pass number so that the mark words need no clearing
+  // between passes.
+  __device__ __forceinline__ uint32_t arc_owner(uint32_t excl, uint32_t deg, uint32_t j0) {
+    if (++mstamp == (1u << 25)) {  // wave-uniform; tags wrap after 2^25 - 1 passes
+      scan[ln] = 0u;
+      mstamp = 1;
+    }
+    if (deg != 0u && excl < j0 + 64u && excl + deg > j0) scan[excl > j0 ? excl - j0 : 0u] = (mstamp << 7) | (ln + 1u);
+    wave_sync();
+    const uint32_t m = scan[ln];
+    wave_sync();
+    return wave_incl_max_dpp((m >> 7) == mstamp ? (m & 127u) : 0u, ln) - 1u;
+  }
+
+  // NP consecutive 64-arc passes starting at arc j0 (every one holds at least
+  // one arc), in straight-line code: every lane loads a target in every pass
+  // (lanes past the last arc repeat it), so the loads of all passes are in
+  // flight together and each relaxation waits only for its own target; then
+  // the atomics of all passes, then their pushes. Returns the successes.
+  template <int NP>
+  __device__ __forceinline__ uint32_t passes(uint32_t j0, uint32_t total, uint32_t excl, uint32_t deg, uint32_t lim1,
+                                             bool ring_ok) {
+    uint32_t w[NP], wt[NP], lim[NP], qo[NP];
+    Val vo[NP];
+    int64_t sbo[NP];
+    bool okl[NP];
+#pragma unroll
+    for (int r = 0; r < NP; r++) {
+      const uint32_t jr = j0 + 64u * (uint32_t)r;
+      const uint32_t owner = arc_owner(excl, deg, jr);
+      const uint32_t ai = jr + ln;
+      okl[r] = ai < total;
+      uint32_t bx;
+      if (MULTI) {
+        const uint4 R = recA[owner];
+        const uint2 S = recB[owner];
+        bx = R.x;
+        if (DIST) {
+          vo[r] = (Val)R.y;
+          lim[r] = R.z;
+          qo[r] = R.w;
+        } else {
+          qo[r] = R.y;
+          vo[r] = (Val)(((unsigned long long)R.w << 32) | R.z);
+          lim[r] = 0xFFFFFFFFu;
+        }
+        sbo[r] = (int64_t)(((unsigned long long)S.y << 32) | S.x);
+      } else {
+        if (DIST) {
+          const uint2 R = ((const uint2 *)recA)[owner];
+          bx = R.x;
+          vo[r] = (Val)R.y;
+        } else {
+          const uint4 R = recA[owner];
+          bx = R.x;
+          vo[r] = (Val)(((unsigned long long)R.w << 32) | R.z);
+        }
+        lim[r] = lim1;
+        qo[r] = 0;
+        sbo[r] = 0;
+      }
+      const int32_t arc = (int32_t)(bx + min(ai, total - 1u));
+      w[r] = (uint32_t)a.tgt[arc];
+      wt[r] = (KIND == KIND_SSSP) ? a.wgt[arc] : 0u;
+    }
+    Rx x[NP];
+#pragma unroll
+    for (int r = 0; r < NP; r++) x[r] = relax_issue(okl[r], sbo[r], w[r], wt[r], vo[r]);
+    uint32_t ns = 0;
+#pragma unroll
+    for (int r = 0; r < NP; r++) {
+      Val nv = 0;
+      const bool ok = okl[r] && relax_finish(x[r], (uint32_t)sbo[r] + w[r], vo[r], nv);
+      ns += __popcll(__ballot(ok));
+      push_lim(ok, w[r], qo[r], nv, lim[r], ring_ok, x[r].nb, x[r].ne);
+    }
+    return ns;
+  }
+
   // Expand the active lanes' entries: scan out-arcs, relax, push successes.
-  // Returns the number of entries expanded (not stale).
-  __device__ __forceinline__ uint32_t expand(bool act, uint32_t v, uint32_t q, Val val, bool ring_ok, int32_t b = 0, int32_t e = 0,
-                             bool have_range = false, bool check_stale = true) {
-    const int64_t sb = (act && MULTI) ? sbase_of(q) : 0;
-    if (act && !have_range) {
-      b = a.off[v];
-      e = a.off[v + 1];
+  // Returns the number of entries expanded (not stale). Every vertex's arcs
+  // are dealt out across the wavefront 64 at a time (consecutive lanes take
+  // consecutive arcs, so one memory instruction touches few cache lines).
+  __device__ __forceinline__ uint32_t expand(bool act, uint32_t v, uint32_t q, Val val, bool ring_ok, int32_t b = 0,
+                                             int32_t e = 0, bool have_range = false, bool check_stale = true) {
+    const int64_t sb = MULTI ? sbase_of(act ? q : 0u) : 0;
+    if (!have_range) {  // inactive lanes read row 0, so the loads need no branch
+      b = a.off[act ? v : 0u];
+      e = a.off[(act ? v : 0u) + 1];
     }
     if (DIST && act && check_stale) {
       // a smaller distance is already known: another entry carries it
@@ -481,103 +591,41 @@ struct Wave {
     const uint32_t incl = wave_incl_sum_dpp(deg, ln);
     const uint32_t total = lane_read(incl, 63);
     if (total == 0) return nexp;
-    // both paths count into these, and one epilogue adds them to the stats
-    // (an update per path let the compiler merge the two into one store
-    // through a selected address, which kept the counters in scratch memory)
-    uint32_t nsucc = 0, arcs = 0;
-    // the row-per-lane path exists only in LANE instantiations: its eight
-    // relaxation records in flight would otherwise set every kernel's
-    // register budget
-    const uint32_t maxd = LANE ? wave_max_dpp(deg, ln) : 0u;
-    if (LANE && maxd <= a.lane_arcs) {
-      int32_t w[8];
-#pragma clang loop unroll(full)
-      for (int u = 0; u < 8; u++) w[u] = ((uint32_t)u < deg) ? a.tgt[b + u] : 0;
-      Rx x[8];
-#pragma clang loop unroll(full)
-      for (int u = 0; u < 8; u++) {
-        x[u].nd = x[u].old = 0;
-        x[u].nb = x[u].ne = 0;
-        if ((uint32_t)u < deg) x[u] = relax_issue(sb, (uint32_t)w[u], b + u, val);
+    const uint32_t excl = incl - deg;
+    if (deg != 0u) {
+      const uint32_t bx = (uint32_t)b - excl;
+      if (MULTI) {
+        if (DIST)
+          recA[ln] = make_uint4(bx, (uint32_t)val, a.window ? limit_of(q) : 0xFFFFFFFFu, q);
+        else
+          recA[ln] = make_uint4(bx, q, (uint32_t)val, (uint32_t)((unsigned long long)val >> 32));
+        recB[ln] = make_uint2((uint32_t)sb, (uint32_t)((unsigned long long)sb >> 32));
+      } else if (DIST) {
+        ((uint2 *)recA)[ln] = make_uint2(bx, (uint32_t)val);
+      } else {
+        recA[ln] = make_uint4(bx, 0u, (uint32_t)val, (uint32_t)((unsigned long long)val >> 32));
       }
-#pragma clang loop unroll(full)
-      for (int u = 0; u < 8; u++) {
-        if ((uint32_t)u < maxd) {  // wave-uniform
-          Val nv = DIST ? x[u].nd : val;
-          const bool ok = (uint32_t)u < deg && relax_finish(x[u], (uint32_t)sb + (uint32_t)w[u], val, nv);
-          arcs += __popcll(__ballot((uint32_t)u < deg));
-          nsucc += __popcll(__ballot(ok));
-          push(ok, (uint32_t)w[u], q, nv, ring_ok, x[u].nb, x[u].ne);
-        }
-      }
-    } else {
-      // Flattened: the wave's arcs are dealt out 64 at a time; each lane finds
-      // its arc's owner lane from marks in LDS carried forward by a prefix
-      // maximum (one LDS round trip per pass).
-      // Up to RB such passes are issued together (target loads, then atomics,
-      // then pushes), so a lane has RB relaxations in flight instead of one;
-      // passes past the last arc are skipped whole (wave-uniform), so a thin
-      // step costs one pass.
-      const uint32_t excl = incl - deg;
-      arcs = total;
-      // single-query BFS steps are thin (one pass); reach steps (deep LIFO
-      // searches), SSSP steps and multi-query steps are several passes wide
-      constexpr int RB = (MULTI || KIND != KIND_BFS) ? 4 : 1;
-      for (uint32_t j0 = 0; j0 < total; j0 += 64 * RB) {
-        uint32_t w[RB], qo[RB], sbl[RB], lim[RB];
-        int32_t arc[RB];
-        int64_t sbo[RB];
-        Val vo[RB];
-        bool okl[RB];
-  #pragma clang loop unroll(full)
-        for (int r = 0; r < RB; r++) {
-          const uint32_t ai = j0 + (uint32_t)r * 64u + ln;
-          okl[r] = ai < total;
-          w[r] = 0;
-          arc[r] = 0;
-          qo[r] = 0;
-          sbo[r] = 0;
-          sbl[r] = 0;
-          lim[r] = 0xFFFFFFFFu;
-          vo[r] = 0;
-          if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform: no arcs left for this pass
-          const int owner = (int)wave_arc_owner(excl, deg, j0 + (uint32_t)r * 64u, scan, ln);
-          // the owner's first arc minus its first dealt position
-          const uint32_t bx = (uint32_t)__shfl((int)((uint32_t)b - excl), owner);
-          qo[r] = MULTI ? (uint32_t)__shfl(q, owner) : 0u;
-          sbo[r] = MULTI ? (int64_t)shfl64((unsigned long long)sb, owner) : 0;
-          sbl[r] = (uint32_t)sbo[r];
-          // looked up now, while the target load is in flight, rather than
-          // after the atomic returns
-          if (DIST && a.window) lim[r] = limit_of(qo[r]);
-          if (DIST)
-            vo[r] = (Val)__shfl((uint32_t)val, owner);
-          else
-            vo[r] = (Val)shfl64((unsigned long long)val, owner);
-          arc[r] = (int32_t)(bx + ai);
-          w[r] = okl[r] ? (uint32_t)a.tgt[arc[r]] : 0u;
-        }
-        Rx x[RB];
-  #pragma clang loop unroll(full)
-        for (int r = 0; r < RB; r++) {
-          x[r].nd = x[r].old = 0;
-          x[r].nb = x[r].ne = 0;
-          if (j0 + (uint32_t)r * 64u >= total) continue;  // wave-uniform
-          if (okl[r]) x[r] = relax_issue(sbo[r], w[r], arc[r], vo[r]);
-        }
-  #pragma clang loop unroll(full)
-        for (int r = 0; r < RB; r++) {
-          if (j0 + (uint32_t)r * 64u >= total) break;  // wave-uniform
-          Val nv = 0;
-          const bool ok = okl[r] && relax_finish(x[r], sbl[r] + w[r], vo[r], nv);
-          nsucc += __popcll(__ballot(ok));
-          push_lim(ok, w[r], qo[r], nv, lim[r], ring_ok, x[r].nb, x[r].ne);
-        }
-      }
-      wave_sync();
     }
+    wave_sync();
+    // one query: the round's limit is the same for every entry
+    const uint32_t lim1 = (!MULTI && DIST && a.window) ? limit_of(0) : 0xFFFFFFFFu;
+    uint32_t nsucc = 0;
+    for (uint32_t j0 = 0; j0 < total;) {  // wave-uniform
+      const uint32_t left = (total - j0 + 63u) >> 6;
+      if (RB >= 4 && left >= 4) {
+        nsucc += passes<(RB >= 4 ? 4 : 1)>(j0, total, excl, deg, lim1, ring_ok);
+        j0 += 256;
+      } else if (RB >= 2 && left >= 2) {
+        nsucc += passes<(RB >= 2 ? 2 : 1)>(j0, total, excl, deg, lim1, ring_ok);
+        j0 += 128;
+      } else {
+        nsucc += passes<1>(j0, total, excl, deg, lim1, ring_ok);
+        j0 += 64;
+      }
+    }
+    wave_sync();
     st_success += nsucc;
-    st_arcs += arcs;
+    st_arcs += total;
     return nexp;
   }
 
@@ -806,7 +854,7 @@ struct Wave {
   }
 };
 
-template <int KIND, bool MULTI, bool PF, bool LANE>
+template <int KIND, bool MULTI, bool PF, bool TF>
 __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ RoundHdr hdr;
@@ -814,7 +862,7 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wid = threadIdx.x >> 6;
   const size_t per_wave = vgc_lds_bytes(KIND, MULTI, PF, 1, a.ring_cap, a.stage_cap, a.filt);
-  Wave<KIND, MULTI, PF, LANE> wv(a, smem + per_wave * wid);
+  Wave<KIND, MULTI, PF, TF> wv(a, smem + per_wave * wid);
   __shared__ QLite qlite[MULTI ? QLITE : 1];
   if (MULTI && a.nq <= QLITE) {
     for (int i = threadIdx.x; i < a.nq; i += blockDim.x) {
@@ -822,7 +870,8 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
       qlite[i].r0 = a.qi[i].r0;
       qlite[i].pad = 0;
     }
-    wv.qlite = qlite;
+    wv.qlite = (const LdsQLite *)qlite;
+    wv.qlite_ok = true;
   }
   const uint32_t total_waves = gridDim.x * nw;
   // XCD-aware numbering: workgroups are dispatched round-robin over the 8
@@ -984,24 +1033,24 @@ hipError_t launch_seed(int kind, const VgcArgs &a, const SeedEnt *seeds, uint32_
 }
 
 template <int KIND, bool MULTI>
-static const void *vgc_variant(bool pf, bool lane) {
-  if (pf) return lane ? (const void *)vgc_kernel<KIND, MULTI, true, true> : (const void *)vgc_kernel<KIND, MULTI, true, false>;
-  return lane ? (const void *)vgc_kernel<KIND, MULTI, false, true> : (const void *)vgc_kernel<KIND, MULTI, false, false>;
+static const void *vgc_variant(bool pf, bool tf) {
+  if (pf) return tf ? (const void *)vgc_kernel<KIND, MULTI, true, true> : (const void *)vgc_kernel<KIND, MULTI, true, false>;
+  return tf ? (const void *)vgc_kernel<KIND, MULTI, false, true> : (const void *)vgc_kernel<KIND, MULTI, false, false>;
 }
 
-const void *vgc_kernel_ptr(int kind, bool multi, bool pf, bool lane) {
+const void *vgc_kernel_ptr(int kind, bool multi, bool pf, bool tf) {
   if (kind == KIND_SSSP) {  // one query per launch
     if (multi) return nullptr;
-    return vgc_variant<KIND_SSSP, false>(pf, lane);
+    return vgc_variant<KIND_SSSP, false>(pf, tf);
   }
-  if (kind == KIND_BFS) return multi ? vgc_variant<KIND_BFS, true>(pf, lane) : vgc_variant<KIND_BFS, false>(pf, lane);
-  return multi ? vgc_variant<KIND_REACH, true>(pf, lane) : vgc_variant<KIND_REACH, false>(pf, lane);
+  if (kind == KIND_BFS) return multi ? vgc_variant<KIND_BFS, true>(pf, tf) : vgc_variant<KIND_BFS, false>(pf, tf);
+  return multi ? vgc_variant<KIND_REACH, true>(pf, tf) : vgc_variant<KIND_REACH, false>(pf, tf);
 }
 
 hipError_t launch_vgc(int kind, bool multi, bool pf, const VgcArgs &a, int grid, int block, size_t lds,
                       bool cooperative, hipStream_t s) {
   (void)hipGetLastError();  // report only this launch's error
-  const void *fn = vgc_kernel_ptr(kind, multi, pf, a.lane_arcs != 0);
+  const void *fn = vgc_kernel_ptr(kind, multi, pf, a.test_first != 0);
   if (!fn) return hipErrorInvalidDeviceFunction;
   VgcArgs copy = a;
   void *args[] = {&copy};

@@ -671,6 +671,7 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
   Workspace *w = workspace_for(o.stream);
   if (!w) return PASGAL_ENOMEM;
   std::lock_guard<std::mutex> lk(w->mu);
+  if (int arc = collect_async(*w)) return arc;
   SccBufs *bp = scc_bufs(w);
   if (!bp) return PASGAL_ENOMEM;
   SccBufs &B = *bp;
@@ -760,7 +761,6 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
   a.window = 0;
   a.round_base = 0;
   a.test_first = o.test_first ? 1u : 0u;
-  a.lane_arcs = o.lane_arcs;
   a.timeout_ticks = (long long)o.timeout_ms * (long long)dev_info().wall_khz;
   a.ctl = (Ctl *)w->ctl.p;
   const uint32_t hcap = slice_capacity(m2, o.heavy, cap);

@@ -346,7 +346,6 @@ struct pasgal_server {
     a.window = vopts.window;
     a.round_base = L.round_abs;
     a.test_first = vopts.test_first ? 1u : 0u;
-    a.lane_arcs = vopts.lane_arcs;
     // filter keys are 32-bit state indices: exact only below 2^32 values
     a.filt = (uint64_t)arena.bytes / es < (1ull << 32) ? L.lg.filt : 0u;
     a.timeout_ticks = (long long)vopts.timeout_ms * (long long)dev_info().wall_khz;

@@ -7,6 +7,7 @@ holds at any size and characterises the exact answer (closed-form grid
 distances, the BFS certificate, reachability closure).
 """
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -63,14 +64,24 @@ def test_c2_knn10m_batched16_and_reach16(pg, knn10m):
 
 
 def test_c2_knn10m_single_source_calls(pg, knn10m):
+    """Every tau the configuration names (64, 256, 1024, 4096), with the
+    distance window off and at its default, and plain, for BFS and reach."""
     g = knn10m
     s = int(gg.sources(g, 16, 1002)[5])
     d = pg.DeviceGraph.from_graph(g)
     exp = oracle.bfs(g, s)
-    for kw in [dict(), dict(tau=4096, window=64), dict(mode="plain")]:
-        _say(f"c2 single {kw}")
-        assert np.array_equal(pg.bfs(d, s, **kw).cpu().numpy(), exp)
-    assert np.array_equal(pg.reach(d, [s]).cpu().numpy().view(np.uint64)[:, 0] == 1, exp >= 0)
+    cases = [dict(mode="plain")]
+    for tau in (64, 256, 1024, 4096):
+        cases += [dict(tau=tau), dict(tau=tau, window=0)]
+    cases.append(dict(tau=4096, window=64))
+    for kw in cases:
+        _say(f"c2 single bfs {kw}")
+        assert np.array_equal(pg.bfs(d, s, **kw).cpu().numpy(), exp), kw
+    for kw in [dict(mode="plain"), dict(tau=64), dict(tau=256), dict(tau=1024), dict(tau=4096)]:
+        _say(f"c2 single reach {kw}")
+        got = pg.reach(d, [s], **kw).cpu().numpy().view(np.uint64)[:, 0]
+        assert np.array_equal(got == 1, exp >= 0), kw
+        assert np.all((got == 0) | (got == 1)), kw
 
 
 def test_c2_knn10m_sssp_against_dijkstra(pg, knn10m):
@@ -97,6 +108,13 @@ def test_c3_road4096_forward_backward_scc(pg):
     t = pg.transpose(d)
     t_off, t_tgt = oracle.transpose(g)
     assert np.array_equal(t.offsets.cpu().numpy(), t_off)
+    # every row as a set (the order inside a row is unspecified): sort the
+    # (row, target) pairs of both sides
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(t_off))
+    got_keys = np.sort(rows * g.n + t.targets.cpu().numpy().astype(np.int64))
+    exp_keys = np.sort(rows * g.n + t_tgt.astype(np.int64))
+    assert np.array_equal(got_keys, exp_keys)
+    del rows, got_keys, exp_keys
     gt = gg.Graph(t_off, t_tgt)
     pivots = gg.sources(g, 64, 1003)
     _say("c3 forward/backward reach")
@@ -133,12 +151,12 @@ def test_c3_road4096_scc_against_tarjan(pg):
         assert st["components"] == 1716206
 
 
-def test_c4_batch_1024_queries_uneven_graphs(pg):
+@pytest.fixture(scope="module")
+def c4():
     rec = gg.batch_recipe()
     _say("c4 generate")
     graphs = gg.batch_graphs(rec)
     packed = gg.pack(graphs)
-    pd = pg.DeviceGraph.from_numpy(packed.offsets, packed.targets)
     qg, qs, qo = [], [], []
     off = 0
     for gi, g in enumerate(graphs):
@@ -147,12 +165,12 @@ def test_c4_batch_1024_queries_uneven_graphs(pg):
             qs.append(int(s))
             qo.append(off)
             off += g.n
-    dist = torch.empty(off, dtype=torch.int32, device="cuda")
-    _say(f"c4 batch of {len(qg)} queries, {packed.n} vertices, {packed.m} arcs")
-    b = pg.Batch(pd, packed.vbase, np.array(qg), np.array(qs), np.array(qo, dtype=np.int64), dist)
-    b.run()
-    got = dist.cpu().numpy()
-    b.close()
+    return rec, graphs, packed, np.array(qg), np.array(qs), np.array(qo, dtype=np.int64), off
+
+
+def _check_c4(rec, graphs, qg, qs, qo, got):
+    """Every query: grids by the closed form, 5-NN graphs by the oracle (the
+    small ones and every 16th) or by the BFS certificate."""
     checked = 0
     for j in range(len(qg)):
         kind = rec[qg[j]]
@@ -161,14 +179,46 @@ def test_c4_batch_1024_queries_uneven_graphs(pg):
         if kind[0] == "grid":
             side = kind[1]
             r, c = np.divmod(np.arange(g.n), side)
-            r0, c0 = divmod(qs[j], side)
+            r0, c0 = divmod(int(qs[j]), side)
             assert np.array_equal(out, np.abs(r - r0) + np.abs(c - c0)), j
         elif j % 16 == 0 or g.n < 30000:
-            assert np.array_equal(out, oracle.bfs(g, qs[j])), j
+            assert np.array_equal(out, oracle.bfs(g, int(qs[j]))), j
             checked += 1
         else:
-            assert pins.bfs_certificate_ok(g, qs[j], out), j
+            assert pins.bfs_certificate_ok(g, int(qs[j]), out), j
     assert checked > 0
+
+
+def test_c4_batch_1024_queries_uneven_graphs(pg, c4):
+    rec, graphs, packed, qg, qs, qo, total = c4
+    pd = pg.DeviceGraph.from_numpy(packed.offsets, packed.targets)
+    dist = torch.empty(total, dtype=torch.int32, device="cuda")
+    _say(f"c4 batch of {len(qg)} queries, {packed.n} vertices, {packed.m} arcs")
+    b = pg.Batch(pd, packed.vbase, qg, qs, qo, dist)
+    b.run()
+    got = dist.cpu().numpy()
+    b.close()
+    _check_c4(rec, graphs, qg, qs, qo, got)
+
+
+def test_c4_batch_autotuned_every_query(pg, c4):
+    """The configuration the c4 suite times: tau, workgroup size and frontier
+    capacity chosen by the autotuner, the captured graph replayed twice (the
+    second replay after eager work on the stream); every query checked."""
+    rec, graphs, packed, qg, qs, qo, total = c4
+    pd = pg.DeviceGraph.from_numpy(packed.offsets, packed.targets)
+    dist = torch.empty(total, dtype=torch.int32, device="cuda")
+    _say("c4 autotuned batch")
+    b = pg.Batch(pd, packed.vbase, qg, qs, qo, dist, autotune=True)
+    cfg = b.config()
+    _say(f"c4 autotuned config {cfg}")
+    b.run()
+    got = dist.cpu().numpy()
+    _check_c4(rec, graphs, qg, qs, qo, got)
+    dist.fill_(-7)
+    b.run()
+    assert np.array_equal(dist.cpu().numpy(), got)
+    b.close()
 
 
 def test_c5_grid8192_closed_form_and_rmat24_sample(pg):
@@ -196,3 +246,78 @@ def test_c5_grid8192_closed_form_and_rmat24_sample(pg):
     assert np.array_equal(pg.bfs_do(dx, s).cpu().numpy(), exp)
     got = pg.reach(dx, [s]).cpu().numpy().view(np.uint64)[:, 0]
     assert np.array_equal(got == 1, exp >= 0)
+
+
+def test_c5_served_full_size_state_past_2_32(pg):
+    """The served configuration at full size: the 8192^2 grid and RMAT-24
+    resident, 256 slots, a burst of requests whose state lies beyond 2^32
+    elements of the arena (so 64-bit state and bitmap indices are used and the
+    32-bit-keyed LDS filter is off). Grid BFS against the Manhattan closed form
+    and grid reach against all bits set (the grid is connected), computed on
+    the device; RMAT requests against the oracle."""
+    side = 8192
+    grid = gg.grid(side, side)
+    _say("c5 served: generate rmat24")
+    rmat = gg.rmat(24, 16, 5)
+    dg, dr = pg.DeviceGraph.from_graph(grid), pg.DeviceGraph.from_graph(rmat)
+    srv = pg.Server(max_slots=256)
+    gid_g, gid_r = srv.add_graph(dg), srv.add_graph(dr)
+    plan = []
+    rng = np.random.default_rng(2025)
+    # reach first: 40 x 8 B x 67M = 21.5 GB of arena, so the BFS requests
+    # admitted after them (first fit, in arrival order, while the reach
+    # requests are still resident) sit past 16 GiB = 2^32 4-byte elements
+    for i in range(40):
+        k = int(rng.integers(1, 65))
+        srcs = [int(x) for x in rng.integers(0, grid.n, size=k)]
+        plan.append(("grid", "reach", srcs, torch.empty(grid.n, dtype=torch.int64, device="cuda")))
+    for i in range(24):
+        plan.append(("grid", "bfs", [int(rng.integers(0, grid.n))], torch.empty(grid.n, dtype=torch.int32,
+                                                                                 device="cuda")))
+    pool = np.flatnonzero(np.diff(rmat.offsets) > 0)
+    for i in range(3):
+        kind = "reach" if i == 2 else "bfs"
+        srcs = [int(pool[x]) for x in rng.integers(0, pool.size, size=(3 if kind == "reach" else 1))]
+        plan.append(("rmat", kind, srcs, torch.empty(rmat.n, dtype=torch.int64 if kind == "reach" else torch.int32,
+                                                     device="cuda")))
+    torch.cuda.synchronize()
+    reqs = [(where, kind, srcs, out, srv.submit(gid_g if where == "grid" else gid_r, kind, srcs, out=out))
+            for where, kind, srcs, out in plan]
+    assert all(r[4] is not None for r in reqs)
+    _say(f"c5 served: {len(reqs)} requests submitted")
+    most = 0
+    for _ in range(4000):
+        info = srv.load_info()
+        most = max(most, info["bytes"])
+        if info["active"] + info["queued"] < len(reqs):
+            break
+        time.sleep(0.0005)
+    # every grid reach request and at least one grid BFS request were resident together
+    assert most >= 40 * 8 * grid.n + 4 * grid.n, most
+    srv.drain(240000)
+    comps = {c["id"]: c for c in srv.poll(1000)}
+    assert len(comps) == len(reqs)
+    assert all(c["status"] == 0 for c in comps.values())
+    idx = torch.arange(grid.n, dtype=torch.int64, device="cuda")
+    r, c = idx // side, idx % side
+    del idx
+    for where, kind, srcs, out, rid in reqs:
+        if where != "grid":
+            continue
+        if kind == "bfs":
+            r0, c0 = divmod(srcs[0], side)
+            exp = ((r - r0).abs() + (c - c0).abs()).to(torch.int32)
+            assert torch.equal(out, exp), (rid, srcs)
+        else:
+            want = int(np.array((1 << len(srcs)) - 1, dtype=np.uint64).view(np.int64))
+            assert bool((out == want).all()), (rid, len(srcs))
+    del r, c
+    for where, kind, srcs, out, rid in reqs:
+        if where != "rmat":
+            continue
+        _say(f"c5 served: rmat {kind} oracle")
+        if kind == "bfs":
+            assert np.array_equal(out.cpu().numpy(), oracle.bfs(rmat, srcs[0])), rid
+        else:
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.reach(rmat, srcs)[:, 0]), rid
+    srv.close()

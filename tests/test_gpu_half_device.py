@@ -114,3 +114,48 @@ def test_two_asynchronous_bfs_calls_overlap(pg):
         torch.cuda.synchronize()
         assert np.array_equal(o1.cpu().numpy(), oracle.bfs(g1, s1)), rep
         assert np.array_equal(o2.cpu().numpy(), oracle.bfs(g2, s2)), rep
+
+
+def test_async_timeout_reported_by_wait_and_next_call(pg):
+    """Status of asynchronous launches (PASGAL_FLAG_ASYNC): a launch whose
+    bounded waits expire (timeout 1 ms on a traversal of about 1,600 tau-1
+    rounds, each ending at a grid barrier) still returns PASGAL_OK at once;
+    pasgal_wait on its stream then reports PASGAL_ETIMEOUT, and a second wait
+    reports OK. When nobody waits, the next call on that stream reports the
+    timeout instead of running; the call after it runs normally. Every kernel
+    exits through its own bounded wait."""
+    g = gg.knn(2_000_000, 5, 2)
+    d = pg.DeviceGraph.from_graph(g)
+    src = int(gg.sources(g, 1, 31)[0])
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    quick = dict(stream=s, asynchronous=True, timeout_ms=1, tau=1, window=0)
+    _say("async timeout, then wait")
+    pg.bfs(d, src, dist_out=out, **quick)
+    with pytest.raises(pg.PasgalError) as ei:
+        pg.wait(s)
+    assert ei.value.code == -7
+    pg.wait(s)
+    _say("async timeout, then the next call")
+    pg.bfs(d, src, dist_out=out, **quick)
+    with pytest.raises(pg.PasgalError) as ei:
+        pg.bfs(d, src, dist_out=out, stream=s)
+    assert ei.value.code == -7
+    got = pg.bfs(d, src, dist_out=out, stream=s).cpu().numpy()
+    assert np.array_equal(got, oracle.bfs(g, src))
+    # an asynchronous launch that finishes in time reports OK
+    pg.bfs(d, src, dist_out=out, stream=s, asynchronous=True)
+    pg.wait(s)
+    assert np.array_equal(out.cpu().numpy(), got)
+
+
+def test_shutdown_then_calls_work_again(pg):
+    """pasgal_shutdown releases every workspace; later calls re-create them."""
+    g = gg.road(80, 9)
+    d = pg.DeviceGraph.from_graph(g)
+    srcs = gg.sources(g, 3, 12)
+    before = pg.bfs(d, int(srcs[0])).cpu().numpy()
+    pg.load().pasgal_shutdown()
+    assert np.array_equal(pg.bfs(d, int(srcs[0])).cpu().numpy(), before)
+    assert np.array_equal(pg.reach(d, srcs).cpu().numpy().view(np.uint64), oracle.reach(g, srcs))
+    assert np.array_equal(before, oracle.bfs(g, int(srcs[0])))

@@ -155,10 +155,8 @@ def test_bfs_window_and_chunk(pg, window, min_chunk):
                 assert np.array_equal(np_dist(got), exp), (g.name, window, min_chunk, tau, cap)
 
 
-@pytest.mark.parametrize("prefetch,test_first,spread", [(True, False, False), (False, False, False),
-                                                         (True, True, False), (False, True, True),
-                                                         (False, False, True), (True, False, True)])
-def test_relax_variants(pg, prefetch, test_first, spread):
+@pytest.mark.parametrize("prefetch,test_first", [(True, False), (False, False), (True, True), (False, True)])
+def test_relax_variants(pg, prefetch, test_first):
     for g in [gg.knn(20000, 5, 3), gg.road(90, 7), gg.rmat(12, 8, 6)]:
         d = dev(pg, g)
         for s in gg.sources(g, 2, 77, min_degree=1):
@@ -166,12 +164,12 @@ def test_relax_variants(pg, prefetch, test_first, spread):
             for tau, window, cap in [(1, 0, 0), (256, 0, 0), (1024, 32, 0), (64, 8, 120)]:
                 _say(f"{g.name} pf={prefetch} tf={test_first} tau={tau} w={window} cap={cap} src={s}")
                 got = pg.bfs(d, int(s), tau=tau, window=window, frontier_capacity=cap, prefetch=prefetch,
-                             test_first=test_first, spread_arcs=spread)
+                             test_first=test_first)
                 assert np.array_equal(np_dist(got), exp)
         srcs = gg.sources(g, 20, 78)
         exp = oracle.reach(g, srcs)
         for tau in [1, 256, 4096]:
-            got = pg.reach(d, srcs, tau=tau, prefetch=prefetch, test_first=test_first, spread_arcs=spread)
+            got = pg.reach(d, srcs, tau=tau, prefetch=prefetch, test_first=test_first)
             assert np.array_equal(np_mask(got), exp)
 
 

@@ -73,9 +73,9 @@ def test_sssp_families(pg, name, make, wr):
 @pytest.mark.parametrize("kw", [dict(mode="plain"), dict(tau=16), dict(tau=1024), dict(window=-1), dict(window=50),
                                 dict(frontier_capacity=64), dict(heavy_arcs=16), dict(wg_size=256, blocks_per_cu=2),
                                 dict(tau=1, window=-1, frontier_capacity=64), dict(prefetch=False),
-                                dict(prefetch=False, frontier_capacity=64), dict(spread_arcs=False)],
+                                dict(prefetch=False, frontier_capacity=64), dict(test_first=True)],
                          ids=["plain", "tau16", "tau1024", "nowindow", "delta50", "cap64", "heavy16", "wg256x2", "bellman",
-                              "no_prefetch", "no_prefetch_cap64", "row_per_lane"])
+                              "no_prefetch", "no_prefetch_cap64", "test_first"])
 def test_sssp_schedules(pg, kw):
     for g, wr in [(gg.road(96, 5), (1, 1000)), (gg.rmat(11, 16, 3), (1, 100)), (gg.knn(8000, 5, 9), (0, 50))]:
         w = gg.weights(g, 83, *wr)
