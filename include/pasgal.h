@@ -93,6 +93,13 @@ typedef struct pasgal_csr {
 #define PASGAL_FLAG_NO_TEST_FIRST 64u /* VGC: never read before the atomic (overrides those defaults) */
 #define PASGAL_FLAG_NO_PREFETCH 128u  /* VGC: never carry arc ranges in the local queue (overrides those
                                          defaults and PASGAL_FLAG_PREFETCH) */
+#define PASGAL_FLAG_NO_IMPLICATIONS 256u /* reach, VGC: do not use source implications. By default, when new
+                                            bits reach the vertex of source j, the sources behind them reach
+                                            everything source j reaches, so bit j implies them, and every
+                                            expansion propagates the closure of its mask under the
+                                            implications known so far (only true reachability facts): the
+                                            bits of sources that reach each other then travel together
+                                            instead of re-expanding each vertex once per bit */
 #define PASGAL_FLAG_HALF_DEVICE 32u /* VGC: size the persistent launch to half of every compute unit (LDS and
                                        wave slots for 2 x blocks_per_cu workgroups per CU; PASGAL_EINVAL if
                                        that many do not fit) and launch it as an ordinary kernel, so that a

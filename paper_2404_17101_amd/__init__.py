@@ -91,7 +91,7 @@ def _stream_ptr(stream) -> int:
 
 def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
           stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=None, test_first=None,
-          heavy_arcs=0, filter_slots=0, chunks_per_wave=0, half_device=False) -> L.Opts:
+          heavy_arcs=0, filter_slots=0, chunks_per_wave=0, half_device=False, implications=True) -> L.Opts:
     """tau: local-search budget (0 = the entry point's default: 1024, SSSP and
     SCC on graphs of mean out-degree above 8: 1). window: BFS distance window per
     round (0 or negative = none).
@@ -115,7 +115,7 @@ def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0,
     o.flags = ((L.FLAG_VALIDATE if validate else 0) | (L.FLAG_ASYNC if asynchronous else 0) |
                (0 if prefetch is None else (L.FLAG_PREFETCH if prefetch else L.FLAG_NO_PREFETCH)) |
                (0 if test_first is None else (L.FLAG_TEST_FIRST if test_first else L.FLAG_NO_TEST_FIRST)) |
-               (L.FLAG_HALF_DEVICE if half_device else 0))
+               (L.FLAG_HALF_DEVICE if half_device else 0) | (0 if implications else L.FLAG_NO_IMPLICATIONS))
     o.timeout_ms = int(timeout_ms)
     o.stream = _stream_ptr(stream)
     o.window = int(window) if int(window) > 0 else -1

@@ -48,7 +48,7 @@ uint32_t slice_capacity(uint64_t m, uint32_t heavy, uint64_t frontier_cap);
 struct Workspace {
   std::mutex mu;
   hipStream_t stream = nullptr;
-  DBuf ctl, fv[2], fq[2], fval[2], dirty, qi, qword, seeds, pf[2], stamp, tmp_state, tscratch, plain_src, aux;
+  DBuf ctl, fv[2], fq[2], fval[2], dirty, qi, qword, seeds, pf[2], stamp, tmp_state, tscratch, plain_src, aux, imp;
   uint32_t cap = 0;
   HBuf h_ctl, h_stage, h_aux, h_src;
   // An asynchronous launch (PASGAL_FLAG_ASYNC) returned before its control

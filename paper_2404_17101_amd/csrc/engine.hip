@@ -105,7 +105,7 @@ void free_hbuf(HBuf &b) {
 
 Workspace::~Workspace() {
   for (DBuf *b : {&ctl, &fv[0], &fv[1], &fq[0], &fq[1], &fval[0], &fval[1], &dirty, &qi, &qword, &seeds, &pf[0],
-                  &pf[1], &stamp, &tmp_state, &tscratch, &plain_src, &aux})
+                  &pf[1], &stamp, &tmp_state, &tscratch, &plain_src, &aux, &imp})
     free_buf(*b);
   free_hbuf(h_ctl);
   free_hbuf(h_stage);
@@ -257,12 +257,21 @@ int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   // a half-device launch sizes its workgroups for twice as many per CU
   const int per_cu = o.half ? 2 * o.bpc : o.bpc;
   const size_t lds_cap_block = std::min<size_t>(di.lds_per_cu / (size_t)per_cu, di.lds_per_block);
+  // dynamic LDS leaves room for the kernel's static arrays (round header,
+  // counts, query table or source-implication tables)
+  const void *fn = vgc_kernel_ptr(kind, multi, o.prefetch, o.test_first);
+  hipFuncAttributes fattr{};
+  if (hipFuncGetAttributes(&fattr, fn) != hipSuccess) {
+    (void)hipGetLastError();
+    fattr.sharedSizeBytes = 4096;
+  }
+  const size_t kStatic = fattr.sharedSizeBytes + 256;
   // stage 128 entries; ring = largest power of two that fits
   const uint32_t S = 128;
   const bool pf = o.prefetch;
   auto largest_ring = [&](uint32_t F) {
     uint32_t Q = 4096;
-    while (Q > 64 && vgc_lds_bytes(kind, multi, pf, waves, Q, S, F) + 2048 > lds_cap_block) Q >>= 1;
+    while (Q > 64 && vgc_lds_bytes(kind, multi, pf, waves, Q, S, F) + kStatic > lds_cap_block) Q >>= 1;
     return Q;
   };
   // The LDS filter (distance kinds) may take at most half of the ring it
@@ -270,18 +279,17 @@ int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   const uint32_t Q0 = largest_ring(0);
   uint32_t F = (kind == KIND_REACH) ? 0u : o.filt;
   while (F > 0 && (largest_ring(F) < Q0 / 2 || largest_ring(F) < 64 ||
-                   vgc_lds_bytes(kind, multi, pf, waves, largest_ring(F), S, F) + 2048 > lds_cap_block))
+                   vgc_lds_bytes(kind, multi, pf, waves, largest_ring(F), S, F) + kStatic > lds_cap_block))
     F >>= 1;
   if (F < 16) F = 0;
   const uint32_t Q = largest_ring(F);
-  if (vgc_lds_bytes(kind, multi, pf, waves, Q, S, F) + 2048 > lds_cap_block) return PASGAL_EINVAL;
+  if (vgc_lds_bytes(kind, multi, pf, waves, Q, S, F) + kStatic > lds_cap_block) return PASGAL_EINVAL;
   lg.ring = Q;
   lg.stage = S;
   lg.filt = F;
   lg.block = o.wg;
   lg.pf = pf;
   lg.lds = vgc_lds_bytes(kind, multi, pf, waves, Q, S, F);
-  const void *fn = vgc_kernel_ptr(kind, multi, pf, o.test_first);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lg.lds);
   if (e != hipSuccess) {
     hipGetLastError();
@@ -329,10 +337,11 @@ void fill_stats_from_ctl(const Ctl &c, pasgal_stats *st, bool add) {
   st->max_frontier = std::max<int64_t>(st->max_frontier, c.max_frontier);
 }
 
-// One query (or one mask word) on one CSR, persistent VGC launch.
+// One query (or one mask word) on one CSR, persistent VGC launch. With
+// implications (reach), seed i is source i of the mask word (bit i).
 static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *state, const uint32_t *sv,
                           const unsigned long long *sval, int nseed, const Opts &o, pasgal_stats *st,
-                          bool add_stats, const uint32_t *wgt = nullptr) {
+                          bool add_stats, const uint32_t *wgt = nullptr, bool implications = false) {
   hipStream_t s = o.stream;
   const uint64_t n = (uint64_t)g->n;
   const uint64_t cap = default_cap(o.cap, n);
@@ -349,8 +358,10 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   if ((rc = grow_host(w.h_ctl, sizeof(Ctl)))) return rc;
   const uint32_t hcap = slice_capacity((uint64_t)g->m, o.heavy, cap);
   if ((rc = w.slices.ensure(hcap, false))) return rc;
-  const size_t stage_bytes = sizeof(QInfo) + 2 * sizeof(int64_t) + sizeof(SeedEnt) * (size_t)nseed;
+  const size_t imp_bytes = implications ? 64 * 8 + 64 * 4 : 0;
+  const size_t stage_bytes = sizeof(QInfo) + 2 * sizeof(int64_t) + sizeof(SeedEnt) * (size_t)nseed + imp_bytes;
   if ((rc = grow_host(w.h_stage, stage_bytes))) return rc;
+  if (implications && (rc = grow(w.imp, imp_bytes))) return rc;
   // host staging (pinned) -> device tables
   uint8_t *hs = (uint8_t *)w.h_stage.p;
   QInfo *hq = (QInfo *)hs;
@@ -371,6 +382,18 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
     he[i].v = sv[i];
     he[i].q = 0;
     he[i].val = sval[i];
+  }
+  if (implications) {
+    // sources at the same vertex imply each other from the start
+    unsigned long long *himp = (unsigned long long *)(he + nseed);
+    int32_t *hsrc = (int32_t *)(himp + 64);
+    for (int j = 0; j < 64; j++) {
+      himp[j] = 0ull;
+      hsrc[j] = j < nseed ? (int32_t)sv[j] : -1;
+      for (int i = 0; i < nseed && j < nseed; i++)
+        if (sv[i] == sv[j]) himp[j] |= sval[i];
+    }
+    if ((e = hipMemcpyAsync(w.imp.p, himp, imp_bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e);
   }
   if ((e = hipMemcpyAsync(w.qi.p, hq, sizeof(QInfo), hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpyAsync(w.qword.p, hw, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s)) != hipSuccess)
@@ -407,6 +430,8 @@ static int run_vgc_single(Workspace &w, int kind, const pasgal_csr *g, void *sta
   a.test_first = o.test_first ? 1u : 0u;
   a.filt = lg.filt;  // single query: keys are vertex ids
   a.ctl = (Ctl *)w.ctl.p;
+  a.imp = implications ? (unsigned long long *)w.imp.p : nullptr;
+  a.srcv = implications ? (const int32_t *)((unsigned long long *)w.imp.p + 64) : nullptr;
   w.slices.apply(a, o.heavy, hcap, false);
 
   if ((e = hipEventRecord(w.ev0, s)) != hipSuccess) return hip_fail(e);
@@ -713,7 +738,8 @@ int pasgal_reach_ex(const pasgal_csr *g, const int32_t *sources, int32_t k, uint
     if (o.mode == PASGAL_MODE_PLAIN)
       rc = run_plain(*w, KIND_REACH, g, state, sv.data(), vals.data(), kk, o, stats, true);
     else
-      rc = run_vgc_single(*w, KIND_REACH, g, state, sv.data(), vals.data(), kk, o, stats, true);
+      rc = run_vgc_single(*w, KIND_REACH, g, state, sv.data(), vals.data(), kk, o, stats, true, nullptr,
+                          kk >= 2 && !(o.flags & PASGAL_FLAG_NO_IMPLICATIONS));
     if (rc) return rc;
     if (W > 1) {
       hipError_t e = launch_strided_u64((unsigned long long *)label_out, W, word,

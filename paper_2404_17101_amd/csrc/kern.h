@@ -103,6 +103,12 @@ struct VgcArgs {
                           // two; 0 = off). Keys are 32-bit state indices, so the state must hold < 2^32 values
   long long timeout_ticks;
   Ctl *ctl;
+  // Reach with one query, source implications: srcv[j] is the vertex of
+  // source j (bit j of the mask word), -1 for an unused bit; imp[j] collects
+  // the bits of the sources found to reach srcv[j], which then reach every
+  // vertex that source j reaches. Null imp: not used.
+  unsigned long long *imp;
+  const int32_t *srcv;
   // Heavy rows: an expanded vertex with more than `heavy` out-arcs (0 = never)
   // is cut into slices of `heavy` arcs {v, q, val, first arc}, written to
   // slice buffer (round parity ^ 1) and dealt one per wavefront next round.

@@ -55,6 +55,12 @@ constexpr int QLITE = 64;
 // compiler merges it with the global fallback into a flat load, whose wait
 // also waits for every relaxation in flight.
 typedef __attribute__((address_space(3))) QLite LdsQLite;
+typedef __attribute__((address_space(3))) unsigned long long LdsU64;
+typedef __attribute__((address_space(3))) int32_t LdsI32;
+// Source vertex -> its bits, an open-addressing table of this many slots in
+// LDS (at most 64 sources: load factor at most 1/2).
+constexpr int SRC_SLOTS = 128;
+__device__ __forceinline__ uint32_t src_slot(uint32_t v) { return (v * 0x9E3779B1u) >> 25; }
 
 // Grid barrier for a persistent launch whose workgroups are all resident.
 // Fence-free: callers keep cross-workgroup data in agent-scope atomics.
@@ -110,6 +116,13 @@ struct Wave {
   // relaxations in flight: single-query BFS steps are thin (one pass); reach
   // steps (deep LIFO searches), SSSP steps and multi-query steps are wider.
   static constexpr int RB = (MULTI || KIND != KIND_BFS) ? 4 : 1;
+  // Source implications (reach with one query): when new bits reach the
+  // vertex of source j, the sources behind them reach everything source j
+  // reaches, so bit j implies them. An expansion then propagates the closure
+  // of its mask under the implications known at the start of the round: only
+  // true reachability facts, which let the bits of sources that reach each
+  // other travel together instead of re-expanding each vertex once per bit.
+  static constexpr bool IMPL = (KIND == KIND_REACH && !MULTI);
 
   const VgcArgs &a;
   Val *state;
@@ -123,6 +136,10 @@ struct Wave {
   // state base (recB).
   uint4 *recA;
   uint2 *recB;
+  const LdsU64 *simp;   // closed implications, per workgroup (refreshed every round)
+  const LdsI32 *shk;    // source hash: vertex (-1 = empty slot)
+  const LdsU64 *shv;    // source hash: the bits of the sources at that vertex
+  bool impl_on;
   uint32_t mstamp;  // pass number, tags the arc-owner marks of the current pass
   unsigned long long *filt;  // LDS filter: (32-bit state index << 32) | a value this wavefront saw stored there
   uint32_t fshift;           // slot = (key * golden) >> fshift
@@ -179,6 +196,10 @@ struct Wave {
     slice_ok = 0;
     qlite = nullptr;
     qlite_ok = false;
+    simp = nullptr;
+    shk = nullptr;
+    shv = nullptr;
+    impl_on = false;
     st_expand = st_arcs = st_success = st_publish = st_overflow = st_stale = st_steps = 0;
     st_filt_lane = 0;
   }
@@ -360,7 +381,9 @@ struct Wave {
 
   // ok: the lane holds a dealt arc (lanes without one pass a valid target,
   // so that every load is issued unconditionally; only the atomic is masked).
-  __device__ __forceinline__ Rx relax_issue(bool ok, int64_t sb, uint32_t w, uint32_t wt, Val val) {
+  // cur (TF): the target's state read by a plain load, issued for every pass
+  // before the first atomic.
+  __device__ __forceinline__ Rx relax_issue(bool ok, int64_t sb, uint32_t w, uint32_t wt, Val val, Val cur_tf) {
     Rx x;
     x.nb = x.ne = 0;
     if (DIST) {
@@ -374,7 +397,7 @@ struct Wave {
       bool go = ok;
       uint32_t old = 0xFFFFFFFFu;
       if (TF) {
-        const uint32_t cur = *(const uint32_t *)p;
+        const uint32_t cur = (uint32_t)cur_tf;
         go = go && cur > nd;
         old = cur;
       }
@@ -400,7 +423,7 @@ struct Wave {
       bool go = ok;
       unsigned long long old = 0;
       if (TF) {
-        const unsigned long long cur = *(const unsigned long long *)p;
+        const unsigned long long cur = (unsigned long long)cur_tf;
         go = go && (cur & m) != m;
         old = cur;
       }
@@ -552,15 +575,35 @@ struct Wave {
       w[r] = (uint32_t)a.tgt[arc];
       wt[r] = (KIND == KIND_SSSP) ? a.wgt[arc] : 0u;
     }
+    Val cur[NP];
+#pragma unroll
+    for (int r = 0; r < NP; r++) cur[r] = TF ? *(const Val *)&state[sbo[r] + w[r]] : (Val)0;
     Rx x[NP];
 #pragma unroll
-    for (int r = 0; r < NP; r++) x[r] = relax_issue(okl[r], sbo[r], w[r], wt[r], vo[r]);
+    for (int r = 0; r < NP; r++) x[r] = relax_issue(okl[r], sbo[r], w[r], wt[r], vo[r], cur[r]);
     uint32_t ns = 0;
 #pragma unroll
     for (int r = 0; r < NP; r++) {
       Val nv = 0;
       const bool ok = okl[r] && relax_finish(x[r], (uint32_t)sbo[r] + w[r], vo[r], nv);
       ns += __popcll(__ballot(ok));
+      if (IMPL && impl_on && ok) {
+        // new bits reached w: if w is a source's vertex, record them
+        uint32_t h = src_slot(w[r]);
+        for (int t = 0; t < SRC_SLOTS; t++) {
+          const int32_t key = shk[h];
+          if (key == (int32_t)w[r]) {
+            unsigned long long bits = shv[h];
+            while (bits) {
+              or_ag(&a.imp[__builtin_ctzll(bits)], (unsigned long long)nv);
+              bits &= bits - 1;
+            }
+            break;
+          }
+          if (key < 0) break;
+          h = (h + 1) & (SRC_SLOTS - 1);
+        }
+      }
       push_lim(ok, w[r], qo[r], nv, lim[r], ring_ok, x[r].nb, x[r].ne);
     }
     return ns;
@@ -603,7 +646,21 @@ struct Wave {
       } else if (DIST) {
         ((uint2 *)recA)[ln] = make_uint2(bx, (uint32_t)val);
       } else {
-        recA[ln] = make_uint4(bx, 0u, (uint32_t)val, (uint32_t)((unsigned long long)val >> 32));
+        unsigned long long m = (unsigned long long)val;
+        if (IMPL && impl_on) {
+          // the closure of the entry's bits: a bit already covered needs no
+          // lookup (the table is transitively closed)
+          unsigned long long M = 0, rem = m;
+          while (rem) {
+            M |= simp[__builtin_ctzll(rem)];
+            rem &= ~M;
+          }
+          if (M != m) {  // the implied bits hold at v too
+            or_ag((unsigned long long *)&state[v], M);
+            m = M;
+          }
+        }
+        recA[ln] = make_uint4(bx, 0u, (uint32_t)m, (uint32_t)(m >> 32));
       }
     }
     wave_sync();
@@ -864,6 +921,32 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
   const size_t per_wave = vgc_lds_bytes(KIND, MULTI, PF, 1, a.ring_cap, a.stage_cap, a.filt);
   Wave<KIND, MULTI, PF, TF> wv(a, smem + per_wave * wid);
   __shared__ QLite qlite[MULTI ? QLITE : 1];
+  constexpr bool IMPL = Wave<KIND, MULTI, PF, TF>::IMPL;
+  __shared__ unsigned long long s_imp[IMPL ? 64 : 1];
+  __shared__ int32_t s_hk[IMPL ? SRC_SLOTS : 1];
+  __shared__ unsigned long long s_hv[IMPL ? SRC_SLOTS : 1];
+  const bool impl = IMPL && a.imp != nullptr;
+  if (impl) {
+    if (threadIdx.x < SRC_SLOTS) s_hk[threadIdx.x] = -1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int j = 0; j < 64; j++) {
+        const int32_t v = a.srcv[j];
+        if (v < 0) continue;
+        uint32_t h = src_slot((uint32_t)v);
+        while (s_hk[h] >= 0 && s_hk[h] != v) h = (h + 1) & (SRC_SLOTS - 1);
+        if (s_hk[h] < 0) {
+          s_hk[h] = v;
+          s_hv[h] = 0ull;
+        }
+        s_hv[h] |= 1ull << j;
+      }
+    }
+    wv.simp = (const LdsU64 *)s_imp;
+    wv.shk = (const LdsI32 *)s_hk;
+    wv.shv = (const LdsU64 *)s_hv;
+    wv.impl_on = true;
+  }
   if (MULTI && a.nq <= QLITE) {
     for (int i = threadIdx.x; i < a.nq; i += blockDim.x) {
       qlite[i].sbase = a.qi[i].sbase;
@@ -901,6 +984,20 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
       st_ag(&a.ctl->cnt[fslot], 0u);
       st_ag(&a.ctl->ovf[fslot], 0u);
       st_ag(&a.ctl->hcnt[fslot], 0u);
+    }
+    if (impl) {
+      // implications recorded so far, closed transitively (Warshall, one row
+      // per lane of the first wavefront, rows exchanged by lane reads)
+      if (threadIdx.x < 64) {
+        unsigned long long x = ld_ag(&a.imp[threadIdx.x]) | (1ull << threadIdx.x);
+        for (int k = 0; k < 64; k++) {
+          const unsigned long long yk = ((unsigned long long)lane_read((uint32_t)(x >> 32), k) << 32) |
+                                        lane_read((uint32_t)x, k);
+          if ((x >> k) & 1ull) x |= yk;
+        }
+        s_imp[threadIdx.x] = x;
+      }
+      __syncthreads();
     }
     wv.nslot = nslot;
     wv.nbuf = cbuf ^ 1u;

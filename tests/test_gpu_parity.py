@@ -198,6 +198,41 @@ def test_reach_matches_oracle(pg, k):
         assert np.array_equal(np_mask(got), exp), (k, mode, tau, cap)
 
 
+IMPL_GRAPHS = [("grid80x70", lambda: gg.grid(80, 70)), ("knn30k", lambda: gg.knn(30000, 5, 4)),
+               ("road120", lambda: gg.road(120, 6)), ("rmat13", lambda: gg.rmat(13, 8, 3)),
+               ("dchain3000", lambda: gg.simple("dchain", 3000)),
+               ("dag4000", lambda: _dag(4000, 12000, 5))]
+
+
+def _dag(n, m0, seed):
+    """The arcs u -> w with u < w of a random digraph: a DAG."""
+    r = gg.random_graph(n, m0, seed)
+    u = np.repeat(np.arange(r.n), np.diff(r.offsets))
+    keep = u < r.targets
+    off = np.concatenate([[0], np.cumsum(np.bincount(u[keep], minlength=n))]).astype(np.int32)
+    return gg.Graph(off, r.targets[keep].astype(np.int32), name=f"dag{n}")
+
+
+@pytest.mark.parametrize("name,make", IMPL_GRAPHS, ids=[x[0] for x in IMPL_GRAPHS])
+def test_reach_source_implications(pg, name, make):
+    """Source implications (on by default for several sources): sources that
+    reach each other (grids, the giant component of k-NN), one-way chains of
+    implications (a directed chain, a DAG) and many small components (road);
+    on and off, at several schedules, up to two mask words, and with
+    repeated sources (which imply each other from the start)."""
+    g = make()
+    d = dev(pg, g)
+    for k in [2, 16, 64, 100]:
+        srcs = gg.sources(g, k, 2000 + k)
+        if k == 16:
+            srcs = np.concatenate([srcs, srcs[:3]])
+        exp = oracle.reach(g, srcs)
+        for kw in [dict(), dict(implications=False), dict(tau=1), dict(tau=64, frontier_capacity=100),
+                   dict(test_first=True), dict(test_first=False, prefetch=False), dict(half_device=True, wg_size=512)]:
+            _say(f"implications {name} k={len(srcs)} {kw}")
+            assert np.array_equal(np_mask(pg.reach(d, srcs, **kw)), exp), (k, kw)
+
+
 def test_reach_duplicate_sources_and_families(pg):
     for g in [gg.simple("dchain", 2000), gg.simple("dcycle", 300), gg.simple("empty", 50), gg.knn(3000, 5, 1)]:
         d = dev(pg, g)
