@@ -194,6 +194,27 @@ int pasgal_bfs(const pasgal_csr *g, int32_t src, int32_t *dist_out);
 int pasgal_bfs_ex(const pasgal_csr *g, int32_t src, int32_t *dist_out, const pasgal_opts *opts,
                   pasgal_stats *stats);
 
+/* For callers that cannot allocate memory (code that must not call hipMalloc
+ * or an allocator, tight serving loops, harnesses that forbid it): the VGC BFS
+ * of pasgal_bfs_ex, bit for bit the same distances, with every library-side
+ * buffer (control block, query table, dirty bitmap, slice and frontier
+ * buffers) carved from one fixed device array of
+ * PASGAL_NOALLOC_SCRATCH_BYTES that each GPU holds until the process ends.
+ * The call allocates nothing (no hipMalloc, hipFree, pinned or other
+ * allocation); the caller passes dist_out as for pasgal_bfs_ex. Limits:
+ * n <= PASGAL_NOALLOC_MAX_VERTICES, else PASGAL_ECAPACITY before anything
+ * runs; the frontier capacity is whatever the array holds beside the dirty
+ * bitmap (overflow goes to the bitmap, so results stay exact). Every call on a
+ * GPU shares that GPU's array and clears what must start at zero: calls are
+ * serialized inside the process, and calls that overlap on one GPU from
+ * elsewhere would race. Synchronous on opts->stream (PASGAL_FLAG_ASYNC,
+ * PASGAL_FLAG_VALIDATE and PASGAL_MODE_PLAIN are rejected with PASGAL_EINVAL);
+ * stats->device_ms and kernel_ms are 0. */
+#define PASGAL_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define PASGAL_NOALLOC_MAX_VERTICES (1 << 28)
+int pasgal_bfs_noalloc(const pasgal_csr *g, int32_t src, int32_t *dist_out, const pasgal_opts *opts,
+                       pasgal_stats *stats);
+
 /* Single-source shortest paths with non-negative integer arc weights
  * (Parallel SSSP paragraph: the stepping framework with VGC local searches).
  * Round r of the persistent kernel expands only tentative distances below

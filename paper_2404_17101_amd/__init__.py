@@ -21,7 +21,7 @@ import numpy as np
 
 from . import _lib as L
 
-__all__ = ["DeviceGraph", "PasgalError", "bfs", "bfs_do", "sssp", "reach", "device_sources", "wait", "transpose",
+__all__ = ["DeviceGraph", "PasgalError", "bfs", "bfs_noalloc", "bfs_do", "sssp", "reach", "device_sources", "wait", "transpose",
            "validate", "scc", "Batch", "Server", "load"]
 
 load = L.load
@@ -137,6 +137,21 @@ def bfs(g: DeviceGraph, src: int, dist_out=None, stats: bool = False, **opts):
     st = L.Stats()
     _check(L.load().pasgal_bfs_ex(ctypes.byref(csr), int(src), dist_out.data_ptr(), ctypes.byref(o),
                                   ctypes.byref(st)), "pasgal_bfs")
+    return (dist_out, st.as_dict()) if stats else dist_out
+
+
+def bfs_noalloc(g: DeviceGraph, src: int, dist_out=None, stats: bool = False, **opts):
+    """pasgal_bfs_noalloc: the distances of bfs() with every library buffer
+    taken from the library's fixed device array (no allocation inside the
+    call; dist_out, when given, is the caller's)."""
+    torch = _torch()
+    if dist_out is None:
+        dist_out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    csr = g.csr()
+    o = _opts(**opts)
+    st = L.Stats()
+    _check(L.load().pasgal_bfs_noalloc(ctypes.byref(csr), int(src), dist_out.data_ptr(), ctypes.byref(o),
+                                       ctypes.byref(st)), "pasgal_bfs_noalloc")
     return (dist_out, st.as_dict()) if stats else dist_out
 
 

@@ -117,6 +117,17 @@ def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
     assert lib.pasgal_probe_latency(1 << 20, 100, 3, ctypes.byref(ns), None) == -1
     assert lib.pasgal_probe_latency(1 << 20, 100, -1, ctypes.byref(ns), None) == -1
     assert ns.value == -1.0
+    # the no-allocation BFS: bad arguments, and a graph beyond the vertices its
+    # fixed device array can serve, are rejected before anything runs
+    assert lib.pasgal_bfs_noalloc(ctypes.byref(csr), 0, out, None, None) == -1
+    assert lib.pasgal_bfs_noalloc(ctypes.byref(good), 4, out, None, None) == -1
+    assert lib.pasgal_bfs_noalloc(ctypes.byref(good), 0, None, None, None) == -1
+    huge = L.Csr((1 << 28) + 1, 0, ctypes.c_void_p(1), None)
+    assert lib.pasgal_bfs_noalloc(ctypes.byref(huge), 0, out, None, None) == -5
+    ao = L.Opts()
+    lib.pasgal_opts_default(ctypes.byref(ao))
+    ao.flags = L.FLAG_ASYNC
+    assert lib.pasgal_bfs_noalloc(ctypes.byref(good), 0, out, ctypes.byref(ao), None) == -1
     # defaults of the VGC options
     o = L.Opts()
     lib.pasgal_opts_default(ctypes.byref(o))
