@@ -240,6 +240,8 @@ def main():
     ap.add_argument("--suite", choices=["c1", "c3", "c4", "c5", "scc", "sssp", "bfs_do"], default=None,
                     help="run one of the other configurations instead of the headline job (one JSON line)")
     ap.add_argument("--rates", default="5,10,20,40,100,300,1000,3000,10000", help="c5: Poisson arrival rates (q/s)")
+    ap.add_argument("--server-tau", type=int, default=0, help="c5: the server's local-search budget (0: its default)")
+    ap.add_argument("--slice-rounds", type=int, default=16, help="c5: rounds per server launch")
     ap.add_argument("--summarize-suite-trace", nargs=2, metavar=("SUITE", "DIR"), default=None,
                     help="write profiles/SUITE_trace.md from DIR/prof_SUITE/run_kernel_stats.csv")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,

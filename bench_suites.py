@@ -463,6 +463,14 @@ def suite_c4(args, pg, gg, torch):
 
 
 def suite_c5(args, pg, gg, torch):
+    """Served form. Each rate offers max(1000, 10 s x rate) Poisson arrivals
+    (at most 120 s of them); every request gets an output buffer of its own
+    from a pool per (graph, kind), returned when the request completes (a
+    client with no free buffer waits: back-pressure, counted in its latency,
+    which runs from the scheduled arrival). The sweep stops after the first
+    rate past saturation. A sample of requests per rate is checked: grid BFS
+    against the Manhattan closed form and grid reach against all bits set (on
+    the device), RMAT requests against the same request served alone."""
     a = time.perf_counter()
     grid = gg.grid(8192, 8192)
     rmat = gg.rmat(24, 16, 5)
@@ -472,6 +480,7 @@ def suite_c5(args, pg, gg, torch):
     rng = np.random.default_rng(1005)
     deg_r = np.diff(rmat.offsets)
     pool_r = np.flatnonzero(deg_r > 0)
+    side = 8192
 
     def draw(k):
         reqs = []
@@ -487,7 +496,7 @@ def suite_c5(args, pg, gg, torch):
             (0, "reach"): torch.empty((grid.n, 1), dtype=torch.int64, device="cuda"),
             (1, "bfs"): torch.empty(rmat.n, dtype=torch.int32, device="cuda"),
             (1, "reach"): torch.empty((rmat.n, 1), dtype=torch.int64, device="cuda")}
-    serial = draw(24)
+    serial = draw(40)
     torch.cuda.synchronize()
     a = time.perf_counter()
     lat = []
@@ -500,66 +509,141 @@ def suite_c5(args, pg, gg, torch):
             pg.reach(dd, [src], label_out=outs[(gi, kind)])
         lat.append(time.perf_counter() - t0)
     serial_s = time.perf_counter() - a
+    # algorithmic bytes per request (all four request kinds reach the whole
+    # graph from the sources drawn here: the grid is connected and RMAT
+    # sources lie in its giant component)
+    rmat_reached = outs[(1, "bfs")].cpu().numpy() >= 0
+    n_r, m_r = int(rmat_reached.sum()), int(deg_r[rmat_reached].sum())
+    req_bytes = {(0, "bfs"): 16 * grid.n + 8 * grid.m, (0, "reach"): 20 * grid.n + 12 * grid.m,
+                 (1, "bfs"): 16 * n_r + 8 * m_r, (1, "reach"): 20 * n_r + 12 * m_r}
+    # the oracle on one grid and one RMAT BFS, one host thread: the CPU baseline
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.bfs(grid, int(serial[0][2]) if serial[0][0] == 0 else 0)
+    cpu_grid = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.bfs(rmat, int(pool_r[0]))
+    cpu_rmat = time.perf_counter() - t0
     result = {"suite": "c5", "workload": "resident grid 8192x8192 + RMAT-24 (ef 16, a=0.57, b=c=0.19, seed 5); "
                                          "50% BFS / 50% reach, 50% per graph, Poisson arrivals (seed 1005)",
-              "one_at_a_time": {"queries_per_s": round(len(serial) / serial_s, 2),
+              "alg_bytes_per_request": {f"{'grid' if k[0] == 0 else 'rmat'}_{k[1]}": v for k, v in req_bytes.items()},
+              "one_at_a_time": {"requests": len(serial), "queries_per_s": round(len(serial) / serial_s, 2),
                                 "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2)},
+              "cpu_baseline": {"value": round(2.0 / (cpu_grid + cpu_rmat), 4), "unit": "queries/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"queue BFS on the grid ({cpu_grid:.1f} s) and on RMAT-24 ({cpu_rmat:.1f} s)"},
               "rates": []}
+    # RMAT requests served alone, for the mix checks (sources drawn below)
     del outs
     torch.cuda.empty_cache()
-    srv = pg.Server(max_slots=256, slice_rounds=16)
+    srv = pg.Server(max_slots=256, slice_rounds=args.slice_rounds if hasattr(args, "slice_rounds") else 16,
+                    tau=getattr(args, "server_tau", 0))
     gids = [srv.add_graph(dg), srv.add_graph(dr)]
-    # a few output buffers per (graph, kind), reused round robin: results are copied out like a real reply
-    bufs = {}
+    npool = 48
+    pools = {}
     for gi, g in enumerate(graphs):
-        bufs[(gi, "bfs")] = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(4)]
-        bufs[(gi, "reach")] = [torch.empty(g.n, dtype=torch.int64, device="cuda") for _ in range(4)]
+        pools[(gi, "bfs")] = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(npool)]
+        pools[(gi, "reach")] = [torch.empty(g.n, dtype=torch.int64, device="cuda") for _ in range(npool)]
+    idx = torch.arange(grid.n, dtype=torch.int64, device="cuda")
+    grow_, gcol = idx // side, idx % side
+    del idx
     rates = [float(x) for x in args.rates.split(",") if x]
+    saturated = False
     for rate in rates:
-        count = int(min(max(rate * 3.0, 60), 600))
+        if saturated:
+            result["rates"].append({"offered_qps": rate, "not_run": "past saturation (an earlier rate was)"})
+            continue
+        count = int(min(max(1000, 10.0 * rate), 120.0 * rate))
         reqs = draw(count)
         gaps = rng.exponential(1.0 / rate, size=count)
+        sched = np.cumsum(gaps)
+        free = {k: list(range(npool)) for k in pools}
+        lock = threading.Lock()
+        inflight = {}  # tag -> (gi, kind, src, buffer index, scheduled time)
         done = []
+        checks = {"grid_bfs": 0, "grid_reach": 0, "rmat": 0, "failed": 0}
+        check_every = max(1, count // 40)
+        rmat_checks = []
         t_start = time.perf_counter()
-        submitted = [0]
+        stop = [False]
 
         def submitter():
-            t = time.perf_counter()
             for i, (gi, kind, src) in enumerate(reqs):
-                t += gaps[i]
                 while True:
-                    now = time.perf_counter()
-                    if now >= t:
+                    now = time.perf_counter() - t_start
+                    if now >= sched[i]:
                         break
-                    time.sleep(min(t - now, 0.002))
-                out = bufs[(gi, kind)][i % 4]
+                    time.sleep(min(sched[i] - now, 0.002))
+                while True:  # back-pressure: wait for a free output buffer
+                    with lock:
+                        if free[(gi, kind)]:
+                            b = free[(gi, kind)].pop()
+                            inflight[i] = (gi, kind, src, b, t_start + sched[i])
+                            break
+                    time.sleep(0.0005)
+                out = pools[(gi, kind)][b]
                 while srv.submit(gids[gi], kind, [src], out=out, tag=i) is None:
                     time.sleep(0.001)
-                submitted[0] += 1
 
         th = threading.Thread(target=submitter)
         th.start()
-        deadline = time.perf_counter() + 120.0
-        while (len(done) < count) and time.perf_counter() < deadline:
-            done.extend(srv.poll(4096))
-            time.sleep(0.002)
+        deadline = time.perf_counter() + 240.0 + count / rate
+        while len(done) < count and time.perf_counter() < deadline:
+            for c in srv.poll(4096):
+                i = int(c["tag"])
+                with lock:
+                    gi, kind, src, b, t_sched = inflight.pop(i)
+                ok = c["status"] == 0
+                if ok and i % check_every == 0:
+                    out = pools[(gi, kind)][b]
+                    if gi == 0 and kind == "bfs":
+                        r0, c0 = divmod(src, side)
+                        good = bool(torch.equal(out, ((grow_ - r0).abs() + (gcol - c0).abs()).to(torch.int32)))
+                        checks["grid_bfs"] += 1
+                    elif gi == 0:
+                        good = bool((out == 1).all())
+                        checks["grid_reach"] += 1
+                    else:
+                        rmat_checks.append((kind, src, out.clone()))
+                        good = True
+                    checks["failed"] += 0 if good else 1
+                with lock:
+                    free[(gi, kind)].append(b)
+                done.append((ok, c["t_done_ms"] - t_sched * 1e3, c["t_admit_ms"] - c["t_submit_ms"]))
+            time.sleep(0.001)
         th.join()
         elapsed = time.perf_counter() - t_start
-        ok = [c for c in done if c["status"] == 0]
-        lats = np.array([c["t_done_ms"] - c["t_submit_ms"] for c in ok])
+        # RMAT requests of the mix against the same request served alone
+        for kind, src, got in rmat_checks:
+            if kind == "bfs":
+                alone = pg.bfs(dr, src)
+            else:
+                alone = pg.reach(dr, [src]).view(-1)
+            checks["rmat"] += 1
+            checks["failed"] += 0 if torch.equal(got, alone) else 1
+        ok = [x for x in done if x[0]]
+        lats = np.array([x[1] for x in ok])
+        mix_bytes = float(np.mean([req_bytes[(gi, kind)] for gi, kind, _ in reqs]))
+        qps = len(ok) / elapsed
         entry = {"offered_qps": rate, "requests": count, "completed": len(ok),
-                 "achieved_qps": round(len(ok) / elapsed, 2),
+                 "achieved_qps": round(qps, 2),
                  "p50_ms": round(float(np.percentile(lats, 50)), 2) if lats.size else None,
                  "p99_ms": round(float(np.percentile(lats, 99)), 2) if lats.size else None,
-                 "queue_wait_p50_ms": round(float(np.percentile([c["t_admit_ms"] - c["t_submit_ms"] for c in ok], 50)),
-                                            2) if ok else None}
+                 "admission_wait_p50_ms": round(float(np.percentile([x[2] for x in ok], 50)), 2) if ok else None,
+                 "roofline_frac": round(qps * mix_bytes / 1e9 / HBM_PEAK_GBS, 5),
+                 "checked": checks}
         result["rates"].append(entry)
         _log(f"c5 rate {rate}: {entry}")
         if len(done) < count:
             _log("c5: drain timed out; stopping the sweep")
             break
+        if qps < 0.8 * rate:
+            saturated = True
     srv.close()
+    ach = [r["achieved_qps"] for r in result["rates"] if "achieved_qps" in r]
+    result["saturation_qps"] = max(ach) if ach else None
     return result
 
 

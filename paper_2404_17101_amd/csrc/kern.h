@@ -177,10 +177,11 @@ size_t transpose_scratch_elems(int32_t n);
 
 hipError_t launch_validate(const int32_t *off, const int32_t *tgt, int32_t n, int32_t m, Ctl *ctl, hipStream_t s);
 
-// Per-query frontier census (served form): counts[q] = entries of query q in
-// the frontier; any[q] |= dirty bits of q non-zero.
-hipError_t launch_census(const uint32_t *fq, uint32_t cnt, uint32_t cap, uint32_t *counts, const QInfo *qi,
-                         const int64_t *qword, const uint32_t *dirty, int32_t nq, uint32_t *dirty_any,
-                         hipStream_t s);
+// Per-query census (served form), after a launch: active[q] = 1 when query q
+// has entries in the frontier the launch left (buffer and count read from the
+// control block's exit record on the device) or, when an overflow is
+// pending, dirty bits. active must be zeroed before.
+hipError_t launch_census(const uint32_t *fq0, const uint32_t *fq1, const Ctl *ctl, uint32_t cap, uint32_t *active,
+                         const QInfo *qi, const int64_t *qword, const uint32_t *dirty, int32_t nq, hipStream_t s);
 
 }  // namespace pg

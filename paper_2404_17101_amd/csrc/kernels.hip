@@ -29,6 +29,8 @@
 // arrays are read-only during a launch and use ordinary cached loads.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 #include <type_traits>
 
 #include "devutil.h"
@@ -1442,13 +1444,22 @@ hipError_t launch_validate(const int32_t *off, const int32_t *tgt, int32_t n, in
 
 // ----------------------------------------------------------------- census --
 
-__global__ void census_kernel(const uint32_t *fq, uint32_t cnt, uint32_t *counts, const QInfo *qi,
-                              const int64_t *qword, const uint32_t *dirty, int32_t nq, uint32_t *dirty_any,
-                              int scan_dirty) {
+// The frontier that a launch left behind is read from its control block
+// (exit record) on the device, so the census follows the launch on the
+// stream with no host round trip. A query only needs "has work left": a flag.
+__global__ void census_kernel(const uint32_t *fq0, const uint32_t *fq1, const Ctl *ctl, uint32_t cap,
+                              uint32_t *active, const QInfo *qi, const int64_t *qword, const uint32_t *dirty,
+                              int32_t nq) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = tid; i < cnt; i += stride) add_ag(&counts[fq[i]], 1u);
-  if (scan_dirty) {
+  const uint32_t buf = ld_ag((uint32_t *)&ctl->final_buf);
+  const uint32_t cnt = min(ld_ag((uint32_t *)&ctl->final_cnt), cap);
+  const uint32_t *fq = buf ? fq1 : fq0;
+  for (int64_t i = tid; i < cnt; i += stride) {
+    const uint32_t q = fq[i];
+    if (ld_ag(&active[q]) == 0u) st_ag(&active[q], 1u);
+  }
+  if (ld_ag((uint32_t *)&ctl->final_ovf)) {
     const int64_t words = qword[nq];
     for (int64_t w = tid; w < words; w += stride) {
       int32_t lo = 0, hi = nq - 1;
@@ -1457,21 +1468,15 @@ __global__ void census_kernel(const uint32_t *fq, uint32_t cnt, uint32_t *counts
         if (qword[mid] <= w) lo = mid;
         else hi = mid - 1;
       }
-      if (dirty[qi[lo].dbase + (w - qword[lo])]) st_ag(&dirty_any[lo], 1u);
+      if (dirty[qi[lo].dbase + (w - qword[lo])] && ld_ag(&active[lo]) == 0u) st_ag(&active[lo], 1u);
     }
   }
 }
 
-hipError_t launch_census(const uint32_t *fq, uint32_t cnt, uint32_t cap, uint32_t *counts, const QInfo *qi,
-                         const int64_t *qword, const uint32_t *dirty, int32_t nq, uint32_t *dirty_any,
-                         hipStream_t s) {
+hipError_t launch_census(const uint32_t *fq0, const uint32_t *fq1, const Ctl *ctl, uint32_t cap, uint32_t *active,
+                         const QInfo *qi, const int64_t *qword, const uint32_t *dirty, int32_t nq, hipStream_t s) {
   (void)hipGetLastError();  // report only this launch's error
-  const uint32_t c = cnt < cap ? cnt : cap;
-  int g = (int)((c + 255) / 256);
-  if (g < 64) g = 64;
-  if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(census_kernel, dim3(g), dim3(256), 0, s, fq, c, counts, qi, qword, dirty, nq, dirty_any,
-                     dirty_any != nullptr ? 1 : 0);
+  hipLaunchKernelGGL(census_kernel, dim3(1024), dim3(256), 0, s, fq0, fq1, ctl, cap, active, qi, qword, dirty, nq);
   return hipGetLastError();
 }
 
@@ -1491,31 +1496,41 @@ hipError_t launch_strided_u64(unsigned long long *dst, int stride, int word, con
   return hipGetLastError();
 }
 
-// One block per segment (grid-stride over segments); segments are
-// [seg_off[i], seg_off[i] + seg_len[i]) of base.
+// Segments are [seg_off[i], seg_off[i] + seg_len[i]) of base; `per` blocks
+// share each segment (block b fills part b % per of segment b / per), so a
+// few long segments still spread over the whole device.
 template <class T>
-__global__ void fill_segments_kernel(T *base, const int64_t *seg_off, const int64_t *seg_len, int32_t nseg, T val) {
-  for (int32_t sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
+__global__ void fill_segments_kernel(T *base, const int64_t *seg_off, const int64_t *seg_len, int32_t nseg, T val,
+                                     int32_t per) {
+  const int64_t nblk = (int64_t)nseg * per;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int32_t sgi = (int32_t)(b / per), part = (int32_t)(b % per);
     T *p = base + seg_off[sgi];
     const int64_t len = seg_len[sgi];
-    for (int64_t j = threadIdx.x; j < len; j += blockDim.x) p[j] = val;
+    for (int64_t j = (int64_t)part * blockDim.x + threadIdx.x; j < len; j += (int64_t)per * blockDim.x) p[j] = val;
   }
 }
+
+static int32_t fill_segments_per(int32_t nseg) { return nseg >= 4096 ? 1 : 4096 / nseg; }
 
 hipError_t launch_fill_segments_u32(uint32_t *base, const int64_t *seg_off, const int64_t *seg_len, int32_t nseg,
                                     uint32_t val, hipStream_t s) {
   (void)hipGetLastError();  // report only this launch's error
   if (nseg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_segments_kernel<uint32_t>, dim3(nseg < 65536 ? nseg : 65536), dim3(1024), 0, s, base,
-                     seg_off, seg_len, nseg, val);
+  const int32_t per = fill_segments_per(nseg);
+  const int64_t blocks = std::min<int64_t>((int64_t)nseg * per, 65536);
+  hipLaunchKernelGGL(fill_segments_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, base, seg_off, seg_len,
+                     nseg, val, per);
   return hipGetLastError();
 }
 hipError_t launch_fill_segments_u64(unsigned long long *base, const int64_t *seg_off, const int64_t *seg_len,
                                     int32_t nseg, unsigned long long val, hipStream_t s) {
   (void)hipGetLastError();  // report only this launch's error
   if (nseg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_segments_kernel<unsigned long long>, dim3(nseg < 65536 ? nseg : 65536), dim3(1024), 0, s,
-                     base, seg_off, seg_len, nseg, val);
+  const int32_t per = fill_segments_per(nseg);
+  const int64_t blocks = std::min<int64_t>((int64_t)nseg * per, 65536);
+  hipLaunchKernelGGL(fill_segments_kernel<unsigned long long>, dim3((unsigned)blocks), dim3(256), 0, s, base, seg_off,
+                     seg_len, nseg, val, per);
   return hipGetLastError();
 }
 

@@ -7,13 +7,18 @@
 //    carved from an arena of memory_budget bytes; a request is admitted when
 //    a slot is free and its state fits (first-fit allocator on the host).
 //  * The scheduler thread runs slices: one persistent VGC launch per kind
-//    (BFS, reach) of at most slice_rounds rounds over every admitted request
-//    of that kind. The frontier survives between slices, newly admitted
-//    requests are seeded into it at the slice boundary, and a census of the
-//    frontier (plus the dirty bitmaps when an overflow is pending) tells
-//    which requests have no work left; those are copied to the caller's
-//    buffer, completed and their memory is returned. Requests therefore join
-//    and leave while others are still being traversed on the device.
+//    (BFS, reach), each on its own stream, of at most slice_rounds rounds
+//    over every admitted request of that kind. When both kinds have work,
+//    the two launches run at the same time, each sized to half of every
+//    compute unit; a kind running alone takes the whole device. The frontier
+//    survives between slices, newly admitted requests are seeded into it at
+//    the slice boundary, and a census kernel that follows each launch on its
+//    stream (reading the launch's exit record on the device) flags the
+//    requests that still have work. One copy back and one wait per slice and
+//    kind: finished requests get their result copy enqueued and are
+//    completed, and their memory returned, once the stream has passed the
+//    copy. Requests therefore join and leave while others are still being
+//    traversed on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -100,19 +105,27 @@ struct Req {
 struct Lane {
   int kind = KIND_BFS;
   uint64_t cap = 0;
-  DBuf fv[2], fq[2], fval[2], ctl, qi, qword, seeds, counts, dany;
+  hipStream_t stream = nullptr;
+  // stat: the control block, then one "has work" flag per slot (census)
+  DBuf fv[2], fq[2], fval[2], stat, qi, qword, seeds;
   SliceBufs slices;
-  HBuf h_ctl, h_counts, h_dany, h_stage;
+  HBuf h_stat, h_stage;
   uint32_t cur_buf = 0, cur_cnt = 0, cur_ovf = 0;
   uint32_t round_abs = 0;  // rounds run so far by this lane (BFS window origin of each request)
-  std::vector<Req *> slots;  // slot -> request (nullptr = free)
-  std::vector<Req *> fresh;  // admitted, not yet seeded
+  std::vector<Req *> slots;    // slot -> request (nullptr = free)
+  std::vector<Req *> fresh;    // admitted, not yet seeded
+  std::vector<Req *> copying;  // finished; result copies enqueued on the stream
   std::atomic<int> active{0};
-  LaunchGeom lg;
+  LaunchGeom lg_full, lg_half;
+  bool enqueued = false;  // a slice is in flight on the stream
+  size_t stat_bytes = 0;
+  Ctl *ctl() const { return (Ctl *)stat.p; }
+  uint32_t *flags() const { return (uint32_t *)((uint8_t *)stat.p + ctl_bytes()); }
+  static size_t ctl_bytes() { return (sizeof(Ctl) + 255) & ~(size_t)255; }
   ~Lane() {
-    for (DBuf *b : {&fv[0], &fv[1], &fq[0], &fq[1], &fval[0], &fval[1], &ctl, &qi, &qword, &seeds, &counts, &dany})
-      free_buf(*b);
-    for (HBuf *b : {&h_ctl, &h_counts, &h_dany, &h_stage}) free_hbuf(*b);
+    for (DBuf *b : {&fv[0], &fv[1], &fq[0], &fq[1], &fval[0], &fval[1], &stat, &qi, &qword, &seeds}) free_buf(*b);
+    for (HBuf *b : {&h_stat, &h_stage}) free_hbuf(*b);
+    if (stream) hipStreamDestroy(stream);
   }
 };
 
@@ -120,7 +133,9 @@ struct Lane {
 
 struct pasgal_server {
   pasgal_server_opts opts{};
-  Opts vopts;
+  Opts vopts;       // whole-device slices
+  Opts vopts_half;  // slices that run beside the other kind's, on half of every compute unit
+  bool half_ok = true;
   hipStream_t stream = nullptr;
   int device = 0;
   // resident packed CSR
@@ -152,8 +167,11 @@ struct pasgal_server {
     cv.notify_all();
     if (thr.joinable()) thr.join();
     for (Req *r : submitted) delete r;
-    for (Lane &l : lanes)
+    for (Lane &l : lanes) {
+      if (l.stream) hipStreamSynchronize(l.stream);
       for (Req *r : l.slots) delete r;
+      for (Req *r : l.copying) delete r;
+    }
     free_buf(off);
     free_buf(tgt);
     free_buf(arena);
@@ -230,6 +248,10 @@ struct pasgal_server {
   }
 
   void fail_lane(Lane &L, int status) {
+    if (L.stream) hipStreamSynchronize(L.stream);
+    (void)hipGetLastError();
+    L.enqueued = false;
+    finish_copies(L);
     for (size_t i = 0; i < L.slots.size(); i++)
       if (L.slots[i]) {
         Req *r = L.slots[i];
@@ -243,12 +265,27 @@ struct pasgal_server {
     L.cur_ovf = 0;
   }
 
-  // One slice of one kind. Returns a PASGAL_* code (device errors).
-  int slice(Lane &L) {
-    hipStream_t s = stream;
+  // After a wait on the lane's stream: the result copies enqueued before it
+  // are done, so those requests complete and their memory is returned.
+  void finish_copies(Lane &L) {
+    for (Req *r : L.copying) {
+      alloc.release(r->off, r->bytes);
+      complete(r, PASGAL_OK);
+    }
+    L.copying.clear();
+  }
+
+  // Enqueue one slice of one kind on the lane's stream (no wait): tables,
+  // state of fresh requests, seeds, the persistent launch, the census and one
+  // copy back of the control block and flags. half: the launch runs beside
+  // the other kind's, on half of every compute unit. Returns a PASGAL_* code.
+  int enqueue_slice(Lane &L, bool half) {
+    hipStream_t s = L.stream;
     const int kind = L.kind;
     const int nslots = (int)L.slots.size();
     const size_t es = kind == KIND_BFS ? 4 : 8;
+    const LaunchGeom &lg = half ? L.lg_half : L.lg_full;
+    const Opts &vo = half ? vopts_half : vopts;
     // query tables over all slots (inactive slots own no words)
     std::vector<QInfo> qi(nslots);
     std::vector<int64_t> qword(nslots + 1, 0);
@@ -337,79 +374,85 @@ struct pasgal_server {
     }
     a.fr.cap = (uint32_t)L.cap;
     a.start_buf = L.cur_buf;
-    a.tau = vopts.tau;
+    a.tau = vo.tau;
     a.max_rounds = (uint32_t)opts.slice_rounds;
-    a.ring_cap = L.lg.ring;
-    a.stage_cap = L.lg.stage;
-    a.min_chunk = vopts.min_chunk;
-    a.chunks_per_wave = vopts.cpw;
-    a.window = vopts.window;
+    a.ring_cap = lg.ring;
+    a.stage_cap = lg.stage;
+    a.min_chunk = vo.min_chunk;
+    a.chunks_per_wave = vo.cpw;
+    a.window = vo.window;
     a.round_base = L.round_abs;
-    a.test_first = vopts.test_first ? 1u : 0u;
+    a.test_first = vo.test_first ? 1u : 0u;
     // filter keys are 32-bit state indices: exact only below 2^32 values
-    a.filt = (uint64_t)arena.bytes / es < (1ull << 32) ? L.lg.filt : 0u;
-    a.timeout_ticks = (long long)vopts.timeout_ms * (long long)dev_info().wall_khz;
-    a.ctl = (Ctl *)L.ctl.p;
+    a.filt = (uint64_t)arena.bytes / es < (1ull << 32) ? lg.filt : 0u;
+    a.timeout_ticks = (long long)vo.timeout_ms * (long long)dev_info().wall_khz;
+    a.ctl = L.ctl();
     // a hub may be cut once per request that expands it
-    const uint32_t hcap = slice_capacity((uint64_t)m_total * 8, vopts.heavy, L.cap);
+    const uint32_t hcap = slice_capacity((uint64_t)m_total * 8, vo.heavy, L.cap);
     if (int rc2 = L.slices.ensure(hcap, true)) return rc2;
-    L.slices.apply(a, vopts.heavy, hcap, true);
-    if ((e = launch_fill_u32((uint32_t *)L.ctl.p, sizeof(Ctl) / 4, 0u, s)) != hipSuccess) return hip_fail(e);
+    L.slices.apply(a, vo.heavy, hcap, true);
+    // control block and census flags start at zero
+    if ((e = launch_fill_u32((uint32_t *)L.stat.p, L.stat_bytes / 4, 0u, s)) != hipSuccess) return hip_fail(e);
     if ((e = launch_seed(kind, a, (const SeedEnt *)L.seeds.p, (uint32_t)nseed, L.cur_cnt, L.cur_ovf, s)) !=
         hipSuccess)
       return hip_fail(e);
-    if ((e = launch_vgc(kind, true, L.lg.pf, a, L.lg.grid, L.lg.block, L.lg.lds, coop_launch(vopts), s)) !=
-        hipSuccess)
+    if ((e = launch_vgc(kind, true, lg.pf, a, lg.grid, lg.block, lg.lds, coop_launch(vo), s)) != hipSuccess)
       return hip_fail(e);
-    if ((e = hipMemcpyAsync(L.h_ctl.p, L.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    if ((e = launch_census((const uint32_t *)L.fq[0].p, (const uint32_t *)L.fq[1].p, L.ctl(), (uint32_t)L.cap,
+                           L.flags(), (const QInfo *)L.qi.p, (const int64_t *)L.qword.p, (const uint32_t *)arena.p,
+                           nslots, s)) != hipSuccess)
       return hip_fail(e);
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemcpyAsync(L.h_stat.p, L.stat.p, L.stat_bytes, hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return hip_fail(e);
     L.fresh.clear();
-    const Ctl c = *(const Ctl *)L.h_ctl.p;
+    L.enqueued = true;
+    return PASGAL_OK;
+  }
+
+  // After the wait on the lane's stream: read the slice's exit record and
+  // census, enqueue the result copies of finished requests (they complete
+  // after the next wait) and free their slots.
+  int finish_slice(Lane &L) {
+    L.enqueued = false;
+    const Ctl c = *(const Ctl *)L.h_stat.p;
     if (c.abort) return PASGAL_ETIMEOUT;
     L.cur_buf = c.final_buf;
     L.cur_cnt = c.final_cnt;
     L.cur_ovf = c.final_ovf;
     L.round_abs += c.rounds;
-    for (Req *r : L.slots)
-      if (r) r->rounds += c.rounds;
-    // census: which requests still have frontier entries or dirty bits
-    if ((e = launch_fill_u32((uint32_t *)L.counts.p, (uint64_t)nslots, 0u, s)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_fill_u32((uint32_t *)L.dany.p, (uint64_t)nslots, 0u, s)) != hipSuccess) return hip_fail(e);
-    if (L.cur_cnt > 0 || L.cur_ovf) {
-      if ((e = launch_census((const uint32_t *)L.fq[L.cur_buf].p, L.cur_cnt, (uint32_t)L.cap, (uint32_t *)L.counts.p,
-                             (const QInfo *)L.qi.p, (const int64_t *)L.qword.p, (const uint32_t *)arena.p, nslots,
-                             L.cur_ovf ? (uint32_t *)L.dany.p : nullptr, s)) != hipSuccess)
-        return hip_fail(e);
-    }
-    if ((e = hipMemcpyAsync(L.h_counts.p, L.counts.p, 4 * (size_t)nslots, hipMemcpyDeviceToHost, s)) != hipSuccess)
-      return hip_fail(e);
-    if ((e = hipMemcpyAsync(L.h_dany.p, L.dany.p, 4 * (size_t)nslots, hipMemcpyDeviceToHost, s)) != hipSuccess)
-      return hip_fail(e);
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
-    const uint32_t *cnts = (const uint32_t *)L.h_counts.p, *dany = (const uint32_t *)L.h_dany.p;
-    std::vector<Req *> fin;
-    for (int i = 0; i < nslots; i++) {
+    const uint32_t *flags = (const uint32_t *)((const uint8_t *)L.h_stat.p + Lane::ctl_bytes());
+    const size_t es = L.kind == KIND_BFS ? 4 : 8;
+    hipError_t e;
+    for (size_t i = 0; i < L.slots.size(); i++) {
       Req *r = L.slots[i];
       if (!r) continue;
-      if (cnts[i] == 0 && dany[i] == 0) fin.push_back(r);
-    }
-    if (fin.empty()) return PASGAL_OK;
-    for (Req *r : fin) {
+      r->rounds += c.rounds;
+      if (flags[i]) continue;
       if (r->r.out) {
         if ((e = hipMemcpyAsync(r->r.out, (uint8_t *)arena.p + r->off, es * (size_t)r->nv, hipMemcpyDeviceToDevice,
-                                s)) != hipSuccess)
+                                L.stream)) != hipSuccess)
           return hip_fail(e);
       }
-    }
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
-    for (Req *r : fin) {
-      L.slots[r->slot] = nullptr;
+      L.slots[i] = nullptr;
       L.active--;
-      alloc.release(r->off, r->bytes);
-      complete(r, PASGAL_OK);
+      L.copying.push_back(r);
     }
     return PASGAL_OK;
+  }
+
+  // Wait for the lane's stream; complete the requests whose copies were
+  // enqueued before, and read the slice that was in flight.
+  void wait_lane(Lane &L) {
+    if (!L.enqueued && L.copying.empty()) return;
+    hipError_t e = hipStreamSynchronize(L.stream);
+    if (e != hipSuccess) {
+      fail_lane(L, hip_fail(e));
+      return;
+    }
+    finish_copies(L);
+    if (L.enqueued) {
+      if (int rc = finish_slice(L)) fail_lane(L, rc);
+    }
   }
 
   void loop() {
@@ -418,18 +461,27 @@ struct pasgal_server {
       {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait_for(lk, std::chrono::milliseconds(50), [&] {
-          return stop || !submitted.empty() || lanes[0].active > 0 || lanes[1].active > 0;
+          return stop || !submitted.empty() || lanes[0].active > 0 || lanes[1].active > 0 ||
+                 !lanes[0].copying.empty() || !lanes[1].copying.empty();
         });
         if (stop) return;
       }
       std::lock_guard<std::mutex> g(gpu_mu);
       admit();
-      for (Lane &L : lanes) {
-        if (L.active == 0) continue;
-        int rc = slice(L);
-        if (rc != PASGAL_OK) {
-          hipGetLastError();
-          fail_lane(L, rc);
+      // both kinds with work: their launches run at the same time, each on
+      // half of every compute unit; otherwise one after the other, each on
+      // the whole device
+      const bool both = half_ok && lanes[0].active > 0 && lanes[1].active > 0;
+      if (both) {
+        for (Lane &L : lanes)
+          if (int rc = enqueue_slice(L, true)) fail_lane(L, rc);
+        for (Lane &L : lanes) wait_lane(L);
+      } else {
+        for (Lane &L : lanes) {
+          if (L.active > 0) {
+            if (int rc = enqueue_slice(L, false)) fail_lane(L, rc);
+          }
+          wait_lane(L);
         }
       }
     }
@@ -479,6 +531,11 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
   }
   po.stream = s->stream;
   s->vopts = resolve_opts(&po);
+  // the half-device slices: half the workgroup size (each CU then holds one
+  // workgroup of each kind)
+  s->vopts_half = s->vopts;
+  s->vopts_half.half = true;
+  s->vopts_half.wg = std::max(64, (s->vopts.wg / 2) & ~63);
   int rc = grow(s->arena, (size_t)so.memory_budget);
   if (rc) {
     delete s;
@@ -496,15 +553,18 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
       if (!rc) rc = grow(L.fq[i], 4 * L.cap);
       if (!rc) rc = grow(L.fval[i], 8 * L.cap);
     }
-    if (!rc) rc = grow(L.ctl, sizeof(Ctl));
+    L.stat_bytes = Lane::ctl_bytes() + 4 * (size_t)so.max_slots;
+    if (!rc) rc = grow(L.stat, L.stat_bytes);
     if (!rc) rc = grow(L.qi, sizeof(QInfo) * so.max_slots);
     if (!rc) rc = grow(L.qword, sizeof(int64_t) * (so.max_slots + 1));
-    if (!rc) rc = grow(L.counts, 4 * (size_t)so.max_slots);
-    if (!rc) rc = grow(L.dany, 4 * (size_t)so.max_slots);
-    if (!rc) rc = grow_host(L.h_ctl, sizeof(Ctl));
-    if (!rc) rc = grow_host(L.h_counts, 4 * (size_t)so.max_slots);
-    if (!rc) rc = grow_host(L.h_dany, 4 * (size_t)so.max_slots);
-    if (!rc) rc = vgc_geometry(L.kind, true, s->vopts, L.lg);
+    if (!rc) rc = grow_host(L.h_stat, L.stat_bytes);
+    if (!rc) rc = vgc_geometry(L.kind, true, s->vopts, L.lg_full);
+    // without room for the half-device geometry the kinds take turns
+    if (!rc && vgc_geometry(L.kind, true, s->vopts_half, L.lg_half) != PASGAL_OK) s->half_ok = false;
+    if (!rc) {
+      hipError_t e2 = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+      if (e2 != hipSuccess) rc = hip_fail(e2);
+    }
     if (rc) {
       delete s;
       return rc;
