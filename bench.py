@@ -10,10 +10,11 @@ batch of sources, inputs resident in HBM:
   * reachability from the 16 sources in one VGC launch with 16-bit masks
     (pasgal_reach_ex, k = 16).
 By default (--schedule concurrent) the two launches run at the same time on
-two streams, each sized to half of every compute unit (PASGAL_FLAG_HALF_DEVICE,
-512-thread workgroups): both are latency-bound, and each loses little when
-given half the wavefronts. --schedule sequential runs them one after the
-other on the whole device (1024-thread workgroups).
+two streams, each sized to a share of every compute unit (pasgal_opts
+device_share: 75% and 768-thread workgroups for the BFS batch, 25% and
+256-thread workgroups for reach): both are latency-bound, and each loses
+little when given part of the wavefronts. --schedule sequential runs them
+one after the other on the whole device (1024-thread workgroups).
 value = traversed edges per second (GTEPS): per query, the arcs whose tail the
 source reaches (BFS and reach alike), summed over the 32 queries, over the
 wall time of the timed steps.
@@ -127,13 +128,46 @@ def summarize_suite_trace(suite, d):
         f.write("\n".join(lines) + "\n")
 
 
+def summarize_scc_traces(d):
+    """profiles/scc_trace.md from one traced run of the default pasgal_scc call
+    per graph (DIR/prof_scc_<graph>/run_kernel_stats.csv)."""
+    import csv
+
+    lines = ["# Kernel traces: the default `pasgal_scc` call, one graph per run", "",
+             "Command per graph (GPU host, `TMPDIR=/tmp`, run from `/tmp`):", "", "```",
+             "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_scc_<graph> -o run -- \\",
+             "    python3 <repo>/bench.py --suite scc --scc-graphs <graph> --scc-default-only", "```", "",
+             "Summarised by `python bench.py --summarize-scc-traces <out>`. Each run makes three default calls "
+             "(tau by mean degree, one trimming pass, weak-connectivity split) after one transpose; the shares "
+             "below are of the GPU time of that run.", ""]
+    for graph in ("road4096", "knn10m", "rmat20"):
+        path = os.path.join(d, f"prof_scc_{graph}", "run_kernel_stats.csv")
+        if not os.path.exists(path):
+            continue
+        rows = list(csv.DictReader(open(path)))
+        lines += [f"## {graph}", "", "| kernel | calls | avg (ms) | total (ms) | share |", "|---|---|---|---|---|"]
+        for r in rows[:12]:
+            name = r["Name"].replace("|", "/")
+            if len(name) > 80:
+                name = name[:77] + "..."
+            lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                         f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f}% |")
+        lines.append("")
+    lines.append("`vgc_kernel<1, false, ...>` is the reach kernel running the forward and backward searches of a "
+                 "batch on the packed 2n-vertex graph; `pack_kernel` builds that graph; `select_kernel` draws the "
+                 "pivots; `union_kernel`/`piece_label_kernel` are the weak-connectivity split; `transpose` kernels "
+                 "(`hist_kernel`, `scatter_kernel`, scans) run once per run.")
+    with open(os.path.join(ROOT, "profiles", "scc_trace.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def summarize_profiles(d, args):
     """Turn the rocprofv3 CSVs of the trace, counter and copy-calibration runs
     into the committed summaries under profiles/."""
     import csv
 
     kb = "void pg::vgc_kernel<0, true, false, false>(pg::VgcArgs)"
-    kr = "void pg::vgc_kernel<1, false, true, false>(pg::VgcArgs)"
+    kr = "void pg::vgc_kernel<1, false, true, true>(pg::VgcArgs)"
     cp = "__amd_rocclr_copyBuffer"
     rows = list(csv.DictReader(open(os.path.join(d, "prof_trace", "run_kernel_stats.csv"))))
     F = _counter_means(os.path.join(d, "prof_fetch", "run_counter_collection.csv"))
@@ -145,12 +179,14 @@ def summarize_profiles(d, args):
     traffic_b = F[kb] * 1024 * f_scale + W[kb] * 1024 * w_scale
     traffic_r = F[kr] * 1024 * f_scale + W[kr] * 1024 * w_scale
     avg = {r["Name"]: float(r["AverageNs"]) / 1e6 for r in rows}
-    wg = args.wg if args.wg > 0 else (512 if args.schedule == "concurrent" else 1024)
-    sched = ("the two launches run concurrently on two streams, each on half of every CU "
-             f"({wg}-thread workgroups)" if args.schedule == "concurrent" else
+    conc = args.schedule == "concurrent"
+    wg = args.wg if args.wg > 0 else (max(64, (1024 * args.bfs_share + 3200) // 6400 * 64) if conc else 1024)
+    sched = (f"the two launches run concurrently on two streams, the batch on {args.bfs_share}% of every CU "
+             f"({wg}-thread workgroups) and reach on the rest ({1024 - wg}-thread workgroups, tau "
+             f"{args.reach_tau if args.reach_tau > 0 else 256})" if conc else
              f"the two launches run one after the other ({wg}-thread workgroups)")
     out = {"kernel": kb, "kernel_hash": kernel_source_hash(), "layout": args.layout, "tau": args.tau,
-           "window": args.window, "wg_size": wg, "schedule": args.schedule, "fetch_kib_per_dispatch": round(F[kb], 1), "write_kib_per_dispatch": round(W[kb], 1),
+           "window": args.window, "wg_size": wg, "schedule": args.schedule, "bfs_share": args.bfs_share if conc else 100, "fetch_kib_per_dispatch": round(F[kb], 1), "write_kib_per_dispatch": round(W[kb], 1),
            "copy_calibration": {"fetch_kib_per_1GiB_copy": round(CF[cp], 1), "write_kib_per_1GiB_copy": round(CW[cp], 1),
                                 "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)},
            "hbm_bytes_per_launch": int(traffic_b), "kernel_avg_ms": round(avg.get(kb, 0.0), 4),
@@ -176,8 +212,9 @@ def summarize_profiles(d, args):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                      f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |")
     lines += ["", "`vgc_kernel<0, true, false, false>` is the multi-query BFS kernel (kind 0 = BFS, multi-query, no "
-                  "arc-range prefetch, no row-per-lane path); `vgc_kernel<1, false, true, false>` is the single-query "
-                  "reach kernel with arc-range prefetch (the reach default), run with a 16-bit mask. "
+                  "arc-range prefetch, no test-first read); `vgc_kernel<1, false, true, true>` is the single-query "
+                  "reach kernel with arc-range prefetch and test-first reads (the defaults for 16 sources on this "
+                  "graph) and source implications, run with a 16-bit mask. "
                   "`__amd_rocclr_copyBuffer` dispatches are the graph upload before the timed steps."]
     with open(os.path.join(prof, "vgc_bfs_batched16_knn10m_trace.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -192,7 +229,7 @@ def summarize_profiles(d, args):
              "```", "", "Per dispatch (KiB as reported), averaged over the dispatches of each kernel:", "",
              "| kernel | FETCH_SIZE | WRITE_SIZE | HBM bytes (calibrated) |", "|---|---|---|---|",
              f"| `vgc_kernel<0, true, false, false>` (BFS, 16 queries) | {F[kb]:,.1f} | {W[kb]:,.1f} | {traffic_b / 1e9:.2f} GB |",
-             f"| `vgc_kernel<1, false, true, false>` (reach, k = 16) | {F[kr]:,.1f} | {W[kr]:,.1f} | {traffic_r / 1e9:.2f} GB |",
+             f"| `vgc_kernel<1, false, true, true>` (reach, k = 16) | {F[kr]:,.1f} | {W[kr]:,.1f} | {traffic_r / 1e9:.2f} GB |",
              f"| `{cp}`, 1 GiB copy (calibration) | {CF[cp]:,.1f} | {CW[cp]:,.1f} | 2.15 GB |", "",
              f"Calibration: a plain 1 GiB copy reads and writes 1 GiB; the counters report {CF[cp] / 1048576:.3f} GiB and "
              f"{CW[cp] / 1048576:.3f} GiB, so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.",
@@ -222,9 +259,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tau", type=int, default=1024)
+    ap.add_argument("--reach-tau", type=int, default=0,
+                    help="tau of the reach launch (default 256 under the concurrent schedule, where it measured "
+                         "best on half the device, else --tau)")
     ap.add_argument("--window", type=int, default=0,
                     help="BFS distance window (default 24 concurrent, 32 sequential: measured best for each)")
     ap.add_argument("--wg", type=int, default=0, help="workgroup size (default 512 concurrent, 1024 sequential)")
+    ap.add_argument("--bfs-share", type=int, default=75,
+                    help="concurrent schedule: percent of every compute unit the batched BFS launch takes (the "
+                         "reach launch takes the rest; workgroup sizes follow the shares). 75/25 measured best: "
+                         "79.1 GTEPS against 74.4 at 50/50; the shares between (odd wavefront counts) measured worse")
     ap.add_argument("--schedule", choices=["concurrent", "sequential"], default="concurrent")
     ap.add_argument("--bpc", type=int, default=1)
     ap.add_argument("--prefetch", choices=["auto", "on", "off"], default="auto",
@@ -242,8 +286,12 @@ def main():
     ap.add_argument("--rates", default="5,10,20,40,100,300,1000,3000,10000", help="c5: Poisson arrival rates (q/s)")
     ap.add_argument("--server-tau", type=int, default=0, help="c5: the server's local-search budget (0: its default)")
     ap.add_argument("--slice-rounds", type=int, default=16, help="c5: rounds per server launch")
+    ap.add_argument("--scc-graphs", default="", help="scc: comma list of graphs to run (road4096, knn10m, rmat20)")
+    ap.add_argument("--scc-default-only", action="store_true", help="scc: only the library's default call")
     ap.add_argument("--summarize-suite-trace", nargs=2, metavar=("SUITE", "DIR"), default=None,
                     help="write profiles/SUITE_trace.md from DIR/prof_SUITE/run_kernel_stats.csv")
+    ap.add_argument("--summarize-scc-traces", metavar="DIR", default=None,
+                    help="write profiles/scc_trace.md from DIR/prof_scc_<graph>/run_kernel_stats.csv")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSV output under DIR (prof_trace, prof_fetch, "
                          "prof_write, prof_cfetch, prof_cwrite)")
@@ -256,6 +304,9 @@ def main():
         return
     if args.summarize_suite_trace:
         summarize_suite_trace(*args.summarize_suite_trace)
+        return
+    if args.summarize_scc_traces:
+        summarize_scc_traces(args.summarize_scc_traces)
         return
 
     if args.suite:
@@ -302,11 +353,16 @@ def main():
     stream = torch.cuda.current_stream()
     conc = args.schedule == "concurrent"
     if args.wg <= 0:
-        args.wg = 512 if conc else 1024
+        args.wg = max(64, (1024 * args.bfs_share + 3200) // 6400 * 64) if conc else 1024
+    rwg = 1024 - args.wg if conc else args.wg
     vgc = dict(tau=args.tau, window=args.window, wg_size=args.wg, blocks_per_cu=args.bpc, stream=stream,
-               half_device=conc, prefetch={"auto": None, "on": True, "off": False}[args.prefetch])
+               device_share=args.bfs_share if conc else 0,
+               prefetch={"auto": None, "on": True, "off": False}[args.prefetch])
     rstream = torch.cuda.Stream() if conc else stream  # the reach launch's stream
-    rvgc = dict(vgc, stream=rstream, asynchronous=conc)
+    if args.reach_tau <= 0:
+        args.reach_tau = 256 if conc else args.tau
+    rvgc = dict(vgc, stream=rstream, asynchronous=conc, tau=args.reach_tau, wg_size=rwg,
+                device_share=100 - args.bfs_share if conc else 0)
     srcs_dev = pg.device_sources(srcs, "cuda", rstream)  # pasgal_reach takes a device array
 
     # outputs: 16 distance arrays (one batched launch) and one 16-bit mask word per vertex
@@ -387,7 +443,8 @@ def main():
             pc = json.load(f)
         if (pc.get("kernel_hash") == kernel_source_hash() and pc.get("layout") == args.layout
                 and pc.get("tau") == args.tau and pc.get("window") == args.window
-                and pc.get("wg_size", 1024) == args.wg and pc.get("schedule", "sequential") == args.schedule):
+                and pc.get("wg_size", 1024) == args.wg and pc.get("schedule", "sequential") == args.schedule
+                and pc.get("bfs_share", 100) == (args.bfs_share if conc else 100)):
             traffic = pc.get("hbm_bytes_per_launch")
             traffic_frac = traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS
         else:
@@ -547,10 +604,13 @@ def main():
         "config": {"workload": f"knn5 n={n} m={g.m} points uniform in [0,1)^2 (seed 2, {args.layout} layout), "
                                f"{nq} sources (seed 1002); step = 16 BFS in one batched launch + "
                                f"16-source reach in one launch"
-                               + (", run concurrently on two streams, each on half of every CU" if conc else
+                               + (f", run concurrently on two streams, the batch on {args.bfs_share}% of every CU "
+                                  f"and reach on the rest" if conc else
                                   ", one after the other"),
                    "schedule": args.schedule,
-                   "tau": args.tau, "window": args.window, "wg_size": args.wg, "blocks_per_cu": args.bpc},
+                   "tau": args.tau, "reach_tau": args.reach_tau, "window": args.window, "wg_size": args.wg,
+                   "reach_wg_size": rwg, "bfs_device_share": args.bfs_share if conc else 100,
+                   "blocks_per_cu": args.bpc},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": detail,

@@ -215,6 +215,13 @@ def _cpu_baseline_scc(g):
 def suite_scc(args, pg, gg, torch):
     graphs = [("road4096", lambda: gg.road(4096, 3)), ("knn10m", lambda: gg.knn(10_000_000, 5, 2, layout="morton")),
               ("rmat20", lambda: gg.rmat(20, 16, 5))]
+    only = [x for x in getattr(args, "scc_graphs", "").split(",") if x]
+    if only:
+        graphs = [x for x in graphs if x[0] in only]
+    configs = [("vgc", dict()), ("tau1024", dict(tau=1024)), ("tau1", dict(mode="plain")),
+               ("no_trim", dict(trim_rounds=0)), ("no_split", dict(split=False))]
+    if getattr(args, "scc_default_only", False):
+        configs = configs[:1]
     res = []
     for name, make in graphs:
         g = make()
@@ -230,9 +237,7 @@ def suite_scc(args, pg, gg, torch):
                  "cpu_baseline": {"tarjan_ms": round(cpu_s * 1e3, 1), "cores": 1, "kind": "oracle",
                                   "value": round(cpu_s * 1e3, 1), "unit": "ms per call",
                                   "sample": "one whole call of Tarjan's algorithm"}, "gpu": {}}
-        for label, kw in [("vgc", dict()), ("tau1024", dict(tau=1024)), ("tau1", dict(mode="plain")),
-                          ("no_trim", dict(trim_rounds=0)),
-                          ("no_split", dict(split=False))]:
+        for label, kw in configs:
             ts, st = [], None
             for _ in range(3):
                 torch.cuda.synchronize()

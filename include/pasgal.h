@@ -105,7 +105,9 @@ typedef struct pasgal_csr {
                                        that many do not fit) and launch it as an ordinary kernel, so that a
                                        second such call on another stream runs beside it: the two grids always
                                        fit the device together. A grid that cannot become resident (a third
-                                       launch holding the CUs) ends in PASGAL_ETIMEOUT, never a hang. */
+                                       launch holding the CUs) ends in PASGAL_ETIMEOUT, never a hang. The same
+                                       as pasgal_opts.device_share = 50; two launches whose shares add up to
+                                       at most 100 fit the device together in the same way. */
 
 typedef struct pasgal_opts {
   int32_t mode;              /* PASGAL_MODE_VGC or PASGAL_MODE_PLAIN */
@@ -142,7 +144,12 @@ typedef struct pasgal_opts {
                                 static): on the 5-NN graph smaller chunks thin the local searches more
                                 than the balancing gains (batched 16-source BFS: 29.6 ms at 1, 42.8 ms
                                 at 4). */
-  int32_t reserved;          /* 0 */
+  int32_t device_share;      /* VGC: percent (1..99) of every compute unit the persistent launch may take,
+                                so that another launch sized to the rest runs beside it on another stream:
+                                its workgroups get that share of a CU's LDS and its waves at most that
+                                share of the wave slots its registers allow (PASGAL_EINVAL if they do
+                                not fit), and it is launched as an ordinary kernel. 0 = the whole device
+                                (a cooperative launch), or 50 with PASGAL_FLAG_HALF_DEVICE. */
 } pasgal_opts;
 
 /* Counters of one call (schedule dependent, never part of the result). */
@@ -417,6 +424,12 @@ typedef struct pasgal_server_opts {
   int32_t timeout_ms;
   int32_t window;          /* BFS distance window per round (see pasgal_opts.window); < 0 selects none,
                               0 selects 32 */
+  uint32_t flags;          /* PASGAL_FLAG_TEST_FIRST / PASGAL_FLAG_NO_TEST_FIRST: read a target's state
+                              before each relaxing atomic in every launch. Default: on once a resident
+                              graph has mean out-degree above 8 (there most arcs reach vertices that
+                              already have the value, and a plain read is cheaper than the atomic),
+                              off otherwise. Other bits must be 0. */
+  int32_t reserved;        /* 0 */
 } pasgal_server_opts;
 
 #define PASGAL_REQ_BFS 0

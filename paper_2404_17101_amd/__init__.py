@@ -91,7 +91,8 @@ def _stream_ptr(stream) -> int:
 
 def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0, validate=False, timeout_ms=20000,
           stream=None, asynchronous=False, window=32, min_chunk=1, prefetch=None, test_first=None,
-          heavy_arcs=0, filter_slots=0, chunks_per_wave=0, half_device=False, implications=True) -> L.Opts:
+          heavy_arcs=0, filter_slots=0, chunks_per_wave=0, half_device=False, implications=True,
+          device_share=0) -> L.Opts:
     """tau: local-search budget (0 = the entry point's default: 1024, SSSP and
     SCC on graphs of mean out-degree above 8: 1). window: BFS distance window per
     round (0 or negative = none).
@@ -99,7 +100,8 @@ def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0,
     wavefronts (0 = default 512, negative = never). filter_slots: per-wavefront
     LDS filter of BFS/SSSP relaxations (0 = default 256, negative = off).
     half_device: the persistent launch takes half of every compute unit, so
-    that a second such call on another stream runs beside it. test_first:
+    that a second such call on another stream runs beside it; device_share:
+    the same with any percentage (1..99) of every compute unit. test_first:
     None = the entry point's default (on for reach with several sources on
     graphs of mean degree >= 4 and for SCC on graphs of mean degree > 8),
     True / False = always / never read before the atomic. prefetch: None =
@@ -123,6 +125,7 @@ def _opts(mode="vgc", tau=0, wg_size=1024, blocks_per_cu=1, frontier_capacity=0,
     o.heavy_arcs = int(heavy_arcs)
     o.filter_slots = int(filter_slots)
     o.chunks_per_wave = int(chunks_per_wave)
+    o.device_share = int(device_share)
     return o
 
 
@@ -355,9 +358,12 @@ class Server:
 
     def __init__(self, memory_budget: int = 0, max_slots: int = 0, slice_rounds: int = 0, tau: int = 0,
                  wg_size: int = 0, blocks_per_cu: int = 0, frontier_capacity: int = 0, timeout_ms: int = 0,
-                 window: int = 0):
+                 window: int = 0, test_first=None):
+        """test_first: None = the server's default (on once a resident graph has
+        mean out-degree above 8), True / False = always / never."""
+        flags = 0 if test_first is None else (L.FLAG_TEST_FIRST if test_first else L.FLAG_NO_TEST_FIRST)
         so = L.ServerOpts(int(memory_budget), int(max_slots), int(slice_rounds), int(tau), int(wg_size),
-                          int(blocks_per_cu), int(frontier_capacity), int(timeout_ms), int(window))
+                          int(blocks_per_cu), int(frontier_capacity), int(timeout_ms), int(window), flags, 0)
         h = ctypes.c_void_p()
         _check(L.load().pasgal_server_create(ctypes.byref(so), ctypes.byref(h)), "pasgal_server_create")
         self._h = h

@@ -42,7 +42,8 @@ class Opts(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("frontier_capacity", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("timeout_ms", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("window", ctypes.c_int32), ("min_chunk", ctypes.c_int32), ("heavy_arcs", ctypes.c_int32),
-                ("filter_slots", ctypes.c_int32), ("chunks_per_wave", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("filter_slots", ctypes.c_int32), ("chunks_per_wave", ctypes.c_int32),
+                ("device_share", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -82,7 +83,8 @@ class BatchDesc(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("slice_rounds", ctypes.c_int32),
                 ("tau", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("frontier_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_int32), ("window", ctypes.c_int32)]
+                ("frontier_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

@@ -77,7 +77,8 @@ struct Opts {
   uint32_t heavy = 512;  // 0 = never cut heavy rows
   uint32_t filt = 256;   // LDS filter entries per wavefront wanted (0 = none)
   uint32_t cpw = 1;      // frontier chunks per wavefront and round
-  bool half = false;     // PASGAL_FLAG_HALF_DEVICE
+  int share = 0;         // percent of every CU for a launch beside another (PASGAL_FLAG_HALF_DEVICE: 50);
+                         // 0 = the whole device
 };
 
 // Persistent launches are cooperative where the device supports it, except

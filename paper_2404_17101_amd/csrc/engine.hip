@@ -188,7 +188,7 @@ Opts resolve_opts(const pasgal_opts *o) {
   r.test_first = (o->flags & PASGAL_FLAG_TEST_FIRST) != 0;  // entry points may turn it on by default
   r.heavy = o->heavy_arcs > 0 ? (uint32_t)o->heavy_arcs : (o->heavy_arcs == 0 ? 512u : 0u);
   r.cpw = o->chunks_per_wave > 0 ? (uint32_t)std::min(o->chunks_per_wave, 64) : 1u;
-  r.half = (o->flags & PASGAL_FLAG_HALF_DEVICE) != 0;
+  r.share = o->device_share > 0 ? o->device_share : ((o->flags & PASGAL_FLAG_HALF_DEVICE) ? 50 : 0);
   if (o->filter_slots > 0) {
     uint32_t f = 1;
     while (f * 2 <= (uint32_t)std::min(o->filter_slots, 4096)) f *= 2;  // round down to a power of two
@@ -240,7 +240,7 @@ bool opts_valid(const pasgal_opts *o) {
   if (o->wg_size > 0 && (o->wg_size % 64 != 0 || o->wg_size > 1024)) return false;
   if (o->blocks_per_cu > 32) return false;
   if (o->min_chunk > 64) return false;
-  if (o->reserved != 0) return false;
+  if (o->device_share < 0 || o->device_share > 99) return false;
   return true;
 }
 
@@ -249,14 +249,15 @@ bool csr_valid(const pasgal_csr *g) {
 }
 
 // Persistent-launch geometry for a kernel and LDS budget.
-bool coop_launch(const Opts &o) { return dev_info().coop != 0 && !o.half; }
+bool coop_launch(const Opts &o) { return dev_info().coop != 0 && o.share == 0; }
 
 int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   const DevInfo &di = dev_info();
   const int waves = o.wg / 64;
-  // a half-device launch sizes its workgroups for twice as many per CU
-  const int per_cu = o.half ? 2 * o.bpc : o.bpc;
-  const size_t lds_cap_block = std::min<size_t>(di.lds_per_cu / (size_t)per_cu, di.lds_per_block);
+  // a launch on a share of every CU sizes its workgroups for that share of a
+  // CU's LDS
+  const size_t lds_cu = o.share ? di.lds_per_cu * (size_t)o.share / 100 : di.lds_per_cu;
+  const size_t lds_cap_block = std::min<size_t>(lds_cu / (size_t)o.bpc, di.lds_per_block);
   // dynamic LDS leaves room for the kernel's static arrays (round header,
   // counts, query table or source-implication tables)
   const void *fn = vgc_kernel_ptr(kind, multi, o.prefetch, o.test_first);
@@ -298,7 +299,14 @@ int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, lg.block, lg.lds);
   if (e != hipSuccess) return hip_fail(e);
   if (nb < 1) return PASGAL_EINVAL;
-  if (o.half && nb < per_cu) return PASGAL_EINVAL;  // the other half would not fit beside it
+  if (o.share) {
+    // its waves may take at most its share of the wave slots the kernel's
+    // registers allow, so that the rest is left for the launch beside it
+    int nw = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, fn, 64, 0);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((int64_t)waves * o.bpc * 100 > (int64_t)o.share * nw + 50 || nb < o.bpc) return PASGAL_EINVAL;
+  }
   const int bpc = std::min(nb, o.bpc);
   lg.grid = bpc * di.cus;
   return PASGAL_OK;

@@ -116,7 +116,7 @@ struct Lane {
   std::vector<Req *> fresh;    // admitted, not yet seeded
   std::vector<Req *> copying;  // finished; result copies enqueued on the stream
   std::atomic<int> active{0};
-  LaunchGeom lg_full, lg_half;
+  LaunchGeom lg_full[2], lg_half[2];  // [test-first]
   bool enqueued = false;  // a slice is in flight on the stream
   size_t stat_bytes = 0;
   Ctl *ctl() const { return (Ctl *)stat.p; }
@@ -136,6 +136,7 @@ struct pasgal_server {
   Opts vopts;       // whole-device slices
   Opts vopts_half;  // slices that run beside the other kind's, on half of every compute unit
   bool half_ok = true;
+  bool dense = false;  // a resident graph has mean out-degree above 8
   hipStream_t stream = nullptr;
   int device = 0;
   // resident packed CSR
@@ -284,8 +285,13 @@ struct pasgal_server {
     const int kind = L.kind;
     const int nslots = (int)L.slots.size();
     const size_t es = kind == KIND_BFS ? 4 : 8;
-    const LaunchGeom &lg = half ? L.lg_half : L.lg_full;
-    const Opts &vo = half ? vopts_half : vopts;
+    // test-first: as asked, else once a dense graph is resident
+    const bool tf = (opts.flags & PASGAL_FLAG_TEST_FIRST) ? true
+                    : (opts.flags & PASGAL_FLAG_NO_TEST_FIRST) ? false
+                                                               : dense;
+    const LaunchGeom &lg = half ? L.lg_half[tf] : L.lg_full[tf];
+    Opts vo = half ? vopts_half : vopts;
+    vo.test_first = tf;
     // query tables over all slots (inactive slots own no words)
     std::vector<QInfo> qi(nslots);
     std::vector<int64_t> qword(nslots + 1, 0);
@@ -508,6 +514,10 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
     }
     so.memory_budget = (int64_t)(fr / 4);
   }
+  if ((so.flags & ~(uint32_t)(PASGAL_FLAG_TEST_FIRST | PASGAL_FLAG_NO_TEST_FIRST)) || so.reserved != 0) {
+    delete s;
+    return PASGAL_EINVAL;
+  }
   if (so.max_slots > 4096) {
     delete s;
     return PASGAL_EINVAL;
@@ -534,7 +544,7 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
   // the half-device slices: half the workgroup size (each CU then holds one
   // workgroup of each kind)
   s->vopts_half = s->vopts;
-  s->vopts_half.half = true;
+  s->vopts_half.share = 50;
   s->vopts_half.wg = std::max(64, (s->vopts.wg / 2) & ~63);
   int rc = grow(s->arena, (size_t)so.memory_budget);
   if (rc) {
@@ -558,9 +568,13 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
     if (!rc) rc = grow(L.qi, sizeof(QInfo) * so.max_slots);
     if (!rc) rc = grow(L.qword, sizeof(int64_t) * (so.max_slots + 1));
     if (!rc) rc = grow_host(L.h_stat, L.stat_bytes);
-    if (!rc) rc = vgc_geometry(L.kind, true, s->vopts, L.lg_full);
-    // without room for the half-device geometry the kinds take turns
-    if (!rc && vgc_geometry(L.kind, true, s->vopts_half, L.lg_half) != PASGAL_OK) s->half_ok = false;
+    for (int tf = 0; tf < 2 && !rc; tf++) {
+      Opts full = s->vopts, half = s->vopts_half;
+      full.test_first = half.test_first = tf != 0;
+      rc = vgc_geometry(L.kind, true, full, L.lg_full[tf]);
+      // without room for the half-device geometry the kinds take turns
+      if (!rc && vgc_geometry(L.kind, true, half, L.lg_half[tf]) != PASGAL_OK) s->half_ok = false;
+    }
     if (!rc) {
       hipError_t e2 = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
       if (e2 != hipSuccess) rc = hip_fail(e2);
@@ -620,6 +634,7 @@ int pasgal_server_add_graph(pasgal_server *s, const pasgal_csr *g, int32_t *grap
   s->tgt = ntgt;
   s->n_total = (int32_t)n2;
   s->m_total = (int32_t)m2;
+  if ((int64_t)g->m > 8 * (int64_t)g->n) s->dense = true;
   std::lock_guard<std::mutex> gm(s->graph_mu);
   s->vbase.push_back((int32_t)n2);
   s->ebase.push_back((int32_t)m2);
