@@ -282,9 +282,12 @@ __global__ void __launch_bounds__(256) trim_kernel(const int32_t *__restrict__ o
 
 // Pivots of positions [lo, hi) of the random order: each unsettled vertex
 // draws the next bit of its subproblem's counter; draws >= 64 wait for a
-// repeat of the batch.
+// repeat of the batch. act != null: the batch covers every remaining position
+// (hi = n), and the active vertices act[0, hi) are walked instead of the
+// positions (fewer once most vertices are settled).
 __global__ void __launch_bounds__(256) select_kernel(uint32_t lo, uint32_t hi, uint32_t n, uint32_t h,
-                                                     uint32_t seed, const int32_t *__restrict__ comp,
+                                                     uint32_t seed, const uint32_t *__restrict__ act,
+                                                     const int32_t *__restrict__ comp,
                                                      const uint32_t *__restrict__ loc,
                                                      const uint32_t *__restrict__ label,
                                                      uint32_t *__restrict__ slot_cnt, uint32_t *__restrict__ piv_v,
@@ -297,7 +300,7 @@ __global__ void __launch_bounds__(256) select_kernel(uint32_t lo, uint32_t hi, u
     uint32_t v = 0, bit = 64;
     bool draw = false;
     if (pos < hi) {
-      v = perm_at((uint32_t)pos, n, h, seed);
+      v = act ? act[pos] : perm_at((uint32_t)pos, n, h, seed);
       if (comp[v] < 0) {
         bit = add_ag(&slot_cnt[label[loc[v]]], 1u);
         draw = true;
@@ -824,15 +827,31 @@ extern "C" int pasgal_scc(const pasgal_csr *g, const pasgal_csr *gt, int32_t *co
     return h_ctl->abort == 0;
   };
   for (uint64_t lo = 0, len = 1; lo < n && R.na > 0; lo += len, len *= 2) {
-    const uint32_t hi = (uint32_t)std::min<uint64_t>(n, lo + len);
+    uint32_t hi = (uint32_t)std::min<uint64_t>(n, lo + len);
+    // with the split on, once the next range of positions is more than twice
+    // the number of unsettled vertices, the batch takes every remaining
+    // position and walks the active vertices instead (the result does not
+    // depend on the order); without the split the few large subproblems left
+    // would give at most 64 pivots each per repeat over a range of every
+    // unsettled vertex, so the doubling ranges stay
+    const bool from_active = split && (uint64_t)hi - lo > 2ull * R.na;
+    if (from_active) {
+      hi = (uint32_t)n;
+      len = n;  // the loop ends after this batch and its repeats
+    }
     // every repeat settles at least one vertex of the range (each drawn
     // subproblem's bit-0 pivot), so more repeats than positions is a bug
     for (uint64_t rep = 0;; rep++) {
       if (rep > (uint64_t)(hi - lo)) return PASGAL_EINTERNAL;
       if ((e = launch_fill_u32(ctr, 3, 0u, s)) != hipSuccess) return fail(e);  // NPIV, DEFER, POOL
-      hipLaunchKernelGGL(select_kernel, dim3(grid_for(hi - lo)), dim3(256), 0, s, (uint32_t)lo, hi, n, fh, seed,
-                         (const int32_t *)comp, (const uint32_t *)R.loc(), (const uint32_t *)R.label(), slot_cnt,
-                         piv_v, piv_bit, ctr);
+      if (from_active)
+        hipLaunchKernelGGL(select_kernel, dim3(grid_for(R.na)), dim3(256), 0, s, 0u, R.na, n, fh, seed,
+                           (const uint32_t *)R.act(), (const int32_t *)comp, (const uint32_t *)R.loc(),
+                           (const uint32_t *)R.label(), slot_cnt, piv_v, piv_bit, ctr);
+      else
+        hipLaunchKernelGGL(select_kernel, dim3(grid_for(hi - lo)), dim3(256), 0, s, (uint32_t)lo, hi, n, fh, seed,
+                           (const uint32_t *)nullptr, (const int32_t *)comp, (const uint32_t *)R.loc(),
+                           (const uint32_t *)R.label(), slot_cnt, piv_v, piv_bit, ctr);
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       if ((e = read_counters()) != hipSuccess) return fail(e);
       if (!collect()) return PASGAL_ETIMEOUT;
