@@ -85,6 +85,11 @@ def _counter_means(path):
 
 
 SUITE_TRACES = {
+    "grid": ("Kernel trace: grid suite, first setting only (16 BFS queries in one batched launch on the 8192x8192 "
+             "grid, tau 1024, window 32; one warm-up and three timed launches)",
+             "vgc_kernel<0, true, false, false> is the multi-query BFS kernel (kind 0 = BFS, multi-query, no "
+             "arc-range prefetch, no test-first read); each launch covers all 16 queries. The suite's roofline "
+             "fraction is 16 x (16 n + 8 m) bytes over that kernel's average time."),
     "scc": ("Kernel trace: SCC suite (road4096, knn 10M/5, RMAT-20; VGC, tau 1, no trim, no split; 3 runs each)",
             "vgc_kernel<1, false, true, false> is the reach kernel (arc-range prefetch on, the SCC default) running "
             "the forward and backward searches of a "
@@ -111,7 +116,8 @@ def summarize_suite_trace(suite, d):
     rows = list(csv.DictReader(open(os.path.join(d, f"prof_{suite}", "run_kernel_stats.csv"))))
     lines = [f"# {title}", "", "Command (GPU host, `TMPDIR=/tmp`, run from `/tmp`):", "", "```",
              f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_{suite} -o run -- \\",
-             f"    python3 <repo>/bench.py --suite {suite}", "```", "",
+             f"    python3 <repo>/bench.py --suite {suite}" + (" --grid-default-only" if suite == "grid" else ""),
+             "```", "",
              f"Summarised by `python bench.py --summarize-suite-trace {suite} <out>`. Times include every "
              f"configuration the suite runs; rocprofv3 may end with a segmentation fault in its own exit handler "
              f"after the program's last line, the CSV files were complete.", "",
@@ -242,6 +248,48 @@ def summarize_profiles(d, args):
     print(json.dumps(out, indent=1))
 
 
+SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR "
+               "SQ_ACTIVE_INST_ANY SQ_WAIT_INST_ANY")
+TCC_COUNTERS = "TCC_HIT_sum TCC_MISS_sum TCC_EA0_RDREQ_sum TCC_EA0_ATOMIC_sum"
+
+
+def summarize_pmc(d):
+    """profiles/vgc_bfs_batched16_knn10m_sq.md from the two instruction and L2
+    counter passes (DIR/pmc_sq, DIR/pmc_tcc), per dispatch of each of the two
+    headline kernels."""
+    import collections
+    import csv
+
+    kb = "void pg::vgc_kernel<0, true, false, false>(pg::VgcArgs)"
+    kr = "void pg::vgc_kernel<1, false, true, true>(pg::VgcArgs)"
+    agg = collections.defaultdict(list)
+    for sub in ("pmc_sq", "pmc_tcc"):
+        with open(os.path.join(d, sub, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+    mean = {k: sum(v) / len(v) for k, v in agg.items()}
+    names = SQ_COUNTERS.split() + TCC_COUNTERS.split()
+    lines = ["# Instruction and L2 counters: batched 16-source BFS kernel and 16-source reach kernel "
+             "(10M-point 5-NN graph)", "",
+             "Commands (GPU host, `TMPDIR=/tmp`, run from `/tmp`; one pass per counter block):", "", "```",
+             f"rocprofv3 --pmc {SQ_COUNTERS} \\",
+             "    --output-format csv -d <out>/pmc_sq -o run -- python3 <repo>/bench.py --steps 1 --warmup 1 --no-extras --no-cpu",
+             f"rocprofv3 --pmc {TCC_COUNTERS} \\",
+             "    --output-format csv -d <out>/pmc_tcc -o run -- python3 <repo>/bench.py --steps 1 --warmup 1 --no-extras --no-cpu",
+             "```", "",
+             "Summarised by `python bench.py --summarize-pmc <out>`. Per dispatch, averaged over the dispatches of "
+             "each kernel (the profiler serialises dispatches under counter collection).", "",
+             "| counter | `vgc_kernel<0, true, false, false>` (BFS, 16 queries) | "
+             "`vgc_kernel<1, false, true, true>` (reach, k = 16) |", "|---|---|---|"]
+    for c in names:
+        b, r = mean.get((kb, c)), mean.get((kr, c))
+        fmt = lambda x: "n/a" if x is None else f"{x:,.0f}"
+        lines.append(f"| {c} | {fmt(b)} | {fmt(r)} |")
+    with open(os.path.join(ROOT, "profiles", "vgc_bfs_batched16_knn10m_sq.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -281,15 +329,19 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (counter calibration for rocprofv3 runs)")
-    ap.add_argument("--suite", choices=["c1", "c3", "c4", "c5", "scc", "sssp", "bfs_do"], default=None,
+    ap.add_argument("--suite", choices=["c1", "c3", "c4", "c5", "scc", "sssp", "bfs_do", "grid"], default=None,
                     help="run one of the other configurations instead of the headline job (one JSON line)")
     ap.add_argument("--rates", default="5,10,20,40,100,300,1000,3000,10000", help="c5: Poisson arrival rates (q/s)")
     ap.add_argument("--server-tau", type=int, default=0, help="c5: the server's local-search budget (0: its default)")
     ap.add_argument("--slice-rounds", type=int, default=16, help="c5: rounds per server launch")
     ap.add_argument("--scc-graphs", default="", help="scc: comma list of graphs to run (road4096, knn10m, rmat20)")
     ap.add_argument("--scc-default-only", action="store_true", help="scc: only the library's default call")
+    ap.add_argument("--grid-default-only", action="store_true",
+                    help="grid: only the first setting (tau 1024, window 32), e.g. for a kernel trace")
     ap.add_argument("--summarize-suite-trace", nargs=2, metavar=("SUITE", "DIR"), default=None,
                     help="write profiles/SUITE_trace.md from DIR/prof_SUITE/run_kernel_stats.csv")
+    ap.add_argument("--summarize-pmc", metavar="DIR", default=None,
+                    help="write profiles/vgc_bfs_batched16_knn10m_sq.md from DIR/pmc_sq and DIR/pmc_tcc")
     ap.add_argument("--summarize-scc-traces", metavar="DIR", default=None,
                     help="write profiles/scc_trace.md from DIR/prof_scc_<graph>/run_kernel_stats.csv")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
@@ -304,6 +356,9 @@ def main():
         return
     if args.summarize_suite_trace:
         summarize_suite_trace(*args.summarize_suite_trace)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc)
         return
     if args.summarize_scc_traces:
         summarize_scc_traces(args.summarize_scc_traces)

@@ -1,4 +1,4 @@
-"""The benchmark's other configurations (bench.py --suite c1|c3|c4|c5).
+"""The benchmark's other configurations (bench.py --suite NAME).
 
 Each suite prints one JSON line. All inputs come from the seeded generators;
 all traversal work runs in libpasgal.so through its C ABI.
@@ -22,6 +22,8 @@ all traversal work runs in libpasgal.so through its C ABI.
       Dijkstra (the CPU oracle, one core) timed beside it.
   bfs_do direction-optimizing BFS against the VGC and plain BFS on the served
       RMAT-24 graph and on the 10M-point 5-NN graph.
+  grid 16 BFS queries in one batched launch on the 8192x8192 grid, checked
+      against the Manhattan closed form.
   c5  resident 8192x8192 grid + RMAT scale 24 (edge factor 16, symmetrised):
       Poisson arrivals of BFS / reach requests from random sources, served by
       the continuous-batching server; p50/p99 latency and achieved q/s per
@@ -467,6 +469,59 @@ def suite_c4(args, pg, gg, torch):
             "speedup_batched_vs_plain": round(plain_s * 1e3 / batched_ms, 1)}
 
 
+def suite_grid(args, pg, gg, torch):
+    """16 BFS queries from seeded random sources on the 8192x8192 grid in one
+    batched launch (the served grid's size, run as a batch): every distance
+    checked against the Manhattan closed form on the device; roofline from the
+    launch's own kernel time."""
+    side = 8192
+    a = time.perf_counter()
+    g = gg.grid(side, side)
+    _log(f"grid generated n={g.n} m={g.m} in {time.perf_counter() - a:.1f}s")
+    d = pg.DeviceGraph.from_graph(g)
+    nq = 16
+    srcs = [int(x) for x in gg.sources(g, nq, 1006)]
+    n = g.n
+    dist = torch.empty(n * nq, dtype=torch.int32, device="cuda")
+    idx = torch.arange(n, dtype=torch.int64, device="cuda")
+    grow_, gcol = idx // side, idx % side
+    del idx
+    # every query reaches the whole (connected) grid: 16 B per vertex and 8 B
+    # per arc per query
+    alg = nq * (16 * g.n + 8 * g.m)
+    out = {}
+    for label, kw in [("tau1024_window32", dict(tau=1024, window=32)),
+                      ("tau1024_window64", dict(tau=1024, window=64)),
+                      ("tau4096_window64", dict(tau=4096, window=64)),
+                      ("tau1024_window16", dict(tau=1024, window=16))][:1 if getattr(args, "grid_default_only", False)
+                                                                         else None]:
+        batch = pg.Batch(d, np.array([0, n], dtype=np.int32), np.zeros(nq, np.int32), np.array(srcs, np.int32),
+                         np.arange(nq, dtype=np.int64) * n, dist, **kw)
+        batch.run()  # warm-up
+        ks, ts, st = [], [], None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = batch.run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            ks.append(st["kernel_ms"])
+        batch.close()
+        dv = dist.view(nq, n)
+        good = all(bool(torch.equal(dv[i], ((grow_ - srcs[i] // side).abs() + (gcol - srcs[i] % side).abs())
+                                    .to(torch.int32))) for i in range(nq))
+        kms, t = float(np.median(ks)), float(np.median(ts))
+        out[label] = {"ms": round(t * 1e3, 3), "kernel_ms": round(kms, 3), "gteps": round(nq * g.m / t / 1e9, 3),
+                      "rounds": st["rounds"], "expansions_per_reached": round(st["expansions"] / (nq * g.n), 4),
+                      "roofline_frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                      "matches_closed_form": good}
+        _log(f"grid {label}: {out[label]}")
+    return {"suite": "grid", "workload": f"4-neighbour grid {side}x{side} (n={g.n}, m={g.m}), {nq} BFS queries "
+                                         f"from seeded random sources (seed 1006) in one batched launch",
+            "alg_bytes_per_launch": alg, "results": out,
+            "cpu_baseline": _cpu_bfs(g, srcs, None, getattr(args, "cpu_seconds", 15.0))}
+
+
 def suite_c5(args, pg, gg, torch):
     """Served form. Each rate offers max(1000, 10 s x rate) Poisson arrivals
     (at most 120 s of them); every request gets an output buffer of its own
@@ -661,6 +716,6 @@ def run(name, args):
     pg.load()
     torch.cuda.set_device(0)
     fn = {"c1": suite_c1, "c3": suite_c3, "c4": suite_c4, "c5": suite_c5, "scc": suite_scc, "sssp": suite_sssp,
-          "bfs_do": suite_bfs_do}[name]
+          "bfs_do": suite_bfs_do, "grid": suite_grid}[name]
     out = fn(args, pg, gg, torch)
     print(json.dumps(out), flush=True)
