@@ -428,9 +428,23 @@ typedef struct pasgal_server_opts {
                               before each relaxing atomic in every launch. Default: on once a resident
                               graph has mean out-degree above 8 (there most arcs reach vertices that
                               already have the value, and a plain read is cheaper than the atomic),
-                              off otherwise. Other bits must be 0. */
+                              off otherwise. PASGAL_SERVER_FIXED_SLICES,
+                              PASGAL_SERVER_NO_DIRECTION_OPT: see there. Other bits must be 0. */
   int32_t reserved;        /* 0 */
 } pasgal_server_opts;
+
+/* Server flag: every launch runs at most slice_rounds rounds. By default a launch made while exactly one
+   request is resident and none is queued runs until that request finishes or another request is
+   submitted (the launch polls a word in coherent host memory once per round and ends at the next round
+   boundary), so that a request served alone pays no per-slice host round trips. */
+#define PASGAL_SERVER_FIXED_SLICES 65536u
+/* Server flag: BFS requests on every graph go through the batched VGC launches. By default a graph added
+   with mean out-degree above 8 (m > 8n: low diameter, where top-down levels scan most arcs) gets a copy of
+   itself and of its transpose in server memory (4(n+1) + 4m bytes each, built once by pasgal_server_
+   add_graph), and its BFS requests are served one at a time by the direction-optimizing BFS
+   (pasgal_bfs_do, default alpha and beta) on a stream of the server's own, between the batched launches;
+   their completions report levels as rounds. Reach requests always use the batched launches. */
+#define PASGAL_SERVER_NO_DIRECTION_OPT 131072u
 
 #define PASGAL_REQ_BFS 0
 #define PASGAL_REQ_REACH 1

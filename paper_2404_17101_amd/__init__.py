@@ -358,10 +358,18 @@ class Server:
 
     def __init__(self, memory_budget: int = 0, max_slots: int = 0, slice_rounds: int = 0, tau: int = 0,
                  wg_size: int = 0, blocks_per_cu: int = 0, frontier_capacity: int = 0, timeout_ms: int = 0,
-                 window: int = 0, test_first=None):
+                 window: int = 0, test_first=None, fixed_slices: bool = False, direction_optimizing: bool = True):
         """test_first: None = the server's default (on once a resident graph has
-        mean out-degree above 8), True / False = always / never."""
+        mean out-degree above 8), True / False = always / never. fixed_slices:
+        every launch runs at most slice_rounds rounds, also for a request
+        served alone. direction_optimizing: BFS requests on graphs with mean
+        out-degree above 8 are served by the direction-optimizing BFS (False:
+        by the batched launches, like every other request)."""
         flags = 0 if test_first is None else (L.FLAG_TEST_FIRST if test_first else L.FLAG_NO_TEST_FIRST)
+        if fixed_slices:
+            flags |= L.SERVER_FIXED_SLICES
+        if not direction_optimizing:
+            flags |= L.SERVER_NO_DIRECTION_OPT
         so = L.ServerOpts(int(memory_budget), int(max_slots), int(slice_rounds), int(tau), int(wg_size),
                           int(blocks_per_cu), int(frontier_capacity), int(timeout_ms), int(window), flags, 0)
         h = ctypes.c_void_p()

@@ -17,6 +17,8 @@ MODE_VGC, MODE_PLAIN = 0, 1
 FLAG_VALIDATE, FLAG_ASYNC, FLAG_PREFETCH, FLAG_TEST_FIRST, FLAG_HALF_DEVICE, FLAG_NO_TEST_FIRST = 1, 2, 4, 8, 32, 64
 FLAG_NO_PREFETCH = 128
 FLAG_NO_IMPLICATIONS = 256
+SERVER_FIXED_SLICES = 65536
+SERVER_NO_DIRECTION_OPT = 131072
 BATCH_AUTOTUNE = 1
 REQ_BFS, REQ_REACH = 0, 1
 

@@ -63,7 +63,7 @@ struct Ctl {
   uint32_t bad_csr;   // validation result
   uint32_t hcnt[3];   // heavy-row slices: round r reads hcnt[r%3], appends to hcnt[(r+1)%3]
   uint32_t claim[3][8];  // frontier chunks claimed in round r, per XCD: claim[r%3][xcd]
-  uint32_t pad[1];
+  uint32_t yld[3];    // yld[(r+1)%3] != 0: a yield request was seen in round r (launches with a yield word)
   unsigned long long stats[8];
 };
 
@@ -118,6 +118,13 @@ struct VgcArgs {
   uint32_t *hq[2];
   unsigned long long *hval[2];
   int32_t *hb[2];
+  // Yield word (null: none): a host-written word in coherent host memory.
+  // When it differs from yield_base the launch ends at the next round
+  // boundary with no heavy-row slices pending, with its exit record written
+  // as if max_rounds had been reached, so that the caller can add work and
+  // continue from the frontier it left.
+  const uint32_t *yield;
+  uint32_t yield_base;
 };
 
 // Initial frontier entries for a launch (host-built, uploaded).

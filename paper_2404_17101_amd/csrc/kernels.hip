@@ -42,7 +42,7 @@ namespace pg {
 // Round state every workgroup needs after a barrier; read once per
 // workgroup by thread 0 and broadcast through LDS.
 struct RoundHdr {
-  uint32_t ncur, ovf, nheavy, abort;
+  uint32_t ncur, ovf, nheavy, abort, yld;
 };
 
 // The per-query fields a step reads (state base, window origin), copied to
@@ -89,6 +89,7 @@ __device__ void grid_barrier(Ctl *ctl, uint32_t &epoch, long long deadline, uint
     hdr->ncur = ld_ag(&ctl->cnt[slot]);
     hdr->ovf = ld_ag(&ctl->ovf[slot]);
     hdr->nheavy = ld_ag(&ctl->hcnt[slot]);
+    hdr->yld = ld_ag(&ctl->yld[slot]);
   }
   __syncthreads();
 }
@@ -977,8 +978,12 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
   uint32_t maxf = 0;
   uint32_t r = 0;
   uint32_t nheavy = 0;
+  bool yielded = false;  // the previous round saw a yield request (the same in every workgroup)
+  uint32_t ysnap = 0;    // workgroup 0, thread 0: the yield word as read at the start of the round
   for (; r < a.max_rounds; ++r) {
     if (ncur == 0 && ovf == 0 && nheavy == 0) break;
+    // a yield ends the launch here unless slices cut last round are pending
+    if (yielded && nheavy == 0) break;
     maxf = max(maxf, ncur);
     const uint32_t nslot = (r + 1) % 3, fslot = (r + 2) % 3;
     if (blockIdx.x == 0 && threadIdx.x < 8) st_ag(&a.ctl->claim[fslot][threadIdx.x], 0u);
@@ -986,6 +991,9 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
       st_ag(&a.ctl->cnt[fslot], 0u);
       st_ag(&a.ctl->ovf[fslot], 0u);
       st_ag(&a.ctl->hcnt[fslot], 0u);
+      st_ag(&a.ctl->yld[fslot], 0u);
+      // issued now, used before the barrier: the host read overlaps the round
+      if (a.yield) ysnap = __hip_atomic_load(a.yield, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (impl) {
       // implications recorded so far, closed transitively (Warshall, one row
@@ -1015,11 +1023,13 @@ __global__ void __launch_bounds__(1024) vgc_kernel(VgcArgs a) {
     chunk = min(max(chunk, max(a.min_chunk, 1u)), a.ring_cap / 2);
     wv.process_frontier(cbuf, nproc, chunk, gw, total_waves, r % 3);
     wv.flush_stage_block(s_cnt, wid, nw);
+    if (a.yield && blockIdx.x == 0 && threadIdx.x == 0 && ysnap != a.yield_base) st_ag(&a.ctl->yld[nslot], 1u);
     grid_barrier(a.ctl, epoch, deadline, nslot, &hdr);
     if (hdr.abort) break;
     ncur = hdr.ncur;
     ovf = hdr.ovf;
     nheavy = hdr.nheavy;
+    yielded = a.yield != nullptr && hdr.yld != 0u;
     cbuf ^= 1u;
   }
   wv.flush_stats();

@@ -12,7 +12,10 @@
 //    the two launches run at the same time, each sized to half of every
 //    compute unit; a kind running alone takes the whole device. The frontier
 //    survives between slices, newly admitted requests are seeded into it at
-//    the slice boundary, and a census kernel that follows each launch on its
+//    the slice boundary (a launch made while a single request is resident and
+//    none is queued runs until it finishes, or until a submission changes a
+//    word in coherent host memory that the launch polls once per round), and
+//    a census kernel that follows each launch on its
 //    stream (reading the launch's exit record on the device) flags the
 //    requests that still have work. One copy back and one wait per slice and
 //    kind: finished requests get their result copy enqueued and are
@@ -37,6 +40,12 @@
 #include "engine.h"
 #include "kern.h"
 #include "pasgal.h"
+
+// BFS requests on low-diameter graphs (mean out-degree above 8) do not join
+// the batched launches: the loop serves them one at a time with the
+// direction-optimizing BFS on a stream of its own, while no batched launch is
+// in flight, from copies of the graph and of its transpose that
+// pasgal_server_add_graph makes.
 
 using namespace pg;
 
@@ -93,6 +102,7 @@ struct Arena {
 struct Req {
   int64_t id = 0;
   pasgal_request r{};
+  bool dobfs = false;  // served by the direction-optimizing BFS
   double t_submit = 0, t_admit = 0;
   int64_t rounds = 0;
   int slot = -1;
@@ -129,6 +139,17 @@ struct Lane {
   }
 };
 
+// A resident graph's own copy (local vertex ids) and its transpose, kept for
+// direction-optimizing BFS requests.
+struct DoGraph {
+  bool on = false;
+  int32_t n = 0, m = 0;
+  DBuf off, tgt, toff, ttgt;
+  ~DoGraph() {
+    for (DBuf *b : {&off, &tgt, &toff, &ttgt}) free_buf(*b);
+  }
+};
+
 }  // namespace
 
 struct pasgal_server {
@@ -145,10 +166,16 @@ struct pasgal_server {
   std::mutex graph_mu;            // guards vbase/ebase
   std::vector<int32_t> vbase{0};
   std::vector<int32_t> ebase{0};
+  std::vector<uint8_t> dobfs;     // per graph: BFS requests use the direction-optimizing BFS
   // request state arena
   DBuf arena;
   Arena alloc;
   Lane lanes[2];
+  // direction-optimizing BFS requests (admitted, in arrival order)
+  std::vector<std::unique_ptr<DoGraph>> dograph;  // per graph id
+  std::deque<Req *> do_q;
+  std::atomic<int> do_active{0};  // admitted direction-optimizing requests not yet completed
+  hipStream_t do_stream = nullptr;
   // queues
   std::mutex mu;
   std::condition_variable cv, cv_done;
@@ -159,12 +186,16 @@ struct pasgal_server {
   bool stop = false;
   std::thread thr;
   std::mutex gpu_mu;             // serializes device work (graph adds vs loop)
+  // yield word: bumped by every submission, polled by long launches
+  uint32_t *h_yield = nullptr;   // coherent pinned host memory
+  const uint32_t *d_yield = nullptr;
 
   ~pasgal_server() {
     {
       std::lock_guard<std::mutex> lk(mu);
       stop = true;
     }
+    if (h_yield) __atomic_fetch_add(h_yield, 1u, __ATOMIC_SEQ_CST);  // end a long launch now
     cv.notify_all();
     if (thr.joinable()) thr.join();
     for (Req *r : submitted) delete r;
@@ -173,9 +204,16 @@ struct pasgal_server {
       for (Req *r : l.slots) delete r;
       for (Req *r : l.copying) delete r;
     }
+    for (Req *r : do_q) delete r;
+    if (do_stream) {
+      hipStreamSynchronize(do_stream);
+      hipStreamDestroy(do_stream);
+    }
+    dograph.clear();
     free_buf(off);
     free_buf(tgt);
     free_buf(arena);
+    if (h_yield) hipHostFree(h_yield);
     if (stream) hipStreamDestroy(stream);
   }
 
@@ -199,23 +237,29 @@ struct pasgal_server {
   }
 
   int64_t state_bytes(const Req *r) const {
+    if (r->dobfs) return r->r.out ? 0 : 4 * (int64_t)r->nv;  // distances only, when the caller keeps none
     const int64_t es = r->r.kind == PASGAL_REQ_BFS ? 4 : 8;
     const int64_t words = ((int64_t)r->nv + 31) / 32;
     return ((es * r->nv + 255) & ~(int64_t)255) + 4 * words;
   }
 
-  // Admit queued requests while slots and memory allow (FIFO, head-of-line).
+  // Admit queued requests while slots and memory allow (FIFO, head-of-line),
+  // under the queue lock, so that every request counts as queued or as
+  // admitted at any time.
   void admit() {
-    std::deque<Req *> q;
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      q.swap(submitted);
-    }
-    std::deque<Req *> back;
-    bool blocked = false;
-    for (Req *r : q) {
-      if (blocked) {
-        back.push_back(r);
+    std::lock_guard<std::mutex> lk(mu);
+    while (!submitted.empty()) {
+      Req *r = submitted.front();
+      if (r->dobfs) {
+        const int64_t bytes = state_bytes(r);
+        const int64_t o = bytes > 0 ? alloc.alloc(bytes) : 0;
+        if (o < 0) break;
+        submitted.pop_front();
+        r->off = bytes > 0 ? o : -1;
+        r->bytes = bytes;
+        r->t_admit = now_ms();
+        do_q.push_back(r);
+        do_active++;
         continue;
       }
       Lane &L = lanes[r->r.kind == PASGAL_REQ_BFS ? 0 : 1];
@@ -226,12 +270,9 @@ struct pasgal_server {
           break;
         }
       const int64_t bytes = state_bytes(r);
-      int64_t o = slot >= 0 ? alloc.alloc(bytes) : -1;
-      if (slot < 0 || o < 0) {
-        blocked = true;  // keep arrival order: later requests wait too
-        back.push_back(r);
-        continue;
-      }
+      const int64_t o = slot >= 0 ? alloc.alloc(bytes) : -1;
+      if (o < 0) break;  // keep arrival order: later requests wait too
+      submitted.pop_front();
       r->off = o;
       r->bytes = bytes;
       const int64_t es = r->r.kind == PASGAL_REQ_BFS ? 4 : 8;
@@ -241,10 +282,6 @@ struct pasgal_server {
       L.slots[slot] = r;
       L.fresh.push_back(r);
       L.active++;
-    }
-    if (!back.empty()) {
-      std::lock_guard<std::mutex> lk(mu);
-      for (auto it = back.rbegin(); it != back.rend(); ++it) submitted.push_front(*it);
     }
   }
 
@@ -279,8 +316,10 @@ struct pasgal_server {
   // Enqueue one slice of one kind on the lane's stream (no wait): tables,
   // state of fresh requests, seeds, the persistent launch, the census and one
   // copy back of the control block and flags. half: the launch runs beside
-  // the other kind's, on half of every compute unit. Returns a PASGAL_* code.
-  int enqueue_slice(Lane &L, bool half) {
+  // the other kind's, on half of every compute unit. lone: the launch runs
+  // until its work is done or the yield word differs from ybase. Returns a
+  // PASGAL_* code.
+  int enqueue_slice(Lane &L, bool half, bool lone = false, uint32_t ybase = 0) {
     hipStream_t s = L.stream;
     const int kind = L.kind;
     const int nslots = (int)L.slots.size();
@@ -381,7 +420,11 @@ struct pasgal_server {
     a.fr.cap = (uint32_t)L.cap;
     a.start_buf = L.cur_buf;
     a.tau = vo.tau;
-    a.max_rounds = (uint32_t)opts.slice_rounds;
+    a.max_rounds = lone ? 0x40000000u : (uint32_t)opts.slice_rounds;
+    if (lone) {
+      a.yield = d_yield;
+      a.yield_base = ybase;
+    }
     a.ring_cap = lg.ring;
     a.stage_cap = lg.stage;
     a.min_chunk = vo.min_chunk;
@@ -446,6 +489,24 @@ struct pasgal_server {
     return PASGAL_OK;
   }
 
+  // One direction-optimizing BFS request, start to finish (synchronous).
+  void run_do(Req *r) {
+    const DoGraph &G = *dograph[r->r.graph];
+    pasgal_csr g{G.n, G.m, (const int32_t *)G.off.p, (const int32_t *)G.tgt.p};
+    pasgal_csr gt{G.n, G.m, (const int32_t *)G.toff.p, (const int32_t *)G.ttgt.p};
+    pasgal_opts po;
+    pasgal_opts_default(&po);
+    po.stream = do_stream;
+    po.timeout_ms = opts.timeout_ms;
+    int32_t *dist = r->r.out ? (int32_t *)r->r.out : (int32_t *)((uint8_t *)arena.p + r->off);
+    pasgal_stats st{};
+    const int rc = pasgal_bfs_do(&g, &gt, r->r.sources[0], dist, 0, 0, &po, &st);
+    r->rounds = st.rounds;
+    if (r->bytes > 0) alloc.release(r->off, r->bytes);
+    do_active--;
+    complete(r, rc);
+  }
+
   // Wait for the lane's stream; complete the requests whose copies were
   // enqueued before, and read the slice that was in flight.
   void wait_lane(Lane &L) {
@@ -468,12 +529,21 @@ struct pasgal_server {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait_for(lk, std::chrono::milliseconds(50), [&] {
           return stop || !submitted.empty() || lanes[0].active > 0 || lanes[1].active > 0 ||
-                 !lanes[0].copying.empty() || !lanes[1].copying.empty();
+                 !lanes[0].copying.empty() || !lanes[1].copying.empty() || !do_q.empty();
         });
         if (stop) return;
       }
       std::lock_guard<std::mutex> g(gpu_mu);
+      // read before admitting: a submission after this point ends a long launch
+      const uint32_t ybase = __atomic_load_n(h_yield, __ATOMIC_SEQ_CST);
       admit();
+      bool queued;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        queued = !submitted.empty();
+      }
+      const bool lone = !(opts.flags & PASGAL_SERVER_FIXED_SLICES) && !queued && do_q.empty() &&
+                        lanes[0].active + lanes[1].active == 1;
       // both kinds with work: their launches run at the same time, each on
       // half of every compute unit; otherwise one after the other, each on
       // the whole device
@@ -485,10 +555,19 @@ struct pasgal_server {
       } else {
         for (Lane &L : lanes) {
           if (L.active > 0) {
-            if (int rc = enqueue_slice(L, false)) fail_lane(L, rc);
+            if (int rc = enqueue_slice(L, false, lone, ybase)) fail_lane(L, rc);
           }
           wait_lane(L);
         }
+      }
+      // direction-optimizing BFS requests, with no batched launch in flight:
+      // all of them while the batched lanes are idle, else one per slice
+      const bool lanes_idle = lanes[0].active == 0 && lanes[1].active == 0;
+      while (!do_q.empty()) {
+        Req *r = do_q.front();
+        do_q.pop_front();
+        run_do(r);
+        if (!lanes_idle) break;
       }
     }
   }
@@ -514,7 +593,9 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
     }
     so.memory_budget = (int64_t)(fr / 4);
   }
-  if ((so.flags & ~(uint32_t)(PASGAL_FLAG_TEST_FIRST | PASGAL_FLAG_NO_TEST_FIRST)) || so.reserved != 0) {
+  if ((so.flags & ~(uint32_t)(PASGAL_FLAG_TEST_FIRST | PASGAL_FLAG_NO_TEST_FIRST | PASGAL_SERVER_FIXED_SLICES |
+                              PASGAL_SERVER_NO_DIRECTION_OPT)) ||
+      so.reserved != 0) {
     delete s;
     return PASGAL_EINVAL;
   }
@@ -536,6 +617,23 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
   }
   hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e);
+  }
+  void *hy = nullptr;
+  if ((e = hipHostMalloc(&hy, 256, hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess) {
+    delete s;
+    return hip_fail(e);
+  }
+  s->h_yield = (uint32_t *)hy;
+  *s->h_yield = 0;
+  void *dy = nullptr;
+  if ((e = hipHostGetDevicePointer(&dy, hy, 0)) != hipSuccess) {
+    delete s;
+    return hip_fail(e);
+  }
+  s->d_yield = (const uint32_t *)dy;
+  if ((e = hipStreamCreateWithFlags(&s->do_stream, hipStreamNonBlocking)) != hipSuccess) {
     delete s;
     return hip_fail(e);
   }
@@ -628,16 +726,55 @@ int pasgal_server_add_graph(pasgal_server *s, const pasgal_csr *g, int32_t *grap
     free_buf(ntgt);
     return hip_fail(e);
   }
+  // low-diameter graph: own copy and transpose for direction-optimizing BFS
+  std::unique_ptr<DoGraph> dg(new (std::nothrow) DoGraph());
+  if (!dg) {
+    free_buf(noff);
+    free_buf(ntgt);
+    return PASGAL_ENOMEM;
+  }
+  const bool dense = (int64_t)g->m > 8 * (int64_t)g->n;
+  if (dense && !(s->opts.flags & PASGAL_SERVER_NO_DIRECTION_OPT)) {
+    DoGraph &D = *dg;
+    D.n = g->n;
+    D.m = g->m;
+    const size_t bo = 4 * ((size_t)g->n + 1), bt = 4 * (size_t)std::max<int32_t>(g->m, 1);
+    rc = grow(D.off, bo);
+    if (!rc) rc = grow(D.tgt, bt);
+    if (!rc) rc = grow(D.toff, bo);
+    if (!rc) rc = grow(D.ttgt, bt);
+    if (!rc) {
+      e = hipMemcpyAsync(D.off.p, g->offsets, bo, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess && g->m > 0) e = hipMemcpyAsync(D.tgt.p, g->targets, 4 * (size_t)g->m, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+    if (!rc) {
+      pasgal_csr lc{g->n, g->m, (const int32_t *)D.off.p, (const int32_t *)D.tgt.p};
+      pasgal_opts po;
+      pasgal_opts_default(&po);
+      po.stream = st;
+      rc = pasgal_transpose(&lc, (int32_t *)D.toff.p, (int32_t *)D.ttgt.p, &po);
+    }
+    if (rc) {
+      free_buf(noff);
+      free_buf(ntgt);
+      return rc;
+    }
+    D.on = true;
+  }
   free_buf(s->off);
   free_buf(s->tgt);
   s->off = noff;
   s->tgt = ntgt;
   s->n_total = (int32_t)n2;
   s->m_total = (int32_t)m2;
-  if ((int64_t)g->m > 8 * (int64_t)g->n) s->dense = true;
+  if (dense) s->dense = true;
+  s->dograph.push_back(std::move(dg));
+  const bool dob = s->dograph.back()->on;
   std::lock_guard<std::mutex> gm(s->graph_mu);
   s->vbase.push_back((int32_t)n2);
   s->ebase.push_back((int32_t)m2);
+  s->dobfs.push_back(dob ? 1 : 0);
   *graph_id = (int32_t)s->vbase.size() - 2;
   return PASGAL_OK;
 }
@@ -646,12 +783,14 @@ int pasgal_server_submit(pasgal_server *s, const pasgal_request *req, int64_t *i
   if (!s || !req || !id) return PASGAL_EINVAL;
   if (req->kind != PASGAL_REQ_BFS && req->kind != PASGAL_REQ_REACH) return PASGAL_EINVAL;
   int32_t nv = 0, vb = 0;
+  bool dob = false;
   {
     std::lock_guard<std::mutex> gm(s->graph_mu);
     const int32_t ng = (int32_t)s->vbase.size() - 1;
     if (req->graph < 0 || req->graph >= ng) return PASGAL_ENOTFOUND;
     vb = s->vbase[req->graph];
     nv = s->vbase[req->graph + 1] - vb;
+    dob = s->dobfs[req->graph] != 0;
   }
   if (req->nsources < 1 || req->nsources > 64 || (req->kind == PASGAL_REQ_BFS && req->nsources != 1))
     return PASGAL_EINVAL;
@@ -662,6 +801,7 @@ int pasgal_server_submit(pasgal_server *s, const pasgal_request *req, int64_t *i
   r->r = *req;
   r->vbase = vb;
   r->nv = nv;
+  r->dobfs = req->kind == PASGAL_REQ_BFS && dob;
   r->t_submit = now_ms();
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -678,6 +818,7 @@ int pasgal_server_submit(pasgal_server *s, const pasgal_request *req, int64_t *i
     s->inflight++;
     *id = r->id;
   }
+  __atomic_fetch_add(s->h_yield, 1u, __ATOMIC_SEQ_CST);  // a long launch ends at its next round boundary
   s->cv.notify_all();
   return PASGAL_OK;
 }
@@ -706,7 +847,7 @@ int pasgal_server_load(pasgal_server *s, int32_t *queued, int32_t *active, int64
   if (!s) return PASGAL_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
   if (queued) *queued = (int32_t)s->submitted.size();
-  if (active) *active = s->lanes[0].active + s->lanes[1].active;
+  if (active) *active = s->lanes[0].active + s->lanes[1].active + s->do_active;
   if (bytes_in_use) *bytes_in_use = s->alloc.used;
   return PASGAL_OK;
 }

@@ -430,6 +430,97 @@ def test_server_tiny_budget_queues_admission(pg):
     srv.close()
 
 
+@pytest.mark.parametrize("fixed", [False, True])
+def test_server_lone_request_long_launch(pg, fixed):
+    """A request served alone: by default one launch runs until it is done
+    (no per-slice round trips); with fixed slices every launch stops after
+    slice_rounds. Both give the oracle's results."""
+    g = gg.grid(120, 90)
+    srv = pg.Server(max_slots=8, slice_rounds=4, tau=64, fixed_slices=fixed)
+    gid = srv.add_graph(dev(pg, g))
+    for i, kind in enumerate(["bfs", "reach", "bfs"]):
+        _say(f"lone request fixed={fixed} {kind}")
+        src = int(gg.sources(g, 1, 700 + i)[0])
+        out = torch.empty(g.n, dtype=torch.int32 if kind == "bfs" else torch.int64, device="cuda")
+        assert srv.submit(gid, kind, [src], out=out, tag=i) is not None
+        srv.drain(60000)
+        (c,) = srv.poll(10)
+        assert c["status"] == 0 and c["tag"] == i
+        if kind == "bfs":
+            assert np.array_equal(np_dist(out), oracle.bfs(g, src))
+        else:
+            assert np.array_equal(np_mask(out)[:, None], oracle.reach(g, [src]))
+    srv.close()
+
+
+def test_server_submission_ends_long_launch(pg):
+    """A long launch for a lone request ends at the next round boundary once
+    another request is submitted: the second (small) request is admitted and
+    finishes while the first is still being traversed."""
+    big, small = gg.grid(4096, 4096), gg.grid(32, 32)
+    srv = pg.Server(max_slots=8, slice_rounds=8)
+    gb, gs = srv.add_graph(dev(pg, big)), srv.add_graph(dev(pg, small))
+    out_b = torch.empty(big.n, dtype=torch.int32, device="cuda")
+    out_s = torch.empty(small.n, dtype=torch.int32, device="cuda")
+    _say("long launch: big grid from corner 0")
+    assert srv.submit(gb, "bfs", [0], out=out_b, tag=1) is not None
+    import time
+    t0 = time.perf_counter()
+    while srv.load_info()["active"] == 0 and time.perf_counter() - t0 < 10:
+        time.sleep(0.0002)
+    time.sleep(0.002)
+    _say("second request during the long launch")
+    assert srv.submit(gs, "bfs", [5], out=out_s, tag=2) is not None
+    srv.drain(60000)
+    comps = {c["tag"]: c for c in srv.poll(10)}
+    assert comps[1]["status"] == 0 and comps[2]["status"] == 0
+    assert comps[2]["t_done_ms"] < comps[1]["t_done_ms"], comps
+    r, c = np.divmod(np.arange(big.n), 4096)
+    assert np.array_equal(np_dist(out_b), (r + c).astype(np.int32))
+    assert np.array_equal(np_dist(out_s), oracle.bfs(small, 5))
+    srv.close()
+
+
+@pytest.mark.parametrize("direction_optimizing", [True, False])
+def test_server_dense_graph_bfs(pg, direction_optimizing):
+    """BFS requests on a graph with mean out-degree above 8 are served by the
+    direction-optimizing BFS by default (from the server's own copy of the
+    graph and its transpose), reach requests by the batched launches; with
+    direction optimization off everything is batched. Results as the
+    oracle's, also for a request whose result is dropped (out=None) between
+    others, and for a directed dense graph (transpose differs)."""
+    gs = gg.rmat(11, 8, 3)
+    gd = gg.random_graph(3000, 36000, 11, symmetric=False)
+    assert gs.m > 8 * gs.n and gd.m > 8 * gd.n
+    srv = pg.Server(max_slots=8, slice_rounds=4, direction_optimizing=direction_optimizing)
+    ids = [srv.add_graph(dev(pg, gs)), srv.add_graph(dev(pg, gd))]
+    reqs = []
+    for i in range(16):
+        gi = i % 2
+        g = (gs, gd)[gi]
+        kind = "reach" if i % 4 == 3 else "bfs"
+        src = int(gg.sources(g, 1, 800 + i, min_degree=1)[0])
+        out = None
+        if i != 5:
+            out = torch.empty(g.n, dtype=torch.int32 if kind == "bfs" else torch.int64, device="cuda")
+        _say(f"dense server do={direction_optimizing} req {i} {kind} graph {gi}")
+        assert srv.submit(ids[gi], kind, [src], out=out, tag=i) is not None
+        reqs.append((i, g, kind, src, out))
+    srv.drain(60000)
+    comps = {c["tag"]: c for c in srv.poll(100)}
+    assert len(comps) == len(reqs)
+    for i, g, kind, src, out in reqs:
+        assert comps[i]["status"] == 0, i
+        if out is None:
+            continue
+        if kind == "bfs":
+            assert np.array_equal(np_dist(out), oracle.bfs(g, src)), i
+        else:
+            assert np.array_equal(np_mask(out)[:, None], oracle.reach(g, [src])), i
+    assert srv.load_info()["active"] == 0
+    srv.close()
+
+
 # ------------------------------------------------------ heavy-row slices ---
 
 def _hub_graph(n_leaves, extra_seed):
