@@ -334,6 +334,10 @@ def main():
     ap.add_argument("--rates", default="5,10,20,40,100,300,1000,3000,10000", help="c5: Poisson arrival rates (q/s)")
     ap.add_argument("--server-tau", type=int, default=0, help="c5: the server's local-search budget (0: its default)")
     ap.add_argument("--slice-rounds", type=int, default=16, help="c5: rounds per server launch")
+    ap.add_argument("--server-fixed-slices", action="store_true",
+                    help="c5: every server launch runs at most --slice-rounds rounds (no long launch for a lone request)")
+    ap.add_argument("--server-no-do", action="store_true",
+                    help="c5: RMAT BFS requests in the batched launches instead of the direction-optimizing BFS")
     ap.add_argument("--scc-graphs", default="", help="scc: comma list of graphs to run (road4096, knn10m, rmat20)")
     ap.add_argument("--scc-default-only", action="store_true", help="scc: only the library's default call")
     ap.add_argument("--grid-default-only", action="store_true",

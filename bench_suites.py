@@ -576,6 +576,11 @@ def suite_c5(args, pg, gg, torch):
             lat.append(time.perf_counter() - t0)
         return time.perf_counter() - a, lat
 
+    def by_kind(lat):
+        keys = [("grid" if gi == 0 else "rmat") + "_" + kind for gi, kind, _ in serial]
+        return {k: round(float(np.percentile([t for t, kk in zip(lat, keys) if kk == k], 50)) * 1e3, 2)
+                for k in sorted(set(keys))}
+
     serial_s_do, lat_do = one_at_a_time(True)
     serial_s, lat = one_at_a_time(False)
     # algorithmic bytes per request (all four request kinds reach the whole
@@ -599,11 +604,12 @@ def suite_c5(args, pg, gg, torch):
               "alg_bytes_per_request": {f"{'grid' if k[0] == 0 else 'rmat'}_{k[1]}": v for k, v in req_bytes.items()},
               "one_at_a_time": {"requests": len(serial), "queries_per_s": round(len(serial) / serial_s, 2),
                                 "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-                                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2)},
+                                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                                "p50_ms_by_kind": by_kind(lat)},
               "one_at_a_time_rmat_bfs_direction_optimizing": {
                   "requests": len(serial), "queries_per_s": round(len(serial) / serial_s_do, 2),
                   "p50_ms": round(float(np.percentile(lat_do, 50)) * 1e3, 2),
-                  "p99_ms": round(float(np.percentile(lat_do, 99)) * 1e3, 2)},
+                  "p99_ms": round(float(np.percentile(lat_do, 99)) * 1e3, 2), "p50_ms_by_kind": by_kind(lat_do)},
               "cpu_baseline": {"value": round(2.0 / (cpu_grid + cpu_rmat), 4), "unit": "queries/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"queue BFS on the grid ({cpu_grid:.1f} s) and on RMAT-24 ({cpu_rmat:.1f} s)"},
@@ -612,7 +618,8 @@ def suite_c5(args, pg, gg, torch):
     del outs
     torch.cuda.empty_cache()
     srv = pg.Server(max_slots=256, slice_rounds=args.slice_rounds if hasattr(args, "slice_rounds") else 16,
-                    tau=getattr(args, "server_tau", 0))
+                    tau=getattr(args, "server_tau", 0), fixed_slices=getattr(args, "server_fixed_slices", False),
+                    direction_optimizing=not getattr(args, "server_no_do", False))
     gids = [srv.add_graph(dg), srv.add_graph(dr)]
     npool = 48
     pools = {}
@@ -688,7 +695,8 @@ def suite_c5(args, pg, gg, torch):
                     checks["failed"] += 0 if good else 1
                 with lock:
                     free[(gi, kind)].append(b)
-                done.append((ok, c["t_done_ms"] - t_sched * 1e3, c["t_admit_ms"] - c["t_submit_ms"]))
+                done.append((ok, c["t_done_ms"] - t_sched * 1e3, c["t_admit_ms"] - c["t_submit_ms"],
+                             ("grid" if gi == 0 else "rmat") + "_" + kind))
             time.sleep(0.001)
         th.join()
         elapsed = time.perf_counter() - t_start
@@ -709,6 +717,8 @@ def suite_c5(args, pg, gg, torch):
                  "p50_ms": round(float(np.percentile(lats, 50)), 2) if lats.size else None,
                  "p99_ms": round(float(np.percentile(lats, 99)), 2) if lats.size else None,
                  "admission_wait_p50_ms": round(float(np.percentile([x[2] for x in ok], 50)), 2) if ok else None,
+                 "p50_ms_by_kind": {k: round(float(np.percentile([x[1] for x in ok if x[3] == k], 50)), 2)
+                                    for k in sorted({x[3] for x in ok})},
                  "roofline_frac": round(qps * mix_bytes / 1e9 / HBM_PEAK_GBS, 5),
                  "checked": checks}
         result["rates"].append(entry)

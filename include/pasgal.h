@@ -35,9 +35,10 @@
  * host threads; each stream has its own workspace. A persistent traversal
  * launch assumes it has the GPU's compute units to itself (its grid barrier
  * needs every workgroup resident), so two such launches must not overlap,
- * except two launches that both set PASGAL_FLAG_HALF_DEVICE, which are sized
- * to share every compute unit. A launch that cannot become resident ends in
- * PASGAL_ETIMEOUT when its barrier deadline passes; it does not hang.
+ * except launches whose pasgal_opts.device_share values add up to at most 100
+ * (PASGAL_FLAG_HALF_DEVICE is a share of 50), which are sized to share every
+ * compute unit. A launch that cannot become resident ends in PASGAL_ETIMEOUT
+ * when its barrier deadline passes; it does not hang.
  */
 #ifndef PASGAL_H
 #define PASGAL_H
@@ -417,7 +418,7 @@ typedef struct pasgal_server_opts {
   int64_t memory_budget;   /* bytes of request state (result slots + bitmaps); <= 0: 1/4 of free HBM */
   int32_t max_slots;       /* concurrent requests; <= 0 selects 256 */
   int32_t slice_rounds;    /* rounds per launch before re-admitting; <= 0 selects 16 */
-  int32_t tau;             /* <= 0 selects 256 */
+  int32_t tau;             /* <= 0 selects 1024 */
   int32_t wg_size;         /* <= 0 selects 1024 */
   int32_t blocks_per_cu;   /* <= 0 selects 1 */
   int64_t frontier_capacity; /* per kind; <= 0 selects 64M entries */
@@ -425,10 +426,10 @@ typedef struct pasgal_server_opts {
   int32_t window;          /* BFS distance window per round (see pasgal_opts.window); < 0 selects none,
                               0 selects 32 */
   uint32_t flags;          /* PASGAL_FLAG_TEST_FIRST / PASGAL_FLAG_NO_TEST_FIRST: read a target's state
-                              before each relaxing atomic in every launch. Default: on once a resident
-                              graph has mean out-degree above 8 (there most arcs reach vertices that
-                              already have the value, and a plain read is cheaper than the atomic),
-                              off otherwise. PASGAL_SERVER_FIXED_SLICES,
+                              before each relaxing atomic in every launch. Default: on in a launch that
+                              holds a request on a graph with mean out-degree above 8 (there most arcs
+                              reach vertices that already have the value, and a plain read is cheaper
+                              than the atomic), off otherwise. PASGAL_SERVER_FIXED_SLICES,
                               PASGAL_SERVER_NO_DIRECTION_OPT: see there. Other bits must be 0. */
   int32_t reserved;        /* 0 */
 } pasgal_server_opts;
@@ -438,12 +439,14 @@ typedef struct pasgal_server_opts {
    submitted (the launch polls a word in coherent host memory once per round and ends at the next round
    boundary), so that a request served alone pays no per-slice host round trips. */
 #define PASGAL_SERVER_FIXED_SLICES 65536u
-/* Server flag: BFS requests on every graph go through the batched VGC launches. By default a graph added
-   with mean out-degree above 8 (m > 8n: low diameter, where top-down levels scan most arcs) gets a copy of
-   itself and of its transpose in server memory (4(n+1) + 4m bytes each, built once by pasgal_server_
-   add_graph), and its BFS requests are served one at a time by the direction-optimizing BFS
-   (pasgal_bfs_do, default alpha and beta) on a stream of the server's own, between the batched launches;
-   their completions report levels as rounds. Reach requests always use the batched launches. */
+/* Server flag: every request goes through the batched VGC launches. By default a graph added with mean
+   out-degree above 8 (m > 8n: low diameter, where top-down levels scan most arcs) gets a copy of itself
+   and of its transpose in server memory (4(n+1) + 4m bytes each, built once by pasgal_server_add_graph),
+   and its BFS requests and single-source reach requests are served one at a time by the
+   direction-optimizing BFS (pasgal_bfs_do, default alpha and beta) on a stream and host thread of the
+   server's own, beside the batched launches (which then take half of every compute unit); a reach
+   request gets bit 0 set where the BFS arrived. Their completions report levels as rounds. Reach
+   requests with several sources always use the batched launches. */
 #define PASGAL_SERVER_NO_DIRECTION_OPT 131072u
 
 #define PASGAL_REQ_BFS 0

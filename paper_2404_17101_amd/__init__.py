@@ -359,8 +359,9 @@ class Server:
     def __init__(self, memory_budget: int = 0, max_slots: int = 0, slice_rounds: int = 0, tau: int = 0,
                  wg_size: int = 0, blocks_per_cu: int = 0, frontier_capacity: int = 0, timeout_ms: int = 0,
                  window: int = 0, test_first=None, fixed_slices: bool = False, direction_optimizing: bool = True):
-        """test_first: None = the server's default (on once a resident graph has
-        mean out-degree above 8), True / False = always / never. fixed_slices:
+        """test_first: None = the server's default (on in a launch holding a
+        request on a graph with mean out-degree above 8), True / False =
+        always / never. fixed_slices:
         every launch runs at most slice_rounds rounds, also for a request
         served alone. direction_optimizing: BFS requests on graphs with mean
         out-degree above 8 are served by the direction-optimizing BFS (False:

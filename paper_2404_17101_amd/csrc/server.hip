@@ -41,11 +41,14 @@
 #include "kern.h"
 #include "pasgal.h"
 
-// BFS requests on low-diameter graphs (mean out-degree above 8) do not join
-// the batched launches: the loop serves them one at a time with the
-// direction-optimizing BFS on a stream of its own, while no batched launch is
-// in flight, from copies of the graph and of its transpose that
-// pasgal_server_add_graph makes.
+// BFS requests and single-source reach requests on low-diameter graphs (mean
+// out-degree above 8) do not join the batched launches: a second host thread
+// serves them one at a time with the direction-optimizing BFS on a stream of
+// its own (a reach request takes the reached set of the BFS as its one mask
+// bit), from copies of the graph and of its transpose that
+// pasgal_server_add_graph makes. While such a
+// request is queued or running, the batched launches take half of every
+// compute unit, so that its ordinary kernels run beside them.
 
 using namespace pg;
 
@@ -102,7 +105,8 @@ struct Arena {
 struct Req {
   int64_t id = 0;
   pasgal_request r{};
-  bool dobfs = false;  // served by the direction-optimizing BFS
+  bool dobfs = false;  // served by the direction-optimizing BFS (BFS, or reach from one source)
+  bool dense = false;  // its graph has mean out-degree above 8
   double t_submit = 0, t_admit = 0;
   int64_t rounds = 0;
   int slot = -1;
@@ -139,6 +143,14 @@ struct Lane {
   }
 };
 
+// Reach mask word (one source, bit 0) from the distances of a BFS from it.
+__global__ void __launch_bounds__(256) mask_from_dist_kernel(const uint32_t *__restrict__ dist,
+                                                             unsigned long long *__restrict__ mask, uint32_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    mask[v] = dist[v] != 0xFFFFFFFFu ? 1ull : 0ull;
+}
+
 // A resident graph's own copy (local vertex ids) and its transpose, kept for
 // direction-optimizing BFS requests.
 struct DoGraph {
@@ -157,7 +169,7 @@ struct pasgal_server {
   Opts vopts;       // whole-device slices
   Opts vopts_half;  // slices that run beside the other kind's, on half of every compute unit
   bool half_ok = true;
-  bool dense = false;  // a resident graph has mean out-degree above 8
+  std::vector<uint8_t> densev;  // per graph: mean out-degree above 8 (guarded by graph_mu)
   hipStream_t stream = nullptr;
   int device = 0;
   // resident packed CSR
@@ -173,9 +185,11 @@ struct pasgal_server {
   Lane lanes[2];
   // direction-optimizing BFS requests (admitted, in arrival order)
   std::vector<std::unique_ptr<DoGraph>> dograph;  // per graph id
-  std::deque<Req *> do_q;
+  std::deque<Req *> do_q;          // guarded by mu
   std::atomic<int> do_active{0};  // admitted direction-optimizing requests not yet completed
   hipStream_t do_stream = nullptr;
+  std::thread do_thr;
+  std::condition_variable cv_do;
   // queues
   std::mutex mu;
   std::condition_variable cv, cv_done;
@@ -197,7 +211,9 @@ struct pasgal_server {
     }
     if (h_yield) __atomic_fetch_add(h_yield, 1u, __ATOMIC_SEQ_CST);  // end a long launch now
     cv.notify_all();
+    cv_do.notify_all();
     if (thr.joinable()) thr.join();
+    if (do_thr.joinable()) do_thr.join();
     for (Req *r : submitted) delete r;
     for (Lane &l : lanes) {
       if (l.stream) hipStreamSynchronize(l.stream);
@@ -237,7 +253,14 @@ struct pasgal_server {
   }
 
   int64_t state_bytes(const Req *r) const {
-    if (r->dobfs) return r->r.out ? 0 : 4 * (int64_t)r->nv;  // distances only, when the caller keeps none
+    if (r->dobfs) {
+      // BFS: the distances, unless they go straight to the caller's array;
+      // reach: the distances (256-byte aligned), then the mask words unless
+      // they go to the caller's array
+      const int64_t d = 4 * (int64_t)r->nv;
+      if (r->r.kind == PASGAL_REQ_BFS) return r->r.out ? 0 : d;
+      return ((d + 255) & ~(int64_t)255) + (r->r.out ? 0 : 8 * (int64_t)r->nv);
+    }
     const int64_t es = r->r.kind == PASGAL_REQ_BFS ? 4 : 8;
     const int64_t words = ((int64_t)r->nv + 31) / 32;
     return ((es * r->nv + 255) & ~(int64_t)255) + 4 * words;
@@ -260,6 +283,7 @@ struct pasgal_server {
         r->t_admit = now_ms();
         do_q.push_back(r);
         do_active++;
+        cv_do.notify_one();
         continue;
       }
       Lane &L = lanes[r->r.kind == PASGAL_REQ_BFS ? 0 : 1];
@@ -285,6 +309,14 @@ struct pasgal_server {
     }
   }
 
+  // Return a request's arena memory (the allocator is shared by the loop and
+  // the direction-optimizing thread; it is used under the queue lock).
+  void release(Req *r) {
+    if (r->bytes <= 0) return;
+    std::lock_guard<std::mutex> lk(mu);
+    alloc.release(r->off, r->bytes);
+  }
+
   void fail_lane(Lane &L, int status) {
     if (L.stream) hipStreamSynchronize(L.stream);
     (void)hipGetLastError();
@@ -293,7 +325,7 @@ struct pasgal_server {
     for (size_t i = 0; i < L.slots.size(); i++)
       if (L.slots[i]) {
         Req *r = L.slots[i];
-        alloc.release(r->off, r->bytes);
+        release(r);
         L.slots[i] = nullptr;
         complete(r, status);
       }
@@ -307,7 +339,7 @@ struct pasgal_server {
   // are done, so those requests complete and their memory is returned.
   void finish_copies(Lane &L) {
     for (Req *r : L.copying) {
-      alloc.release(r->off, r->bytes);
+      release(r);
       complete(r, PASGAL_OK);
     }
     L.copying.clear();
@@ -324,10 +356,13 @@ struct pasgal_server {
     const int kind = L.kind;
     const int nslots = (int)L.slots.size();
     const size_t es = kind == KIND_BFS ? 4 : 8;
-    // test-first: as asked, else once a dense graph is resident
+    // test-first: as asked, else when a request of the launch is on a graph
+    // with mean out-degree above 8
+    bool any_dense = false;
+    for (const Req *r : L.slots) any_dense = any_dense || (r && r->dense);
     const bool tf = (opts.flags & PASGAL_FLAG_TEST_FIRST) ? true
                     : (opts.flags & PASGAL_FLAG_NO_TEST_FIRST) ? false
-                                                               : dense;
+                                                               : any_dense;
     const LaunchGeom &lg = half ? L.lg_half[tf] : L.lg_full[tf];
     Opts vo = half ? vopts_half : vopts;
     vo.test_first = tf;
@@ -498,13 +533,43 @@ struct pasgal_server {
     pasgal_opts_default(&po);
     po.stream = do_stream;
     po.timeout_ms = opts.timeout_ms;
-    int32_t *dist = r->r.out ? (int32_t *)r->r.out : (int32_t *)((uint8_t *)arena.p + r->off);
+    const bool bfs = r->r.kind == PASGAL_REQ_BFS;
+    uint8_t *mine = r->bytes > 0 ? (uint8_t *)arena.p + r->off : nullptr;
+    int32_t *dist = (bfs && r->r.out) ? (int32_t *)r->r.out : (int32_t *)mine;
     pasgal_stats st{};
-    const int rc = pasgal_bfs_do(&g, &gt, r->r.sources[0], dist, 0, 0, &po, &st);
+    int rc = pasgal_bfs_do(&g, &gt, r->r.sources[0], dist, 0, 0, &po, &st);
     r->rounds = st.rounds;
-    if (r->bytes > 0) alloc.release(r->off, r->bytes);
+    if (rc == PASGAL_OK && !bfs) {  // reach from one source: bit 0 where the BFS arrived
+      unsigned long long *mask = r->r.out ? (unsigned long long *)r->r.out
+                                          : (unsigned long long *)(mine + ((4 * (int64_t)r->nv + 255) & ~(int64_t)255));
+      (void)hipGetLastError();
+      const int blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, ((int64_t)r->nv + 255) / 256));
+      hipLaunchKernelGGL(mask_from_dist_kernel, dim3(blocks), dim3(256), 0, do_stream, (const uint32_t *)dist, mask,
+                         (uint32_t)r->nv);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(do_stream);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+    release(r);
     do_active--;
     complete(r, rc);
+  }
+
+  // The direction-optimizing thread: one request at a time, in admission order.
+  void do_loop() {
+    hipSetDevice(device);
+    while (true) {
+      Req *r = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_do.wait(lk, [&] { return stop || !do_q.empty(); });
+        if (stop) return;
+        r = do_q.front();
+        do_q.pop_front();
+      }
+      run_do(r);
+      cv.notify_all();  // the loop may widen its launches again
+    }
   }
 
   // Wait for the lane's stream; complete the requests whose copies were
@@ -529,7 +594,7 @@ struct pasgal_server {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait_for(lk, std::chrono::milliseconds(50), [&] {
           return stop || !submitted.empty() || lanes[0].active > 0 || lanes[1].active > 0 ||
-                 !lanes[0].copying.empty() || !lanes[1].copying.empty() || !do_q.empty();
+                 !lanes[0].copying.empty() || !lanes[1].copying.empty();
         });
         if (stop) return;
       }
@@ -542,12 +607,15 @@ struct pasgal_server {
         std::lock_guard<std::mutex> lk(mu);
         queued = !submitted.empty();
       }
-      const bool lone = !(opts.flags & PASGAL_SERVER_FIXED_SLICES) && !queued && do_q.empty() &&
+      // direction-optimizing requests queued or running: leave them half the device
+      const bool do_busy = do_active > 0;
+      const bool lone = !(opts.flags & PASGAL_SERVER_FIXED_SLICES) && !queued && !do_busy &&
                         lanes[0].active + lanes[1].active == 1;
       // both kinds with work: their launches run at the same time, each on
       // half of every compute unit; otherwise one after the other, each on
       // the whole device
       const bool both = half_ok && lanes[0].active > 0 && lanes[1].active > 0;
+      const bool beside_do = half_ok && do_busy;
       if (both) {
         for (Lane &L : lanes)
           if (int rc = enqueue_slice(L, true)) fail_lane(L, rc);
@@ -555,19 +623,10 @@ struct pasgal_server {
       } else {
         for (Lane &L : lanes) {
           if (L.active > 0) {
-            if (int rc = enqueue_slice(L, false, lone, ybase)) fail_lane(L, rc);
+            if (int rc = enqueue_slice(L, beside_do, lone, ybase)) fail_lane(L, rc);
           }
           wait_lane(L);
         }
-      }
-      // direction-optimizing BFS requests, with no batched launch in flight:
-      // all of them while the batched lanes are idle, else one per slice
-      const bool lanes_idle = lanes[0].active == 0 && lanes[1].active == 0;
-      while (!do_q.empty()) {
-        Req *r = do_q.front();
-        do_q.pop_front();
-        run_do(r);
-        if (!lanes_idle) break;
       }
     }
   }
@@ -684,6 +743,7 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
   }
   try {
     s->thr = std::thread([s] { s->loop(); });
+    s->do_thr = std::thread([s] { s->do_loop(); });
   } catch (...) {
     delete s;
     return PASGAL_ENOMEM;
@@ -768,13 +828,13 @@ int pasgal_server_add_graph(pasgal_server *s, const pasgal_csr *g, int32_t *grap
   s->tgt = ntgt;
   s->n_total = (int32_t)n2;
   s->m_total = (int32_t)m2;
-  if (dense) s->dense = true;
   s->dograph.push_back(std::move(dg));
   const bool dob = s->dograph.back()->on;
   std::lock_guard<std::mutex> gm(s->graph_mu);
   s->vbase.push_back((int32_t)n2);
   s->ebase.push_back((int32_t)m2);
   s->dobfs.push_back(dob ? 1 : 0);
+  s->densev.push_back(dense ? 1 : 0);
   *graph_id = (int32_t)s->vbase.size() - 2;
   return PASGAL_OK;
 }
@@ -783,7 +843,7 @@ int pasgal_server_submit(pasgal_server *s, const pasgal_request *req, int64_t *i
   if (!s || !req || !id) return PASGAL_EINVAL;
   if (req->kind != PASGAL_REQ_BFS && req->kind != PASGAL_REQ_REACH) return PASGAL_EINVAL;
   int32_t nv = 0, vb = 0;
-  bool dob = false;
+  bool dob = false, dense = false;
   {
     std::lock_guard<std::mutex> gm(s->graph_mu);
     const int32_t ng = (int32_t)s->vbase.size() - 1;
@@ -791,6 +851,7 @@ int pasgal_server_submit(pasgal_server *s, const pasgal_request *req, int64_t *i
     vb = s->vbase[req->graph];
     nv = s->vbase[req->graph + 1] - vb;
     dob = s->dobfs[req->graph] != 0;
+    dense = s->densev[req->graph] != 0;
   }
   if (req->nsources < 1 || req->nsources > 64 || (req->kind == PASGAL_REQ_BFS && req->nsources != 1))
     return PASGAL_EINVAL;
@@ -801,7 +862,8 @@ int pasgal_server_submit(pasgal_server *s, const pasgal_request *req, int64_t *i
   r->r = *req;
   r->vbase = vb;
   r->nv = nv;
-  r->dobfs = req->kind == PASGAL_REQ_BFS && dob;
+  r->dobfs = dob && (req->kind == PASGAL_REQ_BFS || req->nsources == 1);
+  r->dense = dense;
   r->t_submit = now_ms();
   {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -483,12 +483,13 @@ def test_server_submission_ends_long_launch(pg):
 
 @pytest.mark.parametrize("direction_optimizing", [True, False])
 def test_server_dense_graph_bfs(pg, direction_optimizing):
-    """BFS requests on a graph with mean out-degree above 8 are served by the
-    direction-optimizing BFS by default (from the server's own copy of the
-    graph and its transpose), reach requests by the batched launches; with
-    direction optimization off everything is batched. Results as the
-    oracle's, also for a request whose result is dropped (out=None) between
-    others, and for a directed dense graph (transpose differs)."""
+    """BFS and single-source reach requests on a graph with mean out-degree
+    above 8 are served by the direction-optimizing BFS by default (from the
+    server's own copy of the graph and its transpose), reach requests with
+    several sources by the batched launches; with direction optimization off
+    everything is batched. Results as the oracle's, also for requests whose
+    result is dropped (out=None) between others, and for a directed dense
+    graph (transpose differs)."""
     gs = gg.rmat(11, 8, 3)
     gd = gg.random_graph(3000, 36000, 11, symmetric=False)
     assert gs.m > 8 * gs.n and gd.m > 8 * gd.n
@@ -498,25 +499,25 @@ def test_server_dense_graph_bfs(pg, direction_optimizing):
     for i in range(16):
         gi = i % 2
         g = (gs, gd)[gi]
-        kind = "reach" if i % 4 == 3 else "bfs"
-        src = int(gg.sources(g, 1, 800 + i, min_degree=1)[0])
+        kind = "reach" if i % 4 == 3 or i == 6 else "bfs"
+        srcs = [int(x) for x in gg.sources(g, 3 if i % 8 == 7 else 1, 800 + i, min_degree=1)]
         out = None
-        if i != 5:
+        if i not in (5, 6):
             out = torch.empty(g.n, dtype=torch.int32 if kind == "bfs" else torch.int64, device="cuda")
-        _say(f"dense server do={direction_optimizing} req {i} {kind} graph {gi}")
-        assert srv.submit(ids[gi], kind, [src], out=out, tag=i) is not None
-        reqs.append((i, g, kind, src, out))
+        _say(f"dense server do={direction_optimizing} req {i} {kind} graph {gi} sources {len(srcs)}")
+        assert srv.submit(ids[gi], kind, srcs, out=out, tag=i) is not None
+        reqs.append((i, g, kind, srcs, out))
     srv.drain(60000)
     comps = {c["tag"]: c for c in srv.poll(100)}
     assert len(comps) == len(reqs)
-    for i, g, kind, src, out in reqs:
+    for i, g, kind, srcs, out in reqs:
         assert comps[i]["status"] == 0, i
         if out is None:
             continue
         if kind == "bfs":
-            assert np.array_equal(np_dist(out), oracle.bfs(g, src)), i
+            assert np.array_equal(np_dist(out), oracle.bfs(g, srcs[0])), i
         else:
-            assert np.array_equal(np_mask(out)[:, None], oracle.reach(g, [src])), i
+            assert np.array_equal(np_mask(out)[:, None], oracle.reach(g, srcs)), i
     assert srv.load_info()["active"] == 0
     srv.close()
 
