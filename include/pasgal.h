@@ -264,6 +264,24 @@ int pasgal_sssp(const pasgal_csr *g, const uint32_t *weights, int32_t src, uint3
 int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t src, int32_t *dist_out, int32_t alpha,
                   int32_t beta, const pasgal_opts *opts, pasgal_stats *stats);
 
+/* Direction-optimizing BFS from k sources at once, 1 <= k <= 64 (the served
+ * form's batches of BFS and single-source reach requests on low-diameter
+ * graphs; not in the paper, which runs one BFS at a time). Every vertex
+ * carries one bit per source in 64-bit words (reached so far, reached in the
+ * current level, in the next); a top-down level ORs the frontier bits of each
+ * frontier vertex into its targets (an atomicOr decides which lane owns each
+ * new bit), a bottom-up level has every vertex still missing some bit OR the
+ * frontier bits of its in-neighbours until it has them all. The switching
+ * rule is pasgal_bfs_do's on the union of the frontiers. sources: HOST array
+ * of k vertex ids (repeats allowed). dist_out: device, k * n int32, row q =
+ * hop distances from sources[q] exactly as pasgal_bfs, or NULL. reach_out:
+ * device, n uint64, bit q set iff sources[q] reaches v, or NULL. gt, alpha,
+ * beta, opts, stats as for pasgal_bfs_do. PASGAL_EINVAL (nothing written): k
+ * outside [1, 64], a source outside [0, n), a null graph pointer. */
+int pasgal_bfs_do_multi(const pasgal_csr *g, const pasgal_csr *gt, int32_t k, const int32_t *sources,
+                        int32_t *dist_out, uint64_t *reach_out, int32_t alpha, int32_t beta, const pasgal_opts *opts,
+                        pasgal_stats *stats);
+
 /* Multi-source reachability (Parallel SCC section: a reachability search from
  * a vertex finds every vertex it reaches; the sources form the initial
  * frontier F0 of Algorithm 1). sources: DEVICE array of k int32 vertex ids
@@ -442,11 +460,11 @@ typedef struct pasgal_server_opts {
 /* Server flag: every request goes through the batched VGC launches. By default a graph added with mean
    out-degree above 8 (m > 8n: low diameter, where top-down levels scan most arcs) gets a copy of itself
    and of its transpose in server memory (4(n+1) + 4m bytes each, built once by pasgal_server_add_graph),
-   and its BFS requests and single-source reach requests are served one at a time by the
-   direction-optimizing BFS (pasgal_bfs_do, default alpha and beta) on a stream and host thread of the
-   server's own, beside the batched launches (which then take half of every compute unit); a reach
-   request gets bit 0 set where the BFS arrived. Their completions report levels as rounds. Reach
-   requests with several sources always use the batched launches. */
+   and its BFS requests and single-source reach requests are served in batches of up to 64 per graph
+   by the multi-source direction-optimizing BFS (pasgal_bfs_do_multi, default alpha and beta) on a host
+   thread and stream of the server's own; its levels and the batched launches take turns on the device.
+   A reach request gets bit 0 set where its source arrives. Their completions report levels as rounds.
+   Reach requests with several sources always use the batched launches. */
 #define PASGAL_SERVER_NO_DIRECTION_OPT 131072u
 
 #define PASGAL_REQ_BFS 0

@@ -176,6 +176,30 @@ def bfs_do(g: DeviceGraph, src: int, transpose: DeviceGraph | None = None, dist_
     return (dist_out, st.as_dict()) if stats else dist_out
 
 
+def bfs_do_multi(g: DeviceGraph, sources, transpose: DeviceGraph | None = None, dist_out=None, reach_out=None,
+                 alpha: int = 0, beta: int = 0, stats: bool = False, **opts):
+    """Direction-optimizing BFS from up to 64 sources at once (one bit per
+    source). dist_out: int32 tensor of k*n (row q: distances from sources[q])
+    or None; reach_out: int64 tensor of n (bit q: sources[q] arrives) or
+    None; with both None, dist_out is allocated. transpose as for bfs_do."""
+    torch = _torch()
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+    if dist_out is None and reach_out is None:
+        dist_out = torch.empty(src.size * g.n, dtype=torch.int32, device=g.offsets.device)
+    csr = g.csr()
+    tcsr = transpose.csr() if transpose is not None else None
+    o = _opts(**opts)
+    st = L.Stats()
+    _check(L.load().pasgal_bfs_do_multi(ctypes.byref(csr), ctypes.byref(tcsr) if tcsr is not None else None,
+                                        int(src.size), _i32p(src),
+                                        dist_out.data_ptr() if dist_out is not None else None,
+                                        reach_out.data_ptr() if reach_out is not None else None,
+                                        int(alpha), int(beta), ctypes.byref(o), ctypes.byref(st)),
+           "pasgal_bfs_do_multi")
+    out = dist_out if reach_out is None else (reach_out if dist_out is None else (dist_out, reach_out))
+    return (out, st.as_dict()) if stats else out
+
+
 def sssp(g: DeviceGraph, weights, src: int, dist_out=None, stats: bool = False, **opts):
     """Shortest-path distances with non-negative integer arc weights (a device
     tensor of m int32/uint32, parallel to g.targets). Returns an int32 tensor

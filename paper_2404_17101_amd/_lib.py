@@ -26,7 +26,7 @@ REQ_BFS, REQ_REACH = 0, 1
 EXPORTS = [
     "pasgal_opts_default", "pasgal_strerror", "pasgal_last_hip_error", "pasgal_version", "pasgal_wait",
     "pasgal_shutdown",
-    "pasgal_bfs", "pasgal_bfs_ex", "pasgal_bfs_noalloc", "pasgal_bfs_do", "pasgal_sssp", "pasgal_reach", "pasgal_reach_ex", "pasgal_transpose", "pasgal_validate",
+    "pasgal_bfs", "pasgal_bfs_ex", "pasgal_bfs_noalloc", "pasgal_bfs_do", "pasgal_bfs_do_multi", "pasgal_sssp", "pasgal_reach", "pasgal_reach_ex", "pasgal_transpose", "pasgal_validate",
     "pasgal_probe_latency",
     "pasgal_scc", "pasgal_batch_create", "pasgal_batch_run", "pasgal_batch_config", "pasgal_batch_destroy",
     "pasgal_server_create", "pasgal_server_add_graph", "pasgal_server_submit", "pasgal_server_poll",
@@ -128,6 +128,7 @@ def load(path: str = LIB_PATH):
     lib.pasgal_bfs_ex.argtypes = [P(Csr), i32, vp, P(Opts), P(Stats)]
     lib.pasgal_bfs_noalloc.argtypes = [P(Csr), i32, vp, P(Opts), P(Stats)]
     lib.pasgal_bfs_do.argtypes = [P(Csr), P(Csr), i32, vp, i32, i32, P(Opts), P(Stats)]
+    lib.pasgal_bfs_do_multi.argtypes = [P(Csr), P(Csr), i32, P(i32), vp, vp, i32, i32, P(Opts), P(Stats)]
     lib.pasgal_sssp.argtypes = [P(Csr), vp, i32, vp, P(Opts), P(Stats)]
     lib.pasgal_reach.argtypes = [P(Csr), P(i32), i32, vp]
     lib.pasgal_reach_ex.argtypes = [P(Csr), P(i32), i32, vp, P(Opts), P(Stats)]
@@ -148,7 +149,7 @@ def load(path: str = LIB_PATH):
     lib.pasgal_server_load.argtypes = [vp, P(i32), P(i32), P(i64)]
     lib.pasgal_server_destroy.argtypes = [vp]
     lib.pasgal_server_destroy.restype = None
-    for f in ("pasgal_bfs", "pasgal_bfs_ex", "pasgal_bfs_noalloc", "pasgal_bfs_do", "pasgal_sssp", "pasgal_reach", "pasgal_reach_ex", "pasgal_transpose",
+    for f in ("pasgal_bfs", "pasgal_bfs_ex", "pasgal_bfs_noalloc", "pasgal_bfs_do", "pasgal_bfs_do_multi", "pasgal_sssp", "pasgal_reach", "pasgal_reach_ex", "pasgal_transpose",
               "pasgal_validate", "pasgal_probe_latency", "pasgal_scc", "pasgal_batch_create", "pasgal_batch_run",
               "pasgal_batch_config",
               "pasgal_server_create", "pasgal_server_add_graph", "pasgal_server_submit", "pasgal_server_poll",

@@ -119,6 +119,158 @@ __global__ void __launch_bounds__(256) collect_kernel(const uint32_t *__restrict
   }
 }
 
+// ---- many sources at once: one bit per source in 64-bit words ----------
+// visited[v] holds the sources that have reached v, cur[v] those that reached
+// it in the current level and nxt[v] those reaching it in the next one. A
+// source q's distance to v is the level at which bit q first appears at v.
+
+// Seeds: bit q at sources[q]; a distance output of 0 there.
+__global__ void ms_seed_kernel(const int32_t *__restrict__ src, int32_t k, unsigned long long *visited,
+                               unsigned long long *cur, const MsQuery *__restrict__ qs) {
+  const int q = (int)threadIdx.x;
+  if (blockIdx.x != 0 || q >= k) return;
+  const uint32_t v = (uint32_t)src[q];
+  or_ag(&visited[v], 1ull << q);
+  or_ag(&cur[v], 1ull << q);
+  if (qs[q].dist) qs[q].dist[v] = 0;
+}
+
+// Distance outputs of the bits in nb: level + 1 at w.
+__device__ __forceinline__ void ms_write_dist(const MsQuery *__restrict__ qs, unsigned long long nb, uint32_t w,
+                                              uint32_t d) {
+  while (nb) {
+    const int q = __builtin_ctzll(nb);
+    nb &= nb - 1;
+    if (qs[q].dist) qs[q].dist[w] = (int32_t)d;
+  }
+}
+
+// Top-down level: one wavefront per frontier vertex, its out-arcs dealt over
+// the lanes. A target gains the frontier bits it has not seen (atomicOr on
+// visited decides which lane owns each new bit); the first lane to give it a
+// next-frontier bit queues it.
+__global__ void __launch_bounds__(256) ms_top_down_kernel(const int32_t *__restrict__ off,
+                                                          const int32_t *__restrict__ tgt,
+                                                          const uint32_t *__restrict__ fq, const uint32_t *fq_len,
+                                                          unsigned long long *visited,
+                                                          const unsigned long long *__restrict__ cur,
+                                                          unsigned long long *nxt, uint32_t *nq, uint32_t *nq_len,
+                                                          const MsQuery *__restrict__ qs, uint32_t level,
+                                                          DoCtr *ctr) {
+  const uint32_t len = *fq_len;
+  const uint32_t ln = lane_id();
+  const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  unsigned long long nf = 0, mf = 0, checked = 0;
+  for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < len; i += waves) {
+    const uint32_t u = fq[i];
+    const unsigned long long c = cur[u];
+    const int32_t b = off[u], e = off[u + 1];
+    for (int32_t j = b + (int32_t)ln; j < e; j += 64) {
+      checked++;
+      const uint32_t w = (uint32_t)tgt[j];
+      const unsigned long long m = c & ~ld_ag(&visited[w]);
+      if (!m) continue;
+      const unsigned long long nb = m & ~or_ag(&visited[w], m);
+      if (!nb) continue;
+      if (or_ag(&nxt[w], nb) == 0ull) {
+        nq[add_ag(nq_len, 1u)] = w;
+        nf++;
+        mf += (unsigned long long)(off[w + 1] - off[w]);
+      }
+      ms_write_dist(qs, nb, w, level + 1u);
+    }
+  }
+  nf = wave_sum64(nf);
+  mf = wave_sum64(mf);
+  checked = wave_sum64(checked);
+  if (ln == 0) {
+    if (nf) add_ag(&ctr->nf, nf);
+    if (mf) add_ag(&ctr->mf, mf);
+    if (checked) add_ag(&ctr->checked, checked);
+  }
+}
+
+// Bottom-up level: every vertex still missing some source's bit scans its
+// in-arcs, gathering the frontier bits it misses, and stops once it has them
+// all. Only v's own thread writes visited[v] and nxt[v] here.
+__global__ void __launch_bounds__(256) ms_bottom_up_kernel(const int32_t *__restrict__ off,
+                                                           const int32_t *__restrict__ t_off,
+                                                           const int32_t *__restrict__ t_tgt, uint32_t n,
+                                                           unsigned long long *visited,
+                                                           const unsigned long long *__restrict__ cur,
+                                                           unsigned long long *nxt, unsigned long long active,
+                                                           const MsQuery *__restrict__ qs, uint32_t level,
+                                                           DoCtr *ctr) {
+  unsigned long long nf = 0, mf = 0, checked = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
+    const uint64_t v = base + lane_id();
+    if (v >= n) continue;
+    const unsigned long long vis = visited[v];
+    const unsigned long long want = active & ~vis;
+    unsigned long long acc = 0;
+    if (want) {
+      const int32_t b = t_off[v], e = t_off[v + 1];
+      for (int32_t j = b; j < e; j++) {
+        checked++;
+        acc |= cur[t_tgt[j]];
+        if ((acc & want) == want) break;
+      }
+      acc &= want;
+    }
+    nxt[v] = acc;
+    if (acc) {
+      visited[v] = vis | acc;
+      nf++;
+      mf += (unsigned long long)(off[v + 1] - off[v]);
+      ms_write_dist(qs, acc, (uint32_t)v, level + 1u);
+    }
+  }
+  nf = wave_sum64(nf);
+  mf = wave_sum64(mf);
+  checked = wave_sum64(checked);
+  if (lane_id() == 0) {
+    if (nf) add_ag(&ctr->nf, nf);
+    if (mf) add_ag(&ctr->mf, mf);
+    if (checked) add_ag(&ctr->checked, checked);
+  }
+}
+
+// Queue of the vertices with a frontier bit (order unspecified).
+__global__ void __launch_bounds__(256) ms_collect_kernel(const unsigned long long *__restrict__ cur, uint32_t n,
+                                                         uint32_t *__restrict__ q, uint32_t *qlen) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
+    const uint64_t v = base + lane_id();
+    const bool in = v < n && cur[v] != 0ull;
+    const unsigned long long bal = __ballot(in);
+    if (bal) {
+      uint32_t at = 0;
+      if (lane_id() == 0) at = add_ag(qlen, (uint32_t)__popcll(bal));
+      at = __shfl(at, 0);
+      if (in) q[at + mbcnt64(bal)] = (uint32_t)v;
+    }
+  }
+}
+
+// Distance outputs start unreached (blockIdx.y = query).
+__global__ void ms_fill_dist_kernel(const MsQuery *__restrict__ qs, uint32_t n) {
+  int32_t *d = qs[blockIdx.y].dist;
+  if (!d) return;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) d[v] = -1;
+}
+
+// Reach outputs: bit 0 of mask1[v] = source q reached v.
+__global__ void ms_reach_out_kernel(const MsQuery *__restrict__ qs, const unsigned long long *__restrict__ visited,
+                                    uint32_t n) {
+  unsigned long long *m = qs[blockIdx.y].mask1;
+  if (!m) return;
+  const int q = (int)blockIdx.y;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) m[v] = (visited[v] >> q) & 1ull;
+}
+
 int blocks_for(uint64_t items) {
   uint64_t b = (items + 255) / 256;
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, 8192));
@@ -130,8 +282,32 @@ int blocks_for(uint64_t items) {
 
 using namespace pg;
 
-extern "C" int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t src, int32_t *dist_out,
-                             int32_t alpha, int32_t beta, const pasgal_opts *opts, pasgal_stats *stats) {
+namespace pg {
+
+namespace {
+// Holds a gate from construction (or open()) to close(); closes at scope exit.
+struct GateHold {
+  LevelGate *g;
+  bool held = false;
+  explicit GateHold(LevelGate *gate) : g(gate) { open(); }
+  void open() {
+    if (g && !held) {
+      g->enter();
+      held = true;
+    }
+  }
+  void close() {
+    if (g && held) {
+      g->leave();
+      held = false;
+    }
+  }
+  ~GateHold() { close(); }
+};
+}  // namespace
+
+int bfs_do_gated(const pasgal_csr *g, const pasgal_csr *gt, int32_t src, int32_t *dist_out, int32_t alpha,
+                 int32_t beta, const pasgal_opts *opts, pasgal_stats *stats, LevelGate *gate) {
   if (!csr_valid(g) || !dist_out || src < 0 || src >= g->n || !opts_valid(opts)) return PASGAL_EINVAL;
   if (gt && (!csr_valid(gt) || gt->n != g->n || gt->m != g->m)) return PASGAL_EINVAL;
   const pasgal_csr *t = gt ? gt : g;
@@ -161,6 +337,7 @@ extern "C" int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t 
   uint32_t *dist = (uint32_t *)dist_out;
   hipError_t e;
   auto fail = [&](hipError_t x) { return hip_fail(x); };
+  GateHold hold(gate);  // the set-up below, then one hold per level
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
   if ((e = hipEventRecord(w->ev0, s)) != hipSuccess) return fail(e);
   if ((e = launch_fill_u32(dist, n, INF32, s)) != hipSuccess) return fail(e);
@@ -183,7 +360,9 @@ extern "C" int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t 
   bool bottom_up = false, have_queue = true;
   int64_t expansions = 0, checked = 0, maxf = 1, visited = 1;
   uint32_t *h_td = (uint32_t *)((uint8_t *)w->h_aux.p + sizeof(DoCtr));  // top-down level: next frontier size
+  hold.close();
   while (nf > 0) {
+    hold.open();
     const uint64_t mu = m - std::min(m, seen_arcs);  // arcs out of unreached vertices
     if (!bottom_up && a > 0.0 && (double)mf > (double)mu / a) {
       bottom_up = true;
@@ -223,6 +402,7 @@ extern "C" int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t 
       if ((e = hipMemcpyAsync(h, ctr, sizeof(DoCtr), hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e);
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+    hold.close();
     if (bottom_up) {
       nf = h->nf;
       checked += (int64_t)h->checked;
@@ -237,10 +417,12 @@ extern "C" int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t 
     level++;
     if (nf > n) return PASGAL_EINTERNAL;
   }
+  hold.open();
   if ((e = hipEventRecord(w->ev1, s)) != hipSuccess) return fail(e);
   if ((e = hipMemcpyAsync(w->h_ctl.p, w->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s)) != hipSuccess)
     return fail(e);
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+  hold.close();
   if (stats) {
     const Ctl &c = *(const Ctl *)w->h_ctl.p;
     memset(stats, 0, sizeof(*stats));
@@ -258,4 +440,179 @@ extern "C" int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t 
     stats->kernel_ms = kms;
   }
   return PASGAL_OK;
+}
+
+}  // namespace pg
+
+extern "C" int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t src, int32_t *dist_out,
+                             int32_t alpha, int32_t beta, const pasgal_opts *opts, pasgal_stats *stats) {
+  return bfs_do_gated(g, gt, src, dist_out, alpha, beta, opts, stats, nullptr);
+}
+
+namespace pg {
+
+int ms_bfs_do_gated(const pasgal_csr *g, const pasgal_csr *gt, int32_t k, const int32_t *src, const MsQuery *qs,
+                    unsigned long long *visited_out, int32_t alpha, int32_t beta, const pasgal_opts *opts,
+                    pasgal_stats *stats, LevelGate *gate) {
+  if (!csr_valid(g) || k < 1 || k > 64 || !src || !qs || !opts_valid(opts)) return PASGAL_EINVAL;
+  if (gt && (!csr_valid(gt) || gt->n != g->n || gt->m != g->m)) return PASGAL_EINVAL;
+  for (int q = 0; q < k; q++)
+    if (src[q] < 0 || src[q] >= g->n) return PASGAL_EINVAL;
+  const pasgal_csr *t = gt ? gt : g;
+  Opts o = resolve_opts(opts);
+  if (o.flags & PASGAL_FLAG_ASYNC) return PASGAL_EINVAL;
+  const double a = alpha > 0 ? (double)alpha : (alpha == 0 ? 100.0 : 0.0);
+  const double bt = beta > 0 ? (double)beta : (beta == 0 ? 24.0 : 0.0);
+  Workspace *w = workspace_for(o.stream);
+  if (!w) return PASGAL_ENOMEM;
+  std::lock_guard<std::mutex> lk(w->mu);
+  if (int arc = collect_async(*w)) return arc;
+  hipStream_t s = o.stream;
+  const uint64_t n = (uint64_t)g->n, m = (uint64_t)g->m;
+  int rc;
+  // visited | cur | nxt words, two queues, counters, the query table and sources
+  const size_t bq = sizeof(MsQuery) * (size_t)k, bs = 4 * (size_t)k;
+  if ((rc = grow(w->tmp_state, 8 * n)) || (rc = grow(w->fval[0], 8 * n)) || (rc = grow(w->fval[1], 8 * n)) ||
+      (rc = grow(w->pf[0], 4 * n)) || (rc = grow(w->pf[1], 4 * n)) || (rc = grow(w->aux, sizeof(DoCtr) + 16)) ||
+      (rc = grow(w->seeds, bq + bs + 16)) || (rc = grow_host(w->h_aux, sizeof(DoCtr) + 16)) ||
+      (rc = grow_host(w->h_stage, bq + bs + 16)))
+    return rc;
+  unsigned long long *visited = visited_out ? visited_out : (unsigned long long *)w->tmp_state.p;
+  unsigned long long *cur = (unsigned long long *)w->fval[0].p, *nxt = (unsigned long long *)w->fval[1].p;
+  uint32_t *qa = (uint32_t *)w->pf[0].p, *qb = (uint32_t *)w->pf[1].p;
+  DoCtr *ctr = (DoCtr *)w->aux.p;
+  uint32_t *qlen = (uint32_t *)((uint8_t *)w->aux.p + sizeof(DoCtr));
+  MsQuery *dqs = (MsQuery *)w->seeds.p;
+  int32_t *dsrc = (int32_t *)((uint8_t *)w->seeds.p + bq);
+  DoCtr *h = (DoCtr *)w->h_aux.p;
+  uint32_t *h_len = (uint32_t *)((uint8_t *)w->h_aux.p + sizeof(DoCtr));
+  memcpy(w->h_stage.p, qs, bq);
+  memcpy((uint8_t *)w->h_stage.p + bq, src, bs);
+  unsigned long long bfs_mask = 0, reach_any = 0;
+  for (int q = 0; q < k; q++) {
+    if (qs[q].dist) bfs_mask |= 1ull << q;
+    if (qs[q].mask1) reach_any = 1;
+  }
+  const unsigned long long active = k == 64 ? ~0ull : ((1ull << k) - 1ull);
+  hipError_t e;
+  auto fail = [&](hipError_t x) { return hip_fail(x); };
+  GateHold hold(gate);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+  if ((e = hipEventRecord(w->ev0, s)) != hipSuccess) return fail(e);
+  if ((e = hipMemcpyAsync(w->seeds.p, w->h_stage.p, bq + bs, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return fail(e);
+  if ((e = launch_fill_u64(visited, n, 0ull, s)) != hipSuccess) return fail(e);
+  if ((e = launch_fill_u64(cur, n, 0ull, s)) != hipSuccess) return fail(e);
+  if ((e = launch_fill_u64(nxt, n, 0ull, s)) != hipSuccess) return fail(e);
+  (void)hipGetLastError();
+  if (bfs_mask) hipLaunchKernelGGL(ms_fill_dist_kernel, dim3(blocks_for(n / 4 + 1), k), dim3(256), 0, s, dqs, (uint32_t)n);
+  hipLaunchKernelGGL(ms_seed_kernel, dim3(1), dim3(64), 0, s, dsrc, k, visited, cur, dqs);
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+  // the seed queue: the distinct sources
+  if ((e = launch_fill_u32(qlen, 1, 0u, s)) != hipSuccess) return fail(e);
+  if ((e = launch_fill_u32((uint32_t *)ctr, sizeof(DoCtr) / 4, 0u, s)) != hipSuccess) return fail(e);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(ms_collect_kernel, dim3(blocks_for(n)), dim3(256), 0, s, (const unsigned long long *)cur,
+                     (uint32_t)n, qa, qlen);
+  hipLaunchKernelGGL(degsum_kernel, dim3(blocks_for(n / 4 + 1)), dim3(256), 0, s, g->offsets, (const uint32_t *)qa,
+                     (const uint32_t *)qlen, ctr);
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+  if ((e = hipMemcpyAsync(h, ctr, sizeof(DoCtr), hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e);
+  if ((e = hipMemcpyAsync(h_len, qlen, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+  if ((e = hipEventRecord(w->evk, s)) != hipSuccess) return fail(e);
+  hold.close();
+
+  uint64_t nf = *h_len, mf = h->mf, seen_arcs = h->mf;
+  uint32_t level = 0;
+  bool bottom_up = false, have_queue = true;
+  int64_t checked = 0, maxf = (int64_t)nf, levels = 0;
+  while (nf > 0) {
+    hold.open();
+    const uint64_t mu = m - std::min(m, seen_arcs);
+    if (!bottom_up && a > 0.0 && (double)mf > (double)mu / a) {
+      bottom_up = true;
+    } else if (bottom_up && bt > 0.0 && (double)nf < (double)n / bt) {
+      bottom_up = false;
+      have_queue = false;
+    }
+    if ((e = launch_fill_u32((uint32_t *)ctr, sizeof(DoCtr) / 4, 0u, s)) != hipSuccess) return fail(e);
+    if (bottom_up) {
+      (void)hipGetLastError();
+      hipLaunchKernelGGL(ms_bottom_up_kernel, dim3(blocks_for(n)), dim3(256), 0, s, g->offsets, t->offsets,
+                         t->targets, (uint32_t)n, visited, (const unsigned long long *)cur, nxt, active, dqs, level,
+                         ctr);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+    } else {
+      if (!have_queue) {
+        if ((e = launch_fill_u32(qlen, 1, 0u, s)) != hipSuccess) return fail(e);
+        (void)hipGetLastError();
+        hipLaunchKernelGGL(ms_collect_kernel, dim3(blocks_for(n)), dim3(256), 0, s, (const unsigned long long *)cur,
+                           (uint32_t)n, qa, qlen);
+        if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+        have_queue = true;
+      }
+      // the next frontier's words start empty; its queue gets the length
+      if ((e = launch_fill_u64(nxt, n, 0ull, s)) != hipSuccess) return fail(e);
+      uint32_t *nlen = qlen + 1;
+      if ((e = launch_fill_u32(nlen, 1, 0u, s)) != hipSuccess) return fail(e);
+      (void)hipGetLastError();
+      const uint64_t waves = std::min<uint64_t>(nf, 8192ull * 4);
+      hipLaunchKernelGGL(ms_top_down_kernel, dim3((int)((waves + 3) / 4)), dim3(256), 0, s, g->offsets, g->targets,
+                         (const uint32_t *)qa, (const uint32_t *)qlen, visited, (const unsigned long long *)cur, nxt,
+                         qb, nlen, dqs, level, ctr);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+      if ((e = hipMemcpyAsync(qlen, nlen, 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) return fail(e);
+      std::swap(qa, qb);
+    }
+    if ((e = hipMemcpyAsync(h, ctr, sizeof(DoCtr), hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+    hold.close();
+    nf = h->nf;
+    mf = h->mf;
+    checked += (int64_t)h->checked;
+    seen_arcs += mf;
+    maxf = std::max<int64_t>(maxf, (int64_t)nf);
+    std::swap(cur, nxt);
+    level++;
+    levels++;
+    if (nf > n || level > n + 1) return PASGAL_EINTERNAL;
+  }
+  hold.open();
+  if (reach_any) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(ms_reach_out_kernel, dim3(blocks_for(n / 4 + 1), k), dim3(256), 0, s, dqs,
+                       (const unsigned long long *)visited, (uint32_t)n);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+  }
+  if ((e = hipEventRecord(w->ev1, s)) != hipSuccess) return fail(e);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+  hold.close();
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->rounds = levels;
+    stats->arcs_scanned = checked;
+    stats->max_frontier = maxf;
+    float ms = 0, kms = 0;
+    hipEventElapsedTime(&ms, w->ev0, w->ev1);
+    hipEventElapsedTime(&kms, w->evk, w->ev1);
+    (void)hipGetLastError();
+    stats->device_ms = ms;
+    stats->kernel_ms = kms;
+  }
+  return PASGAL_OK;
+}
+
+}  // namespace pg
+
+extern "C" int pasgal_bfs_do_multi(const pasgal_csr *g, const pasgal_csr *gt, int32_t k, const int32_t *sources,
+                                   int32_t *dist_out, uint64_t *reach_out, int32_t alpha, int32_t beta,
+                                   const pasgal_opts *opts, pasgal_stats *stats) {
+  if (!csr_valid(g) || k < 1 || k > 64 || !sources) return PASGAL_EINVAL;
+  MsQuery qs[64];
+  for (int q = 0; q < k; q++) {
+    qs[q].dist = dist_out ? dist_out + (size_t)q * (size_t)g->n : nullptr;
+    qs[q].mask1 = nullptr;
+  }
+  return ms_bfs_do_gated(g, gt, k, sources, qs, (unsigned long long *)reach_out, alpha, beta, opts, stats, nullptr);
 }

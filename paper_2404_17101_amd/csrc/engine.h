@@ -101,6 +101,35 @@ int grow_host(HBuf &b, size_t bytes);
 void free_buf(DBuf &b);
 void free_hbuf(HBuf &b);
 Workspace *workspace_for(hipStream_t s);
+
+// A caller's gate around each burst of device work of a host-driven
+// traversal (one level of the direction-optimizing BFS, enqueued and waited
+// for): enter() before its first launch, leave() once the stream is idle. The
+// served form uses it to keep such kernels off the device while a persistent
+// launch, which needs every one of its workgroups resident, is in flight.
+struct LevelGate {
+  virtual void enter() = 0;
+  virtual void leave() = 0;
+  virtual ~LevelGate() = default;
+};
+// One source of a multi-source direction-optimizing BFS and where its result
+// goes (device pointers, either may be null): dist[n] its hop distances (-1
+// where it does not arrive), mask1[n] a reach word with bit 0 set where it
+// arrives.
+struct MsQuery {
+  int32_t *dist;
+  unsigned long long *mask1;
+};
+// Direction-optimizing BFS from k <= 64 sources at once (host array src),
+// with per-source outputs qs (host array of k); visited_out (device, n words,
+// may be null) receives bit q where source q arrives. Synchronous on
+// opts->stream; gate as for bfs_do_gated.
+int ms_bfs_do_gated(const pasgal_csr *g, const pasgal_csr *gt, int32_t k, const int32_t *src, const MsQuery *qs,
+                    unsigned long long *visited_out, int32_t alpha, int32_t beta, const pasgal_opts *opts,
+                    pasgal_stats *stats, LevelGate *gate);
+// pasgal_bfs_do with a gate (nullptr: none).
+int bfs_do_gated(const pasgal_csr *g, const pasgal_csr *gt, int32_t src, int32_t *dist_out, int32_t alpha,
+                 int32_t beta, const pasgal_opts *opts, pasgal_stats *stats, LevelGate *gate);
 Opts resolve_opts(const pasgal_opts *o);
 bool opts_valid(const pasgal_opts *o);
 bool csr_valid(const pasgal_csr *g);

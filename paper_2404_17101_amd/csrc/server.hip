@@ -42,13 +42,12 @@
 #include "pasgal.h"
 
 // BFS requests and single-source reach requests on low-diameter graphs (mean
-// out-degree above 8) do not join the batched launches: a second host thread
-// serves them one at a time with the direction-optimizing BFS on a stream of
-// its own (a reach request takes the reached set of the BFS as its one mask
-// bit), from copies of the graph and of its transpose that
-// pasgal_server_add_graph makes. While such a
-// request is queued or running, the batched launches take half of every
-// compute unit, so that its ordinary kernels run beside them.
+// out-degree above 8) do not join the batched launches: another host thread
+// serves them in batches of up to 64 per graph with the multi-source
+// direction-optimizing BFS (one bit per request; a reach request's mask bit
+// is its source's bit of the reached set), from copies of the graph and of
+// its transpose that pasgal_server_add_graph makes. Its levels and the
+// batched launches take turns on the device (see DevGate).
 
 using namespace pg;
 
@@ -143,13 +142,53 @@ struct Lane {
   }
 };
 
-// Reach mask word (one source, bit 0) from the distances of a BFS from it.
-__global__ void __launch_bounds__(256) mask_from_dist_kernel(const uint32_t *__restrict__ dist,
-                                                             unsigned long long *__restrict__ mask, uint32_t n) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    mask[v] = dist[v] != 0xFFFFFFFFu ? 1ull : 0ull;
-}
+// Device phases: the persistent launches of a slice need every workgroup
+// resident, and ordinary kernels on other streams can hold the compute units
+// they wait for, so the loop's slices (exclusive) and the levels of the
+// direction-optimizing requests (shared among their threads) never overlap on
+// the device. The phases take turns: a waiting slice stops new levels from
+// starting, and the levels that waited through a slice start before the next
+// one.
+struct DevGate {
+  std::mutex m;
+  std::condition_variable cv;
+  int shared = 0, shared_waiting = 0, excl_waiting = 0;
+  bool excl = false;
+  bool turn_shared = false;  // set when a slice ends with levels waiting
+  void enter_shared() {
+    std::unique_lock<std::mutex> lk(m);
+    shared_waiting++;
+    cv.wait(lk, [&] { return !excl && (excl_waiting == 0 || turn_shared); });
+    shared_waiting--;
+    shared++;
+    if (shared_waiting == 0) turn_shared = false;
+  }
+  void leave_shared() {
+    std::lock_guard<std::mutex> lk(m);
+    if (--shared == 0) cv.notify_all();
+  }
+  void enter_excl() {
+    std::unique_lock<std::mutex> lk(m);
+    excl_waiting++;
+    cv.wait(lk, [&] { return !excl && shared == 0 && !turn_shared; });
+    excl_waiting--;
+    excl = true;
+  }
+  void leave_excl() {
+    std::lock_guard<std::mutex> lk(m);
+    excl = false;
+    turn_shared = shared_waiting > 0;
+    cv.notify_all();
+  }
+};
+
+// The direction-optimizing levels' side of the gate.
+struct SharedGate : LevelGate {
+  DevGate *d;
+  explicit SharedGate(DevGate *g) : d(g) {}
+  void enter() override { d->enter_shared(); }
+  void leave() override { d->leave_shared(); }
+};
 
 // A resident graph's own copy (local vertex ids) and its transpose, kept for
 // direction-optimizing BFS requests.
@@ -187,8 +226,12 @@ struct pasgal_server {
   std::vector<std::unique_ptr<DoGraph>> dograph;  // per graph id
   std::deque<Req *> do_q;          // guarded by mu
   std::atomic<int> do_active{0};  // admitted direction-optimizing requests not yet completed
-  hipStream_t do_stream = nullptr;
-  std::thread do_thr;
+  // host threads (and streams) running batches of direction-optimizing
+  // requests
+  static constexpr int DO_THREADS = 1;
+  hipStream_t do_stream[DO_THREADS] = {};
+  std::thread do_thr[DO_THREADS];
+  DevGate gate;
   std::condition_variable cv_do;
   // queues
   std::mutex mu;
@@ -213,7 +256,8 @@ struct pasgal_server {
     cv.notify_all();
     cv_do.notify_all();
     if (thr.joinable()) thr.join();
-    if (do_thr.joinable()) do_thr.join();
+    for (std::thread &t : do_thr)
+      if (t.joinable()) t.join();
     for (Req *r : submitted) delete r;
     for (Lane &l : lanes) {
       if (l.stream) hipStreamSynchronize(l.stream);
@@ -221,10 +265,11 @@ struct pasgal_server {
       for (Req *r : l.copying) delete r;
     }
     for (Req *r : do_q) delete r;
-    if (do_stream) {
-      hipStreamSynchronize(do_stream);
-      hipStreamDestroy(do_stream);
-    }
+    for (hipStream_t &st : do_stream)
+      if (st) {
+        hipStreamSynchronize(st);
+        hipStreamDestroy(st);
+      }
     dograph.clear();
     free_buf(off);
     free_buf(tgt);
@@ -253,14 +298,8 @@ struct pasgal_server {
   }
 
   int64_t state_bytes(const Req *r) const {
-    if (r->dobfs) {
-      // BFS: the distances, unless they go straight to the caller's array;
-      // reach: the distances (256-byte aligned), then the mask words unless
-      // they go to the caller's array
-      const int64_t d = 4 * (int64_t)r->nv;
-      if (r->r.kind == PASGAL_REQ_BFS) return r->r.out ? 0 : d;
-      return ((d + 255) & ~(int64_t)255) + (r->r.out ? 0 : 8 * (int64_t)r->nv);
-    }
+    if (r->dobfs)  // the distances or mask words, unless they go straight to the caller's array
+      return r->r.out ? 0 : (r->r.kind == PASGAL_REQ_BFS ? 4 : 8) * (int64_t)r->nv;
     const int64_t es = r->r.kind == PASGAL_REQ_BFS ? 4 : 8;
     const int64_t words = ((int64_t)r->nv + 31) / 32;
     return ((es * r->nv + 255) & ~(int64_t)255) + 4 * words;
@@ -525,50 +564,60 @@ struct pasgal_server {
   }
 
   // One direction-optimizing BFS request, start to finish (synchronous).
-  void run_do(Req *r) {
-    const DoGraph &G = *dograph[r->r.graph];
+  // A batch of direction-optimizing requests on one graph (at most 64, one
+  // source each), start to finish in one multi-source run (synchronous).
+  void run_do(std::vector<Req *> &batch, hipStream_t ds) {
+    const DoGraph &G = *dograph[batch[0]->r.graph];
     pasgal_csr g{G.n, G.m, (const int32_t *)G.off.p, (const int32_t *)G.tgt.p};
     pasgal_csr gt{G.n, G.m, (const int32_t *)G.toff.p, (const int32_t *)G.ttgt.p};
     pasgal_opts po;
     pasgal_opts_default(&po);
-    po.stream = do_stream;
+    po.stream = ds;
     po.timeout_ms = opts.timeout_ms;
-    const bool bfs = r->r.kind == PASGAL_REQ_BFS;
-    uint8_t *mine = r->bytes > 0 ? (uint8_t *)arena.p + r->off : nullptr;
-    int32_t *dist = (bfs && r->r.out) ? (int32_t *)r->r.out : (int32_t *)mine;
-    pasgal_stats st{};
-    int rc = pasgal_bfs_do(&g, &gt, r->r.sources[0], dist, 0, 0, &po, &st);
-    r->rounds = st.rounds;
-    if (rc == PASGAL_OK && !bfs) {  // reach from one source: bit 0 where the BFS arrived
-      unsigned long long *mask = r->r.out ? (unsigned long long *)r->r.out
-                                          : (unsigned long long *)(mine + ((4 * (int64_t)r->nv + 255) & ~(int64_t)255));
-      (void)hipGetLastError();
-      const int blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, ((int64_t)r->nv + 255) / 256));
-      hipLaunchKernelGGL(mask_from_dist_kernel, dim3(blocks), dim3(256), 0, do_stream, (const uint32_t *)dist, mask,
-                         (uint32_t)r->nv);
-      hipError_t e = hipGetLastError();
-      if (e == hipSuccess) e = hipStreamSynchronize(do_stream);
-      if (e != hipSuccess) rc = hip_fail(e);
+    const int k = (int)batch.size();
+    std::vector<int32_t> src(k);
+    std::vector<MsQuery> qs(k);
+    for (int q = 0; q < k; q++) {
+      Req *r = batch[q];
+      src[q] = r->r.sources[0];
+      void *out = r->r.out ? r->r.out : (void *)((uint8_t *)arena.p + r->off);
+      qs[q].dist = r->r.kind == PASGAL_REQ_BFS ? (int32_t *)out : nullptr;
+      qs[q].mask1 = r->r.kind == PASGAL_REQ_BFS ? nullptr : (unsigned long long *)out;
     }
-    release(r);
-    do_active--;
-    complete(r, rc);
+    pasgal_stats st{};
+    SharedGate sg(&gate);
+    const int rc = ms_bfs_do_gated(&g, &gt, k, src.data(), qs.data(), nullptr, 0, 0, &po, &st, &sg);
+    for (Req *r : batch) {
+      r->rounds = st.rounds;
+      release(r);
+      do_active--;
+      complete(r, rc);
+    }
   }
 
-  // The direction-optimizing thread: one request at a time, in admission order.
-  void do_loop() {
+  // Direction-optimizing thread k: takes the oldest queued request and up to
+  // 63 more queued on the same graph, in admission order, as one batch.
+  void do_loop(int k) {
     hipSetDevice(device);
+    std::vector<Req *> batch;
     while (true) {
-      Req *r = nullptr;
+      batch.clear();
       {
         std::unique_lock<std::mutex> lk(mu);
         cv_do.wait(lk, [&] { return stop || !do_q.empty(); });
         if (stop) return;
-        r = do_q.front();
-        do_q.pop_front();
+        const int32_t gid = do_q.front()->r.graph;
+        for (auto it = do_q.begin(); it != do_q.end() && batch.size() < 64;) {
+          if ((*it)->r.graph == gid) {
+            batch.push_back(*it);
+            it = do_q.erase(it);
+          } else {
+            ++it;
+          }
+        }
       }
-      run_do(r);
-      cv.notify_all();  // the loop may widen its launches again
+      run_do(batch, do_stream[k]);
+      cv.notify_all();
     }
   }
 
@@ -607,15 +656,23 @@ struct pasgal_server {
         std::lock_guard<std::mutex> lk(mu);
         queued = !submitted.empty();
       }
-      // direction-optimizing requests queued or running: leave them half the device
+      // with direction-optimizing requests waiting for the device, a slice
+      // is short (it holds the device exclusively)
       const bool do_busy = do_active > 0;
       const bool lone = !(opts.flags & PASGAL_SERVER_FIXED_SLICES) && !queued && !do_busy &&
                         lanes[0].active + lanes[1].active == 1;
+      const bool work = lanes[0].active > 0 || lanes[1].active > 0 || !lanes[0].copying.empty() ||
+                        !lanes[1].copying.empty();
+      if (!work) {
+        // requests wait for memory that direction-optimizing requests hold
+        if (queued) std::this_thread::sleep_for(std::chrono::microseconds(200));
+        continue;
+      }
+      gate.enter_excl();
       // both kinds with work: their launches run at the same time, each on
       // half of every compute unit; otherwise one after the other, each on
       // the whole device
       const bool both = half_ok && lanes[0].active > 0 && lanes[1].active > 0;
-      const bool beside_do = half_ok && do_busy;
       if (both) {
         for (Lane &L : lanes)
           if (int rc = enqueue_slice(L, true)) fail_lane(L, rc);
@@ -623,11 +680,12 @@ struct pasgal_server {
       } else {
         for (Lane &L : lanes) {
           if (L.active > 0) {
-            if (int rc = enqueue_slice(L, beside_do, lone, ybase)) fail_lane(L, rc);
+            if (int rc = enqueue_slice(L, false, lone, ybase)) fail_lane(L, rc);
           }
           wait_lane(L);
         }
       }
+      gate.leave_excl();
     }
   }
 };
@@ -692,10 +750,11 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
     return hip_fail(e);
   }
   s->d_yield = (const uint32_t *)dy;
-  if ((e = hipStreamCreateWithFlags(&s->do_stream, hipStreamNonBlocking)) != hipSuccess) {
-    delete s;
-    return hip_fail(e);
-  }
+  for (hipStream_t &st : s->do_stream)
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) {
+      delete s;
+      return hip_fail(e);
+    }
   po.stream = s->stream;
   s->vopts = resolve_opts(&po);
   // the half-device slices: half the workgroup size (each CU then holds one
@@ -743,7 +802,7 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
   }
   try {
     s->thr = std::thread([s] { s->loop(); });
-    s->do_thr = std::thread([s] { s->do_loop(); });
+    for (int k = 0; k < pasgal_server::DO_THREADS; k++) s->do_thr[k] = std::thread([s, k] { s->do_loop(k); });
   } catch (...) {
     delete s;
     return PASGAL_ENOMEM;
