@@ -367,11 +367,27 @@ def suite_bfs_do(args, pg, gg, torch):
                                    "gteps_src0_arcs": round(arcs / (float(np.median(ts)) * 1e-3) / 1e9, 3),
                                    "roofline_frac_src0_bytes": _frac(alg, float(np.median(ts)))}
             _log(f"bfs_do {name} {label}: {entry['gpu'][label]}")
+        # 16 sources in one multi-source run: every row against the
+        # single-source direction-optimizing call (distances are unique),
+        # source 0 against the oracle
+        msrc = [int(x) for x in gg.sources(g, 16, 1006, min_degree=1)]
+        msrc[0] = srcs[0]
+        dist16 = torch.empty(16 * g.n, dtype=torch.int32, device="cuda")
+        pg.bfs_do_multi(d, msrc, transpose=t, dist_out=dist16)
+        dv = dist16.view(16, g.n)
+        ok = bool(np.array_equal(dv[0].cpu().numpy(), exp)) and all(
+            bool(torch.equal(dv[q], pg.bfs_do(d, msrc[q], transpose=t))) for q in range(1, 16))
+        ms, _ = _median_ms(lambda: pg.bfs_do_multi(d, msrc, transpose=t, dist_out=dist16), reps=3)
+        entry["gpu"]["direction_optimizing_16_sources"] = {
+            "ms_per_run": round(ms, 2), "ms_per_source": round(ms / 16, 3), "matches": ok,
+            "roofline_frac_16x_src0_bytes": _frac(16 * alg, ms)}
+        _log(f"bfs_do {name} direction_optimizing_16_sources: {entry['gpu']['direction_optimizing_16_sources']}")
+        del dist16, dv
         res.append(entry)
         del d, t
         torch.cuda.empty_cache()
     return {"suite": "bfs_do", "workload": "single-source BFS on RMAT-24 (ef 16, seed 5) and knn 10M/5 (seed 2), "
-                                           "4 sources (seed 1005)", "results": res}
+                                           "4 sources (seed 1005); one 16-source run (seed 1006)", "results": res}
 
 
 def suite_c4(args, pg, gg, torch):
