@@ -84,8 +84,9 @@ typedef struct pasgal_csr {
                                       relaxing atomic is in flight, instead of when the entry is expanded.
                                       On by default for pasgal_bfs_ex, pasgal_sssp, pasgal_reach_ex and
                                       pasgal_scc when their tau is above 1 (1-8% faster there; at tau 1
-                                      no carried range is used); off by default for the batched and
-                                      served forms, where it measured neutral */
+                                      no carried range is used) and for the served form's launches
+                                      (a lone 8192^2 grid BFS request: 31 against 33.5 ms); off by
+                                      default for the batched form, where it measured neutral */
 #define PASGAL_FLAG_TEST_FIRST 8u  /* VGC: read a target's state before the atomic and skip the atomic when
                                       the relaxation cannot change it. On by default for pasgal_reach_ex
                                       with k >= 2 sources on graphs with m >= 4n and for pasgal_scc on

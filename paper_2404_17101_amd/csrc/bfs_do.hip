@@ -33,10 +33,17 @@ namespace pg {
 
 namespace {
 
-// per-level counters (device): new frontier size, arcs out of it, arcs checked
+// per-level counters (device): new frontier size, arcs out of it, arcs checked;
+// with many sources, the union of the new frontier's bits
 struct DoCtr {
-  unsigned long long nf, mf, checked, pad;
+  unsigned long long nf, mf, checked, bits;
 };
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x |= shfl64(x, (int)(lane_id() ^ (uint32_t)d));
+  return x;
+}
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
 #pragma unroll
@@ -160,7 +167,7 @@ __global__ void __launch_bounds__(256) ms_top_down_kernel(const int32_t *__restr
   const uint32_t len = *fq_len;
   const uint32_t ln = lane_id();
   const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  unsigned long long nf = 0, mf = 0, checked = 0;
+  unsigned long long nf = 0, mf = 0, checked = 0, bits = 0;
   for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < len; i += waves) {
     const uint32_t u = fq[i];
     const unsigned long long c = cur[u];
@@ -172,6 +179,7 @@ __global__ void __launch_bounds__(256) ms_top_down_kernel(const int32_t *__restr
       if (!m) continue;
       const unsigned long long nb = m & ~or_ag(&visited[w], m);
       if (!nb) continue;
+      bits |= nb;
       if (or_ag(&nxt[w], nb) == 0ull) {
         nq[add_ag(nq_len, 1u)] = w;
         nf++;
@@ -183,16 +191,19 @@ __global__ void __launch_bounds__(256) ms_top_down_kernel(const int32_t *__restr
   nf = wave_sum64(nf);
   mf = wave_sum64(mf);
   checked = wave_sum64(checked);
+  bits = wave_or64(bits);
   if (ln == 0) {
     if (nf) add_ag(&ctr->nf, nf);
     if (mf) add_ag(&ctr->mf, mf);
     if (checked) add_ag(&ctr->checked, checked);
+    if (bits) or_ag(&ctr->bits, bits);
   }
 }
 
-// Bottom-up level: every vertex still missing some source's bit scans its
-// in-arcs, gathering the frontier bits it misses, and stops once it has them
-// all. Only v's own thread writes visited[v] and nxt[v] here.
+// Bottom-up level: every vertex still missing some bit of `active` (the
+// bits present in the current frontier: no other bit can arrive this level)
+// scans its in-arcs, gathering the frontier bits it misses, and stops once it
+// has them all. Only v's own thread writes visited[v] and nxt[v] here.
 __global__ void __launch_bounds__(256) ms_bottom_up_kernel(const int32_t *__restrict__ off,
                                                            const int32_t *__restrict__ t_off,
                                                            const int32_t *__restrict__ t_tgt, uint32_t n,
@@ -201,7 +212,7 @@ __global__ void __launch_bounds__(256) ms_bottom_up_kernel(const int32_t *__rest
                                                            unsigned long long *nxt, unsigned long long active,
                                                            const MsQuery *__restrict__ qs, uint32_t level,
                                                            DoCtr *ctr) {
-  unsigned long long nf = 0, mf = 0, checked = 0;
+  unsigned long long nf = 0, mf = 0, checked = 0, bits = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
     const uint64_t v = base + lane_id();
@@ -221,6 +232,7 @@ __global__ void __launch_bounds__(256) ms_bottom_up_kernel(const int32_t *__rest
     nxt[v] = acc;
     if (acc) {
       visited[v] = vis | acc;
+      bits |= acc;
       nf++;
       mf += (unsigned long long)(off[v + 1] - off[v]);
       ms_write_dist(qs, acc, (uint32_t)v, level + 1u);
@@ -229,10 +241,12 @@ __global__ void __launch_bounds__(256) ms_bottom_up_kernel(const int32_t *__rest
   nf = wave_sum64(nf);
   mf = wave_sum64(mf);
   checked = wave_sum64(checked);
+  bits = wave_or64(bits);
   if (lane_id() == 0) {
     if (nf) add_ag(&ctr->nf, nf);
     if (mf) add_ag(&ctr->mf, mf);
     if (checked) add_ag(&ctr->checked, checked);
+    if (bits) or_ag(&ctr->bits, bits);
   }
 }
 
@@ -527,6 +541,7 @@ int ms_bfs_do_gated(const pasgal_csr *g, const pasgal_csr *gt, int32_t k, const 
   uint32_t level = 0;
   bool bottom_up = false, have_queue = true;
   int64_t checked = 0, maxf = (int64_t)nf, levels = 0;
+  unsigned long long fbits = active;  // bits present in the current frontier
   while (nf > 0) {
     hold.open();
     const uint64_t mu = m - std::min(m, seen_arcs);
@@ -540,7 +555,7 @@ int ms_bfs_do_gated(const pasgal_csr *g, const pasgal_csr *gt, int32_t k, const 
     if (bottom_up) {
       (void)hipGetLastError();
       hipLaunchKernelGGL(ms_bottom_up_kernel, dim3(blocks_for(n)), dim3(256), 0, s, g->offsets, t->offsets,
-                         t->targets, (uint32_t)n, visited, (const unsigned long long *)cur, nxt, active, dqs, level,
+                         t->targets, (uint32_t)n, visited, (const unsigned long long *)cur, nxt, fbits, dqs, level,
                          ctr);
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     } else {
@@ -570,6 +585,7 @@ int ms_bfs_do_gated(const pasgal_csr *g, const pasgal_csr *gt, int32_t k, const 
     hold.close();
     nf = h->nf;
     mf = h->mf;
+    fbits = h->bits;
     checked += (int64_t)h->checked;
     seen_arcs += mf;
     maxf = std::max<int64_t>(maxf, (int64_t)nf);
