@@ -167,6 +167,9 @@ def summarize_scc_traces(d):
         f.write("\n".join(lines) + "\n")
 
 
+TRACE_STEPS, TRACE_WARMUP = 5, 1  # the kernel-trace run of the headline job
+
+
 def summarize_profiles(d, args):
     """Turn the rocprofv3 CSVs of the trace, counter and copy-calibration runs
     into the committed summaries under profiles/."""
@@ -176,6 +179,14 @@ def summarize_profiles(d, args):
     kr = "void pg::vgc_kernel<1, false, true, true>(pg::VgcArgs)"
     cp = "__amd_rocclr_copyBuffer"
     rows = list(csv.DictReader(open(os.path.join(d, "prof_trace", "run_kernel_stats.csv"))))
+    # the timed steps' dispatches of the two traversal kernels (the trace run
+    # makes TRACE_WARMUP warm-up steps, then TRACE_STEPS timed ones; the
+    # first launch of a kernel also pays its first touch of the buffers)
+    disp = {}
+    for r in csv.DictReader(open(os.path.join(d, "prof_trace", "run_kernel_trace.csv"))):
+        disp.setdefault(r["Kernel_Name"], []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    timed = {k: [(e - b) / 1e6 for b, e in sorted(v)[TRACE_WARMUP:TRACE_WARMUP + TRACE_STEPS]]
+             for k, v in disp.items()}
     F = _counter_means(os.path.join(d, "prof_fetch", "run_counter_collection.csv"))
     W = _counter_means(os.path.join(d, "prof_write", "run_counter_collection.csv"))
     CF = _counter_means(os.path.join(d, "prof_cfetch", "run_counter_collection.csv"))
@@ -184,7 +195,7 @@ def summarize_profiles(d, args):
     w_scale = (1 << 30) / (CW[cp] * 1024)
     traffic_b = F[kb] * 1024 * f_scale + W[kb] * 1024 * w_scale
     traffic_r = F[kr] * 1024 * f_scale + W[kr] * 1024 * w_scale
-    avg = {r["Name"]: float(r["AverageNs"]) / 1e6 for r in rows}
+    avg = {k: sum(v) / len(v) for k, v in timed.items() if v}
     conc = args.schedule == "concurrent"
     wg = args.wg if args.wg > 0 else (max(64, (1024 * args.bfs_share + 3200) // 6400 * 64) if conc else 1024)
     sched = (f"the two launches run concurrently on two streams, the batch on {args.bfs_share}% of every CU "
@@ -204,13 +215,20 @@ def summarize_profiles(d, args):
     lines = ["# Kernel trace: batched 16-source BFS + 16-source reach on the 10M-point 5-NN graph", "",
              "Command (GPU host, `TMPDIR=/tmp`, run from `/tmp`):", "", "```",
              "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_trace -o run -- \\",
-             "    python3 <repo>/bench.py --steps 2 --warmup 1 --no-extras --no-cpu", "```", "",
+             f"    python3 <repo>/bench.py --steps {TRACE_STEPS} --warmup {TRACE_WARMUP} --no-extras --no-cpu", "```", "",
              f"Summarised by `python bench.py --summarize-profiles <out>`. Workload: directed 5-NN graph of 10^7 "
              f"uniform points ({args.layout} layout), 16 sources; each step is one batched VGC BFS launch (16 "
              f"queries, tau {args.tau}, window {args.window}) and one 16-source VGC reach launch; {sched}; "
-             f"1 warm-up + 2 timed steps. rocprofv3 may end with a segmentation fault in its own exit handler after the "
-             f"program's last line; the CSV files were complete.", "",
-             "| kernel | calls | avg (ms) | min (ms) | max (ms) | share |", "|---|---|---|---|---|---|"]
+             f"{TRACE_WARMUP} warm-up + {TRACE_STEPS} timed steps. rocprofv3 may end with a segmentation fault in its own exit "
+             f"handler after the program's last line; the CSV files were complete.", "",
+             "Timed steps only (from `run_kernel_trace.csv`; the warm-up launch also pays the first touch of the "
+             "buffers):", "", "| kernel | timed dispatches | avg (ms) | min (ms) | max (ms) |", "|---|---|---|---|---|"]
+    for k in (kb, kr):
+        v = timed.get(k, [])
+        if v:
+            lines.append(f"| `{k}` | {len(v)} | {sum(v) / len(v):.3f} | {min(v):.3f} | {max(v):.3f} |")
+    lines += ["", "Every dispatch of the run (`run_kernel_stats.csv`, warm-up included):", "",
+              "| kernel | calls | avg (ms) | min (ms) | max (ms) | share |", "|---|---|---|---|---|---|"]
     for r in rows[:8]:
         name = r["Name"].replace("|", "/")
         if len(name) > 70:
@@ -319,6 +337,8 @@ def main():
                          "79.1 GTEPS against 74.4 at 50/50; the shares between (odd wavefront counts) measured worse")
     ap.add_argument("--schedule", choices=["concurrent", "sequential"], default="concurrent")
     ap.add_argument("--bpc", type=int, default=1)
+    ap.add_argument("--filter-slots", type=int, default=0,
+                    help="LDS filter entries per wavefront of the BFS launch (0: the library default)")
     ap.add_argument("--prefetch", choices=["auto", "on", "off"], default="auto",
                     help="arc ranges carried in the local queue (auto: each entry point's default)")
     ap.add_argument("--points", type=int, default=10_000_000)
@@ -415,6 +435,7 @@ def main():
         args.wg = max(64, (1024 * args.bfs_share + 3200) // 6400 * 64) if conc else 1024
     rwg = 1024 - args.wg if conc else args.wg
     vgc = dict(tau=args.tau, window=args.window, wg_size=args.wg, blocks_per_cu=args.bpc, stream=stream,
+               filter_slots=args.filter_slots,
                device_share=args.bfs_share if conc else 0,
                prefetch={"auto": None, "on": True, "off": False}[args.prefetch])
     rstream = torch.cuda.Stream() if conc else stream  # the reach launch's stream
