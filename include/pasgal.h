@@ -273,7 +273,9 @@ int pasgal_bfs_do(const pasgal_csr *g, const pasgal_csr *gt, int32_t src, int32_
  * frontier vertex into its targets (an atomicOr decides which lane owns each
  * new bit), a bottom-up level has every vertex still missing some bit OR the
  * frontier bits of its in-neighbours until it has them all. The switching
- * rule is pasgal_bfs_do's on the union of the frontiers. sources: HOST array
+ * rule is pasgal_bfs_do's on the union of the frontiers, with alpha 0
+ * selecting 14 for k > 1 (such a bottom-up scan stops only once every
+ * missing bit is found; 100 for k = 1). sources: HOST array
  * of k vertex ids (repeats allowed). dist_out: device, k * n int32, row q =
  * hop distances from sources[q] exactly as pasgal_bfs, or NULL. reach_out:
  * device, n uint64, bit q set iff sources[q] reaches v, or NULL. gt, alpha,
