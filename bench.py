@@ -353,7 +353,7 @@ def main():
                     help="run one of the other configurations instead of the headline job (one JSON line)")
     ap.add_argument("--rates", default="5,10,20,40,100,300,1000,3000,10000", help="c5: Poisson arrival rates (q/s)")
     ap.add_argument("--server-tau", type=int, default=0, help="c5: the server's local-search budget (0: its default)")
-    ap.add_argument("--slice-rounds", type=int, default=16, help="c5: rounds per server launch")
+    ap.add_argument("--slice-rounds", type=int, default=0, help="c5: rounds per server launch (0: the server default)")
     ap.add_argument("--server-fixed-slices", action="store_true",
                     help="c5: every server launch runs at most --slice-rounds rounds (no long launch for a lone request)")
     ap.add_argument("--server-no-do", action="store_true",

@@ -633,7 +633,7 @@ def suite_c5(args, pg, gg, torch):
     # RMAT requests served alone, for the mix checks (sources drawn below)
     del outs
     torch.cuda.empty_cache()
-    srv = pg.Server(max_slots=256, slice_rounds=args.slice_rounds if hasattr(args, "slice_rounds") else 16,
+    srv = pg.Server(max_slots=256, slice_rounds=getattr(args, "slice_rounds", 0),
                     tau=getattr(args, "server_tau", 0), fixed_slices=getattr(args, "server_fixed_slices", False),
                     direction_optimizing=not getattr(args, "server_no_do", False))
     gids = [srv.add_graph(dg), srv.add_graph(dr)]

@@ -700,7 +700,7 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
   if (o) s->opts = *o;
   pasgal_server_opts &so = s->opts;
   if (so.max_slots <= 0) so.max_slots = 256;
-  if (so.slice_rounds <= 0) so.slice_rounds = 16;
+  if (so.slice_rounds <= 0) so.slice_rounds = 32;  // c5 saturation: 163 q/s at 32 or 64, 143 at 16
   if (so.timeout_ms <= 0) so.timeout_ms = 20000;
   if (so.memory_budget <= 0) {
     size_t fr = 0, tot = 0;
