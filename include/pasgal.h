@@ -439,7 +439,7 @@ typedef struct pasgal_server_opts {
   int64_t memory_budget;   /* bytes of request state (result slots + bitmaps); <= 0: 1/4 of free HBM */
   int32_t max_slots;       /* concurrent requests; <= 0 selects 256 */
   int32_t slice_rounds;    /* rounds per launch before re-admitting; <= 0 selects 32 */
-  int32_t tau;             /* <= 0 selects 1024 */
+  int32_t tau;             /* <= 0 selects 256 */
   int32_t wg_size;         /* <= 0 selects 1024 */
   int32_t blocks_per_cu;   /* <= 0 selects 1 */
   int64_t frontier_capacity; /* per kind; <= 0 selects 64M entries */

@@ -723,7 +723,8 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
   hipGetDevice(&s->device);
   pasgal_opts po;
   pasgal_opts_default(&po);
-  if (so.tau > 0) po.tau = so.tau;
+  // c5 at 150 q/s offered: p50 0.43 s at tau 256, 0.97 s at 1024, 1.04 s at 4096
+  po.tau = so.tau > 0 ? so.tau : 256;
   if (so.wg_size > 0) po.wg_size = so.wg_size;
   if (so.blocks_per_cu > 0) po.blocks_per_cu = so.blocks_per_cu;
   po.timeout_ms = so.timeout_ms;
