@@ -37,6 +37,7 @@
 #include <thread>
 #include <vector>
 
+#include "devgate.h"
 #include "engine.h"
 #include "kern.h"
 #include "pasgal.h"
@@ -139,46 +140,6 @@ struct Lane {
     for (DBuf *b : {&fv[0], &fv[1], &fq[0], &fq[1], &fval[0], &fval[1], &stat, &qi, &qword, &seeds}) free_buf(*b);
     for (HBuf *b : {&h_stat, &h_stage}) free_hbuf(*b);
     if (stream) hipStreamDestroy(stream);
-  }
-};
-
-// Device phases: the persistent launches of a slice need every workgroup
-// resident, and ordinary kernels on other streams can hold the compute units
-// they wait for, so the loop's slices (exclusive) and the levels of the
-// direction-optimizing requests (shared among their threads) never overlap on
-// the device. The phases take turns: a waiting slice stops new levels from
-// starting, and the levels that waited through a slice start before the next
-// one.
-struct DevGate {
-  std::mutex m;
-  std::condition_variable cv;
-  int shared = 0, shared_waiting = 0, excl_waiting = 0;
-  bool excl = false;
-  bool turn_shared = false;  // set when a slice ends with levels waiting
-  void enter_shared() {
-    std::unique_lock<std::mutex> lk(m);
-    shared_waiting++;
-    cv.wait(lk, [&] { return !excl && (excl_waiting == 0 || turn_shared); });
-    shared_waiting--;
-    shared++;
-    if (shared_waiting == 0) turn_shared = false;
-  }
-  void leave_shared() {
-    std::lock_guard<std::mutex> lk(m);
-    if (--shared == 0) cv.notify_all();
-  }
-  void enter_excl() {
-    std::unique_lock<std::mutex> lk(m);
-    excl_waiting++;
-    cv.wait(lk, [&] { return !excl && shared == 0 && !turn_shared; });
-    excl_waiting--;
-    excl = true;
-  }
-  void leave_excl() {
-    std::lock_guard<std::mutex> lk(m);
-    excl = false;
-    turn_shared = shared_waiting > 0;
-    cv.notify_all();
   }
 };
 
