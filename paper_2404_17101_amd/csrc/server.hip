@@ -131,6 +131,8 @@ struct Lane {
   std::vector<Req *> copying;  // finished; result copies enqueued on the stream
   std::atomic<int> active{0};
   LaunchGeom lg_full[2], lg_half[2];  // [test-first]
+  LaunchGeom lg_one[2];  // single-query kernel, whole device [test-first]: a lone request's launch
+  bool one_ok = false;
   bool enqueued = false;  // a slice is in flight on the stream
   size_t stat_bytes = 0;
   Ctl *ctl() const { return (Ctl *)stat.p; }
@@ -150,6 +152,29 @@ struct SharedGate : LevelGate {
   void enter() override { d->enter_shared(); }
   void leave() override { d->leave_shared(); }
 };
+
+// After a lone request's single-query launch: its frontier entries get the
+// request's slot as query, and the vertices it marked in the global-id
+// bitmap move to the request's own dirty bitmap (local ids), so that the
+// multi-query slices and the census read them as theirs.
+__global__ void __launch_bounds__(256) lone_fix_kernel(const Ctl *ctl, uint32_t *fq0, uint32_t *fq1, uint32_t cap,
+                                                       uint32_t slot, const uint32_t *__restrict__ gdirty,
+                                                       uint32_t *__restrict__ ldirty, uint32_t vbase, uint32_t nv) {
+  const uint32_t cnt = min(ctl->final_cnt, cap);
+  uint32_t *fq = ctl->final_buf ? fq1 : fq0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint64_t i = t0; i < cnt; i += stride) fq[i] = slot;
+  if (!ctl->final_ovf) return;
+  const uint32_t words = (nv + 31) / 32, sh = vbase & 31;
+  for (uint64_t j = t0; j < words; j += stride) {
+    const uint64_t g = ((uint64_t)vbase >> 5) + j;  // global word holding local bit 32j
+    uint32_t w = gdirty[g] >> sh;
+    if (sh) w |= gdirty[g + 1] << (32 - sh);
+    if (j == words - 1 && (nv & 31)) w &= (1u << (nv & 31)) - 1u;
+    if (w) ldirty[j] |= w;
+  }
+}
 
 // A resident graph's own copy (local vertex ids) and its transpose, kept for
 // direction-optimizing BFS requests.
@@ -204,6 +229,9 @@ struct pasgal_server {
   bool stop = false;
   std::thread thr;
   std::mutex gpu_mu;             // serializes device work (graph adds vs loop)
+  // a lone request's launch runs the single-query kernel, which marks
+  // overflowing vertices in a bitmap over global vertex ids
+  DBuf lone_dirty;
   // yield word: bumped by every submission, polled by long launches
   uint32_t *h_yield = nullptr;   // coherent pinned host memory
   const uint32_t *d_yield = nullptr;
@@ -235,6 +263,7 @@ struct pasgal_server {
     free_buf(off);
     free_buf(tgt);
     free_buf(arena);
+    free_buf(lone_dirty);
     if (h_yield) hipHostFree(h_yield);
     if (stream) hipStreamDestroy(stream);
   }
@@ -480,8 +509,44 @@ struct pasgal_server {
     if ((e = launch_seed(kind, a, (const SeedEnt *)L.seeds.p, (uint32_t)nseed, L.cur_cnt, L.cur_ovf, s)) !=
         hipSuccess)
       return hip_fail(e);
-    if ((e = launch_vgc(kind, true, lg.pf, a, lg.grid, lg.block, lg.lds, coop_launch(vo), s)) != hipSuccess)
+    // a lone request with no dirty bits pending runs in the single-query
+    // kernel (faster on one query), on its own state region addressed by
+    // global vertex id, with a global-id dirty bitmap; lone_fix_kernel then
+    // hands its frontier back in the multi-query layout
+    Req *one = nullptr;
+    if (lone && !half && L.one_ok && L.cur_ovf == 0)
+      for (Req *r : L.slots)
+        if (r) one = r;
+    if (one) {
+      const LaunchGeom &l1 = L.lg_one[tf];
+      const uint64_t gwords = ((uint64_t)n_total + 31) / 32 + 1;
+      if (int rc2 = grow(lone_dirty, 4 * gwords)) return rc2;
+      VgcArgs b = a;
+      b.state = (uint8_t *)arena.p + one->off - (int64_t)one->vbase * (int64_t)es;
+      b.dirty = (uint32_t *)lone_dirty.p;
+      b.dirty_words = (int64_t)gwords;
+      b.qi = nullptr;
+      b.qword = nullptr;
+      b.nq = 1;
+      for (int i = 0; i < 2; i++) b.fr.q[i] = nullptr;
+      b.round_base = L.round_abs - one->r0;  // the request's own window origin
+      b.ring_cap = l1.ring;
+      b.stage_cap = l1.stage;
+      b.filt = l1.filt;  // keys are global vertex ids
+      L.slices.apply(b, vo.heavy, hcap, false);
+      if ((e = launch_fill_u32((uint32_t *)lone_dirty.p, gwords, 0u, s)) != hipSuccess) return hip_fail(e);
+      if ((e = launch_vgc(kind, false, l1.pf, b, l1.grid, l1.block, l1.lds, coop_launch(vo), s)) != hipSuccess)
+        return hip_fail(e);
+      (void)hipGetLastError();
+      const uint32_t fix_items = std::max<uint32_t>((uint32_t)std::min<uint64_t>(L.cap, 1u << 30), ((uint32_t)one->nv + 31) / 32);
+      const int fix_blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(8192, ((uint64_t)fix_items + 255) / 256));
+      hipLaunchKernelGGL(lone_fix_kernel, dim3(fix_blocks), dim3(256), 0, s, (const Ctl *)L.ctl(), (uint32_t *)L.fq[0].p,
+                         (uint32_t *)L.fq[1].p, (uint32_t)L.cap, (uint32_t)one->slot, (const uint32_t *)lone_dirty.p,
+                         (uint32_t *)((uint8_t *)arena.p + one->dirty_off), (uint32_t)one->vbase, (uint32_t)one->nv);
+      if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
+    } else if ((e = launch_vgc(kind, true, lg.pf, a, lg.grid, lg.block, lg.lds, coop_launch(vo), s)) != hipSuccess) {
       return hip_fail(e);
+    }
     if ((e = launch_census((const uint32_t *)L.fq[0].p, (const uint32_t *)L.fq[1].p, L.ctl(), (uint32_t)L.cap,
                            L.flags(), (const QInfo *)L.qi.p, (const int64_t *)L.qword.p, (const uint32_t *)arena.p,
                            nslots, s)) != hipSuccess)
@@ -753,6 +818,7 @@ int pasgal_server_create(const pasgal_server_opts *o, pasgal_server **out) {
       Opts full = s->vopts, half = s->vopts_half;
       full.test_first = half.test_first = tf != 0;
       rc = vgc_geometry(L.kind, true, full, L.lg_full[tf]);
+      if (!rc) L.one_ok = vgc_geometry(L.kind, false, full, L.lg_one[tf]) == PASGAL_OK && (tf == 0 || L.one_ok);
       // without room for the half-device geometry the kinds take turns
       if (!rc && vgc_geometry(L.kind, true, half, L.lg_half[tf]) != PASGAL_OK) s->half_ok = false;
     }
