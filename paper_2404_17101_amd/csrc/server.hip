@@ -13,8 +13,9 @@
 //    compute unit; a kind running alone takes the whole device. The frontier
 //    survives between slices, newly admitted requests are seeded into it at
 //    the slice boundary (a launch made while a single request is resident and
-//    none is queued runs until it finishes, or until a submission changes a
-//    word in coherent host memory that the launch polls once per round), and
+//    none is queued runs the single-query kernel until the request finishes,
+//    or until a submission changes a word in coherent host memory that the
+//    launch polls once per round), and
 //    a census kernel that follows each launch on its
 //    stream (reading the launch's exit record on the device) flags the
 //    requests that still have work. One copy back and one wait per slice and

@@ -481,6 +481,36 @@ def test_server_submission_ends_long_launch(pg):
     srv.close()
 
 
+def test_server_lone_launch_hands_back_overflow(pg):
+    """A lone request runs in the single-query kernel; with a frontier of
+    1024 entries its overflow goes to the global-id dirty bitmap. A second
+    submission ends the launch at a round boundary, and the frontier entries
+    and dirty bits move to the request's own (multi-query) layout: both
+    requests still give exact results. The big grid's second graph offset is
+    not a multiple of 32, so the bitmap handover shifts words."""
+    small, big = gg.grid(33, 33), gg.grid(2048, 2048)
+    srv = pg.Server(max_slots=8, slice_rounds=8, frontier_capacity=1024)
+    gs, gb = srv.add_graph(dev(pg, small)), srv.add_graph(dev(pg, big))
+    assert small.n % 32 != 0
+    out_b = torch.empty(big.n, dtype=torch.int32, device="cuda")
+    out_s = torch.empty(small.n, dtype=torch.int32, device="cuda")
+    _say("lone launch with a 1024-entry frontier: big grid from corner 0")
+    assert srv.submit(gb, "bfs", [0], out=out_b, tag=1) is not None
+    import time
+    t0 = time.perf_counter()
+    while srv.load_info()["active"] == 0 and time.perf_counter() - t0 < 10:
+        time.sleep(0.0002)
+    time.sleep(0.003)
+    assert srv.submit(gs, "bfs", [7], out=out_s, tag=2) is not None
+    srv.drain(120000)
+    comps = {c["tag"]: c for c in srv.poll(10)}
+    assert comps[1]["status"] == 0 and comps[2]["status"] == 0
+    r, c = np.divmod(np.arange(big.n), 2048)
+    assert np.array_equal(np_dist(out_b), (r + c).astype(np.int32))
+    assert np.array_equal(np_dist(out_s), oracle.bfs(small, 7))
+    srv.close()
+
+
 @pytest.mark.parametrize("direction_optimizing", [True, False])
 def test_server_dense_graph_bfs(pg, direction_optimizing):
     """BFS and single-source reach requests on a graph with mean out-degree
