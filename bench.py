@@ -101,10 +101,12 @@ SUITE_TRACES = {
              "prefetch, the default at tau above 1, and vgc_kernel<2, false, false, false> the same without it "
              "(tau 1: RMAT-22 and the tau1 rows); sum_u32_kernel is the "
              "mean-weight reduction behind the default bucket width."),
-    "bfs_do": ("Kernel trace: direction-optimizing BFS suite (RMAT-24 and knn 10M/5, 4 sources each)",
+    "bfs_do": ("Kernel trace: direction-optimizing BFS suite (RMAT-24 and knn 10M/5, 4 sources each, and one "
+               "16-source run per graph)",
                "bottom_up_kernel, collect_kernel and degsum_kernel belong to the direction-optimizing BFS; "
-               "plain_level_kernel<0> runs its top-down levels and the plain BFS; vgc_kernel<0, false, true, false> is the "
-               "VGC BFS (arc-range prefetch on, the single-source default)."),
+               "plain_level_kernel<0> runs its top-down levels and the plain BFS; ms_* kernels are the multi-source "
+               "run (one bit per source; on the k-NN graph its many bottom-up levels dominate the suite's time); "
+               "vgc_kernel<0, false, true, false> is the VGC BFS (arc-range prefetch on, the single-source default)."),
 }
 
 
