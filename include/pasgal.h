@@ -456,9 +456,10 @@ typedef struct pasgal_server_opts {
 } pasgal_server_opts;
 
 /* Server flag: every launch runs at most slice_rounds rounds. By default a launch made while exactly one
-   request is resident and none is queued runs until that request finishes or another request is
-   submitted (the launch polls a word in coherent host memory once per round and ends at the next round
-   boundary), so that a request served alone pays no per-slice host round trips. */
+   request is resident and none is queued runs the single-query kernel until that request finishes or
+   another request is submitted (the launch polls a word in coherent host memory once per round and ends
+   at the next round boundary, handing its frontier back to the multi-query layout), so that a request
+   served alone pays no per-slice host round trips and no multi-query overhead. */
 #define PASGAL_SERVER_FIXED_SLICES 65536u
 /* Server flag: every request goes through the batched VGC launches. By default a graph added with mean
    out-degree above 8 (m > 8n: low diameter, where top-down levels scan most arcs) gets a copy of itself
@@ -493,6 +494,8 @@ typedef struct pasgal_completion {
   int64_t rounds;         /* rounds the request was resident for */
 } pasgal_completion;
 
+/* Starts the server's host threads (the request loop and the direction-optimizing thread) and streams;
+ * opts may be NULL (all defaults). PASGAL_EINVAL: unknown flag bits, reserved != 0, max_slots > 4096. */
 int pasgal_server_create(const pasgal_server_opts *opts, pasgal_server **out);
 /* Copies the graph into server-owned device memory; returns its id. */
 int pasgal_server_add_graph(pasgal_server *s, const pasgal_csr *g, int32_t *graph_id);
