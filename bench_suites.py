@@ -687,10 +687,14 @@ def suite_c5(args, pg, gg, torch):
         th.start()
         deadline = time.perf_counter() + 240.0 + count / rate
         t_note = time.perf_counter()
+        depth_max, active_max = 0, 0  # admission queue depth and admitted requests, sampled
         while len(done) < count and time.perf_counter() < deadline:
             if time.perf_counter() - t_note > 30.0:  # progress, for long low-rate runs
                 t_note = time.perf_counter()
                 _log(f"c5 rate {rate}: {len(done)} of {count} requests completed")
+            li = srv.load_info()
+            depth_max = max(depth_max, li["queued"])
+            active_max = max(active_max, li["active"])
             for c in srv.poll(4096):
                 i = int(c["tag"])
                 with lock:
@@ -733,6 +737,7 @@ def suite_c5(args, pg, gg, torch):
                  "p50_ms": round(float(np.percentile(lats, 50)), 2) if lats.size else None,
                  "p99_ms": round(float(np.percentile(lats, 99)), 2) if lats.size else None,
                  "admission_wait_p50_ms": round(float(np.percentile([x[2] for x in ok], 50)), 2) if ok else None,
+                 "admission_queue_max": depth_max, "admitted_max": active_max,
                  "p50_ms_by_kind": {k: round(float(np.percentile([x[1] for x in ok if x[3] == k], 50)), 2)
                                     for k in sorted({x[3] for x in ok})},
                  "roofline_frac": round(qps * mix_bytes / 1e9 / HBM_PEAK_GBS, 5),
