@@ -552,6 +552,38 @@ def test_server_dense_graph_bfs(pg, direction_optimizing):
     srv.close()
 
 
+def test_server_dense_batches_split_at_64(pg):
+    """More than 64 direction-optimizing requests queued on one dense graph
+    (and a few on another) are served in several multi-source batches; every
+    result equals the oracle's."""
+    ga, gb = gg.rmat(10, 12, 4), gg.random_graph(1500, 18000, 13, symmetric=False)
+    assert ga.m > 8 * ga.n and gb.m > 8 * gb.n
+    srv = pg.Server(max_slots=8)
+    ia, ib = srv.add_graph(dev(pg, ga)), srv.add_graph(dev(pg, gb))
+    reqs = []
+    srcs_a = [int(x) for x in gg.sources(ga, 80, 900, min_degree=1)]
+    _say("dense batches: 80 + 6 direction-optimizing requests")
+    for i, s in enumerate(srcs_a):
+        kind = "bfs" if i % 3 else "reach"
+        out = torch.empty(ga.n, dtype=torch.int32 if kind == "bfs" else torch.int64, device="cuda")
+        assert srv.submit(ia, kind, [s], out=out, tag=i) is not None
+        reqs.append((i, ga, kind, s, out))
+    for j, s in enumerate(int(x) for x in gg.sources(gb, 6, 901, min_degree=1)):
+        out = torch.empty(gb.n, dtype=torch.int32, device="cuda")
+        assert srv.submit(ib, "bfs", [s], out=out, tag=1000 + j) is not None
+        reqs.append((1000 + j, gb, "bfs", s, out))
+    srv.drain(60000)
+    comps = {c["tag"]: c for c in srv.poll(1000)}
+    assert len(comps) == len(reqs)
+    for tag, g, kind, s, out in reqs:
+        assert comps[tag]["status"] == 0, tag
+        if kind == "bfs":
+            assert np.array_equal(np_dist(out), oracle.bfs(g, s)), tag
+        else:
+            assert np.array_equal(np_mask(out)[:, None], oracle.reach(g, [s])), tag
+    srv.close()
+
+
 # ------------------------------------------------------ heavy-row slices ---
 
 def _hub_graph(n_leaves, extra_seed):
