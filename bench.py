@@ -435,7 +435,8 @@ def main():
     conc = args.schedule == "concurrent"
     if args.wg <= 0:
         args.wg = max(64, (1024 * args.bfs_share + 3200) // 6400 * 64) if conc else 1024
-    rwg = 1024 - args.wg if conc else args.wg
+    # the reach launch takes the rest of every CU, in as many workgroups per CU
+    rwg = max(64, (1024 - args.wg * args.bpc) // args.bpc // 64 * 64) if conc else args.wg
     vgc = dict(tau=args.tau, window=args.window, wg_size=args.wg, blocks_per_cu=args.bpc, stream=stream,
                filter_slots=args.filter_slots,
                device_share=args.bfs_share if conc else 0,

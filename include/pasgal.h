@@ -150,8 +150,10 @@ typedef struct pasgal_opts {
                                 so that another launch sized to the rest runs beside it on another stream:
                                 its workgroups get that share of a CU's LDS and its waves at most that
                                 share of the wave slots its registers allow (PASGAL_EINVAL if they do
-                                not fit), and it is launched as an ordinary kernel. 0 = the whole device
-                                (a cooperative launch), or 50 with PASGAL_FLAG_HALF_DEVICE. */
+                                not fit, or if wg_size is not a multiple of 256, i.e. its waves do not
+                                spread evenly over a CU's four SIMDs), and it is launched as an ordinary
+                                kernel. 0 = the whole device (a cooperative launch), or 50 with
+                                PASGAL_FLAG_HALF_DEVICE. */
 } pasgal_opts;
 
 /* Counters of one call (schedule dependent, never part of the result). */

@@ -300,6 +300,10 @@ int vgc_geometry(int kind, bool multi, const Opts &o, LaunchGeom &lg) {
   if (e != hipSuccess) return hip_fail(e);
   if (nb < 1) return PASGAL_EINVAL;
   if (o.share) {
+    // a workgroup whose waves do not spread evenly over the CU's four SIMDs
+    // can leave a SIMD without room for the other launch's waves: two 6-wave
+    // workgroups per CU beside two 2-wave ones never all became resident
+    if (waves % 4 != 0) return PASGAL_EINVAL;
     // its waves may take at most its share of the wave slots the kernel's
     // registers allow, so that the rest is left for the launch beside it
     int nw = 0;

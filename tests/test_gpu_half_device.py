@@ -67,6 +67,13 @@ def test_half_device_rejects_a_grid_that_cannot_share_the_cus(pg):
     with pytest.raises(pg.PasgalError) as ei:
         pg.bfs(d, 0, half_device=True, wg_size=1024)
     assert ei.value.code == -1
+    # workgroups whose waves do not spread evenly over the four SIMDs of a CU
+    # are refused before anything is launched
+    for kw in [dict(half_device=True, wg_size=384), dict(device_share=75, wg_size=704),
+               dict(device_share=25, wg_size=128, blocks_per_cu=2)]:
+        with pytest.raises(pg.PasgalError) as ei:
+            pg.bfs(d, 0, **kw)
+        assert ei.value.code == -1, kw
 
 
 def test_concurrent_batch_and_reach_on_two_streams(pg):
