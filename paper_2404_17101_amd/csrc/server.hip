@@ -38,6 +38,7 @@
 #include <thread>
 #include <vector>
 
+#include "arena.h"
 #include "devgate.h"
 #include "engine.h"
 #include "kern.h"
@@ -59,49 +60,6 @@ double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
-
-// First-fit allocator over [0, size) with coalescing, 256-byte granules.
-struct Arena {
-  std::map<int64_t, int64_t> free_;  // offset -> length
-  int64_t size = 0;
-  std::atomic<int64_t> used{0};
-  void reset(int64_t sz) {
-    free_.clear();
-    size = sz;
-    used = 0;
-    if (sz > 0) free_[0] = sz;
-  }
-  int64_t alloc(int64_t len) {
-    len = (len + 255) & ~(int64_t)255;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= len) {
-        const int64_t off = it->first, rest = it->second - len;
-        free_.erase(it);
-        if (rest > 0) free_[off + len] = rest;
-        used += len;
-        return off;
-      }
-    }
-    return -1;
-  }
-  void release(int64_t off, int64_t len) {
-    len = (len + 255) & ~(int64_t)255;
-    used -= len;
-    auto it = free_.emplace(off, len).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-};
 
 struct Req {
   int64_t id = 0;
