@@ -116,13 +116,13 @@ struct Wave {
   // relaxations that cannot change it (test-first).
   // Most passes of up to this many 64-arc batches are issued together
   // (target loads, then atomics, then pushes), so that a lane has several
-  // relaxations in flight: single-query BFS steps are thin (one pass); reach
-  // steps (deep LIFO searches), SSSP steps and multi-query steps are wider.
-  // The plain multi-query BFS variant takes five: a full step of 64 entries
-  // of out-degree 5 is then one block instead of two (batched 16-query BFS
-  // on the 5-NN graph: 19.5 against 19.95 ms); its other variants keep four,
-  // which stay free of scratch.
-  static constexpr int RB = (MULTI && KIND == KIND_BFS && !PF && !TF) ? 5 : ((MULTI || KIND != KIND_BFS) ? 4 : 1);
+  // relaxations in flight. The plain multi-query BFS variant takes five: a
+  // full step of 64 entries of out-degree 5 is then one block instead of two
+  // (batched 16-query BFS on the 5-NN graph: 19.5 against 19.95 ms). Every
+  // other variant takes four; single-query BFS gained from the wider blocks
+  // too (one query on the 10M-point 5-NN graph, tau 1024 with a 32-level
+  // window: 8.6 against 9.6 ms), at 3% on the 8192x8192 grid.
+  static constexpr int RB = (MULTI && KIND == KIND_BFS && !PF && !TF) ? 5 : 4;
   // Source implications (reach with one query): when new bits reach the
   // vertex of source j, the sources behind them reach everything source j
   // reaches, so bit j implies them. An expansion then propagates the closure
@@ -682,6 +682,9 @@ struct Wave {
       } else if (RB >= 4 && left >= 4) {
         nsucc += passes<(RB >= 4 ? 4 : 1)>(j0, total, excl, deg, lim1, ring_ok);
         j0 += 256;
+      } else if (RB >= 3 && left == 3) {
+        nsucc += passes<(RB >= 3 ? 3 : 1)>(j0, total, excl, deg, lim1, ring_ok);
+        j0 += 192;
       } else if (RB >= 2 && left >= 2) {
         nsucc += passes<(RB >= 2 ? 2 : 1)>(j0, total, excl, deg, lim1, ring_ok);
         j0 += 128;
