@@ -331,8 +331,10 @@ def main():
                     help="tau of the reach launch (default 256 under the concurrent schedule, where it measured "
                          "best on half the device, else --tau)")
     ap.add_argument("--window", type=int, default=0,
-                    help="BFS distance window (default 24 concurrent, 32 sequential: measured best for each)")
-    ap.add_argument("--wg", type=int, default=0, help="workgroup size (default 512 concurrent, 1024 sequential)")
+                    help="BFS distance window (default 32, measured best under both schedules)")
+    ap.add_argument("--wg", type=int, default=0,
+                    help="BFS workgroup size (default: the BFS share of 1024 threads in whole wavefronts when "
+                         "concurrent, 1024 sequential)")
     ap.add_argument("--bfs-share", type=int, default=75,
                     help="concurrent schedule: percent of every compute unit the batched BFS launch takes (the "
                          "reach launch takes the rest; workgroup sizes follow the shares). 75/25 measured best: "
@@ -375,7 +377,7 @@ def main():
                          "prof_write, prof_cfetch, prof_cwrite)")
     args = ap.parse_args()
     if args.window <= 0:
-        args.window = 24 if args.schedule == "concurrent" else 32
+        args.window = 32
 
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args)
