@@ -172,9 +172,9 @@ def summarize_scc_traces(d):
 TRACE_STEPS, TRACE_WARMUP = 5, 1  # the kernel-trace run of the headline job
 
 
-def summarize_profiles(d, args):
+def summarize_profiles(d, args, out_dir=None):
     """Turn the rocprofv3 CSVs of the trace, counter and copy-calibration runs
-    into the committed summaries under profiles/."""
+    into the committed summaries under profiles/ (or out_dir)."""
     import csv
 
     kb = "void pg::vgc_kernel<0, true, false, false>(pg::VgcArgs)"
@@ -211,7 +211,7 @@ def summarize_profiles(d, args):
            "hbm_bytes_per_launch": int(traffic_b), "kernel_avg_ms": round(avg.get(kb, 0.0), 4),
            "reach16_kernel": kr, "reach16_fetch_kib": round(F[kr], 1), "reach16_write_kib": round(W[kr], 1),
            "reach16_hbm_bytes_per_launch": int(traffic_r), "reach16_avg_ms": round(avg.get(kr, 0.0), 4)}
-    prof = os.path.join(ROOT, "profiles")
+    prof = out_dir or os.path.join(ROOT, "profiles")
     with open(os.path.join(prof, "vgc_bfs_batched16_knn10m_counters.txt"), "w") as f:
         f.write(json.dumps(out, indent=1) + "\n")
     lines = ["# Kernel trace: batched 16-source BFS + 16-source reach on the 10M-point 5-NN graph", "",
@@ -273,7 +273,7 @@ SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_
 TCC_COUNTERS = "TCC_HIT_sum TCC_MISS_sum TCC_EA0_RDREQ_sum TCC_EA0_ATOMIC_sum"
 
 
-def summarize_pmc(d):
+def summarize_pmc(d, out_dir=None):
     """profiles/vgc_bfs_batched16_knn10m_sq.md from the two instruction and L2
     counter passes (DIR/pmc_sq, DIR/pmc_tcc), per dispatch of each of the two
     headline kernels."""
@@ -305,7 +305,7 @@ def summarize_pmc(d):
         b, r = mean.get((kb, c)), mean.get((kr, c))
         fmt = lambda x: "n/a" if x is None else f"{x:,.0f}"
         lines.append(f"| {c} | {fmt(b)} | {fmt(r)} |")
-    with open(os.path.join(ROOT, "profiles", "vgc_bfs_batched16_knn10m_sq.md"), "w") as f:
+    with open(os.path.join(out_dir or os.path.join(ROOT, "profiles"), "vgc_bfs_batched16_knn10m_sq.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
